@@ -1,0 +1,165 @@
+/*
+ * vca.h -- C ABI of the MI355X (gfx950) Video Complexity Analyzer library.
+ *
+ * The library computes, per video frame, the seven block-DCT features of
+ * Menon et al., "Green Video Complexity Analysis for Efficient Encoding in
+ * Adaptive Video Streaming" (GMSys 2023), Section 2:
+ *   E_Y  luma texture energy          h    gradient (frame-to-frame change) of E_Y
+ *   L_Y  luma brightness              E_U, E_V  chroma texture energies
+ *   L_U, L_V  chroma brightness
+ * including the low-pass DCT option of Section 2 (optimisation (3)), read as
+ * computing only the top-left K x K coefficients of each w x w block.
+ *
+ * Definitions (the cited VCA paper, which Section 2 defers to for formulas,
+ * is not reproduced here; these are the readings this library implements):
+ *   - Each plane (Y: W x H, U and V: W/2 x H/2, 4:2:0) is tiled with complete
+ *     w x w blocks anchored at (0,0); rows/columns past the last complete
+ *     block are ignored.  C_P = number of blocks of plane P.
+ *   - Per block X (raw samples, bit depth B), the H.265 integer core transform
+ *     C_w (entries in [-90, 90]) in two rounded passes, horizontal first:
+ *       T = floor((X C_w^T + 2^(s1-1)) / 2^s1),  s1 = log2 w + B - 9
+ *       Y = floor((C_w T   + 2^(s2-1)) / 2^s2),  s2 = log2 w + 6
+ *     Y[i][k]: i = vertical, k = horizontal frequency; DC = Y[0][0].
+ *   - Block energy H = sum_{(i,k) != (0,0), i,k < K} W_ik |Y[i][k]| with
+ *     W_ik = exp(|((i+1)(k+1)/w^2)^2 - 1|).
+ *   - E_P = sum H / (C_P w^2); L_P = sum sqrt(DC) / (C_P w^2);
+ *     h = sum over luma blocks |H_p - H_{p-1}| / (C_Y w^2), h = 0 for the
+ *     first frame after vca_open or vca_reset.
+ * DCT coefficients and DC are exact integers (bit-exact); E, h and L are
+ * accumulated in FP64 on the device and returned as FP32.
+ *
+ * Conventions: every function returns vca_status (except where noted); no
+ * exception crosses the ABI.  A context is not thread-safe: use one per host
+ * thread.  All device work of a context runs on the HIP stream given to
+ * vca_open, in submission order.
+ */
+#ifndef VCA_H
+#define VCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vca_ctx vca_ctx; /* opaque; owned by the library */
+
+typedef enum {
+  VCA_OK = 0,
+  VCA_ERR_INVALID_ARG = 1, /* null pointer, out-of-range field, misaligned buffer      */
+  VCA_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. host-resident frames)     */
+  VCA_ERR_OOM = 3,         /* device or host allocation failed                          */
+  VCA_ERR_DEVICE = 4,      /* a HIP call failed; vca_last_error() holds its message     */
+  VCA_ERR_STATE = 5        /* request inconsistent with the context's history           */
+} vca_status;
+
+/* vca_config.flags */
+#define VCA_F_KEEP_COEFFS 0x1u /* keep the K x K int16 coefficients of the last call (tests) */
+#define VCA_F_VALIDATE 0x2u    /* 10-bit: count samples above 1023; vca_features then fails  */
+#define VCA_F_TIMING 0x4u      /* record HIP events around every kernel launch (vca_timing)  */
+
+typedef struct {
+  uint32_t struct_size;  /* = sizeof(vca_config); guards ABI evolution                    */
+  int32_t width;         /* luma width in samples; even; width/2  >= block_size            */
+  int32_t height;        /* luma height in samples; even; height/2 >= block_size           */
+  int32_t bit_depth;     /* 8 (uint8 samples) or 10 (uint16 little-endian, 0..1023)       */
+  int32_t chroma_format; /* 420 (the only supported layout)                              */
+  int32_t block_size;    /* w: 8, 16 or 32                                                 */
+  int32_t lowpass_k;     /* 0 or w: full transform; else K in {w/2, w/4}                   */
+  int32_t device;        /* HIP device ordinal                                             */
+  uint32_t flags;        /* VCA_F_*                                                        */
+  int32_t max_batch;     /* frames per internal launch (scratch sizing); 0 = 256           */
+  int32_t feature_capacity; /* frames of features kept on the device (ring); 0 = 65536     */
+} vca_config;
+
+/* A run of consecutive frames of one video, as device pointers.
+ * Alignment: y/u/v, pitches and frame strides must be multiples of 16 bytes. */
+typedef struct {
+  const void* y;       /* first sample of frame 0 of each plane                        */
+  const void* u;
+  const void* v;
+  int64_t pitch_y;     /* bytes between rows of Y (>= width * bytes per sample)        */
+  int64_t pitch_uv;    /* bytes between rows of U and of V (>= width/2 * bytes/sample) */
+  int64_t fstride_y;   /* bytes between consecutive frames of Y                        */
+  int64_t fstride_uv;  /* bytes between consecutive frames of U and of V               */
+  int32_t on_device;   /* 1: device pointers (the only supported form); 0: host        */
+} vca_frames;
+
+/* Per-frame feature record, in the order Section 2 lists the features. */
+typedef struct {
+  float E_Y, h, L_Y, E_U, E_V, L_U, L_V;
+} vca_frame_features;
+
+/* Device time spent in the library's kernels (needs VCA_F_TIMING), summed
+ * over launches since vca_open or the last reset of the counters. */
+typedef struct {
+  double forward_ms;        /* block transform + energy kernels                   */
+  double reduce_ms;         /* per-frame feature reduction kernels                */
+  int64_t forward_launches;
+  int64_t reduce_launches;
+  int64_t frames;           /* frames covered by the timed launches                */
+} vca_timing;
+
+/* Number of complete blocks of the Y, U and V planes for a configuration.
+ * Host only; touches no device. */
+vca_status vca_block_counts(const vca_config* cfg, int32_t counts[3]);
+
+/* Creates a context: validates cfg, builds the transform and weight tables,
+ * allocates device state on cfg->device.  hip_stream is a hipStream_t (NULL:
+ * the context creates and owns a stream of default priority).  On success
+ * *out receives the context; on failure *out is NULL. */
+vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out);
+
+/* Enqueues the analysis of n_frames frames (n_frames >= 0) on the context's
+ * stream and returns without waiting.  Frames are numbered after those of
+ * earlier calls, and h chains across calls.  The caller keeps the frame
+ * buffers valid until the stream has finished the work (vca_features waits).
+ * With VCA_F_KEEP_COEFFS, n_frames must not exceed max_batch. */
+vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* frames, int32_t n_frames);
+
+/* Waits for the context's stream, then copies the features of frames
+ * [first_frame, first_frame + count) into out_host (count records).
+ * VCA_ERR_STATE if a frame was not yet submitted or has left the ring, or if
+ * VCA_F_VALIDATE found an out-of-range sample. */
+vca_status vca_features(vca_ctx* ctx, int64_t first_frame, int32_t count,
+                        vca_frame_features* out_host);
+
+/* Test/debug export (needs VCA_F_KEEP_COEFFS): waits for the stream, then
+ * copies the coefficients of frame `frame` of the most recent
+ * vca_analyze_frames call: blocks of Y, then U, then V, each in raster order;
+ * per block K x K int16, row-major (row = vertical frequency), DC included.
+ * capacity is the number of int16 elements out_host can hold. */
+vca_status vca_block_coeffs(vca_ctx* ctx, int64_t frame, int16_t* out_host, size_t capacity);
+
+/* Per-block export of frame `frame` of the most recent call: block energies
+ * H (FP64) and DC (int32), blocks ordered as in vca_block_coeffs.  Waits for
+ * the stream.  capacity is the number of blocks each array can hold. */
+vca_status vca_block_stats(vca_ctx* ctx, int64_t frame, double* h_host, int32_t* dc_host,
+                           size_t capacity);
+
+/* Waits for the context's stream and returns the kernel times measured with
+ * HIP events on that stream (VCA_F_TIMING); reset != 0 clears the counters
+ * afterwards.  VCA_ERR_STATE if the context was opened without the flag. */
+vca_status vca_get_timing(vca_ctx* ctx, vca_timing* out, int32_t reset);
+
+/* Forgets the previous frame: the next analysed frame gets h = 0.  Frame
+ * numbering continues. */
+vca_status vca_reset(vca_ctx* ctx);
+
+/* Number of frames submitted so far (returns -1 for a NULL context). */
+int64_t vca_frames_submitted(const vca_ctx* ctx);
+
+/* Waits for outstanding work and frees the context.  NULL-safe. */
+void vca_close(vca_ctx* ctx);
+
+/* Static string naming a status code. */
+const char* vca_status_str(vca_status s);
+
+/* Message of the last failure of ctx (owned by ctx; "" if none). */
+const char* vca_last_error(const vca_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCA_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) Video Complexity Analyzer.
+
+Per-frame block-DCT complexity features (E_Y, h, L_Y, E_U, E_V, L_U, L_V) of
+Menon et al., "Green Video Complexity Analysis for Efficient Encoding in
+Adaptive Video Streaming", Section 2, computed by hand-written HIP kernels
+behind the C ABI in include/vca.h.
+"""
+from ._lib import VcaError, EXPORTS, LIB_PATH
+from .analyzer import Analyzer, FEATURE_NAMES, block_counts
+
+__all__ = ["Analyzer", "FEATURE_NAMES", "block_counts", "VcaError", "EXPORTS", "LIB_PATH"]

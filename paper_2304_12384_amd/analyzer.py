@@ -1,0 +1,158 @@
+"""Python face of the VCA library: one ``Analyzer`` per video stream.
+
+Frames are torch tensors already on the GPU (uint8 for 8-bit, uint16 stored
+as int16/uint16 for 10-bit); every step of the analysis runs in the HIP
+library through the C ABI, on the caller's current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import VcaConfig, VcaFrames, check
+
+FEATURE_NAMES = ("E_Y", "h", "L_Y", "E_U", "E_V", "L_U", "L_V")
+
+
+def block_counts(width: int, height: int, block_size: int = 32, bit_depth: int = 8,
+                 lowpass_k: int = 0) -> tuple[int, int, int]:
+    cfg = _config(width, height, bit_depth, block_size, lowpass_k, 0, 0, 0, 0)
+    out = (ctypes.c_int32 * 3)()
+    check(_lib.lib().vca_block_counts(ctypes.byref(cfg), out), "vca_block_counts")
+    return out[0], out[1], out[2]
+
+
+def _config(width, height, bit_depth, block_size, lowpass_k, device, flags, max_batch,
+            feature_capacity) -> VcaConfig:
+    return VcaConfig(ctypes.sizeof(VcaConfig), width, height, bit_depth, 420, block_size,
+                     lowpass_k, device, flags, max_batch, feature_capacity)
+
+
+def _plane_geometry(t: torch.Tensor, bps: int):
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError("planes must be [n, rows, cols] with unit column stride")
+    if not t.is_cuda:
+        raise ValueError("frames must be device tensors")
+    if t.element_size() != bps:
+        raise ValueError(f"expected {bps}-byte samples, got {t.dtype}")
+    return t, t.stride(1) * bps, t.stride(0) * bps
+
+
+class Analyzer:
+    """Wraps one ``vca_ctx``.
+
+    >>> an = Analyzer(3840, 2160, block_size=32)
+    >>> an.submit(y, u, v)          # y: [n, H, W] uint8 cuda tensor, u/v: [n, H/2, W/2]
+    >>> feats = an.features(0, n)   # numpy [n, 7] float32
+    """
+
+    def __init__(self, width: int, height: int, *, bit_depth: int = 8, block_size: int = 32,
+                 lowpass_k: int = 0, device: int | None = None, keep_coeffs: bool = False,
+                 validate: bool = False, timing: bool = False, max_batch: int = 0,
+                 feature_capacity: int = 0,
+                 stream: torch.cuda.Stream | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        flags = ((_lib.VCA_F_KEEP_COEFFS if keep_coeffs else 0) |
+                 (_lib.VCA_F_VALIDATE if validate else 0) | (_lib.VCA_F_TIMING if timing else 0))
+        self.cfg = _config(width, height, bit_depth, block_size, lowpass_k, device, flags,
+                           max_batch, feature_capacity)
+        self.width, self.height, self.bit_depth = width, height, bit_depth
+        self.block_size = block_size
+        self.k = block_size if lowpass_k == 0 else lowpass_k
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._ctx = ctypes.c_void_p()
+        check(_lib.lib().vca_open(ctypes.byref(self.cfg), ctypes.c_void_p(self.stream.cuda_stream),
+                                  ctypes.byref(self._ctx)), "vca_open")
+        self.counts = block_counts(width, height, block_size, bit_depth, lowpass_k)
+        self._keep = []   # frame tensors referenced until their work is known to be done
+
+    # ------------------------------------------------------------------ calls
+    def close(self) -> None:
+        if self._ctx:
+            _lib.lib().vca_close(self._ctx)
+            self._ctx = ctypes.c_void_p()
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def submitted(self) -> int:
+        return int(_lib.lib().vca_frames_submitted(self._ctx))
+
+    def submit(self, y: torch.Tensor, u: torch.Tensor, v: torch.Tensor) -> int:
+        """Enqueues frames (asynchronous).  Returns the index of the first one."""
+        bps = 1 if self.bit_depth == 8 else 2
+        y, py, fy = _plane_geometry(y, bps)
+        u, pu, fu = _plane_geometry(u, bps)
+        v, pv, fv = _plane_geometry(v, bps)
+        if pu != pv or fu != fv:
+            raise ValueError("U and V must share pitch and frame stride")
+        n = y.shape[0]
+        if u.shape[0] != n or v.shape[0] != n:
+            raise ValueError("planes hold different frame counts")
+        if y.shape[1:] != (self.height, self.width):
+            raise ValueError(f"luma shape {tuple(y.shape[1:])} != {(self.height, self.width)}")
+        if u.shape[1:] != (self.height // 2, self.width // 2) or v.shape[1:] != u.shape[1:]:
+            raise ValueError("chroma planes must be [n, H/2, W/2]")
+        fr = VcaFrames(y.data_ptr(), u.data_ptr(), v.data_ptr(), py, pu, fy, fu, 1)
+        first = self.submitted
+        check(_lib.lib().vca_analyze_frames(self._ctx, ctypes.byref(fr), n), "vca_analyze_frames",
+              self._ctx)
+        self._keep = [y, u, v]
+        return first
+
+    def features(self, first: int, count: int) -> np.ndarray:
+        """Features of frames [first, first + count) as float32 [count, 7]; waits."""
+        out = np.zeros((count, 7), np.float32)
+        check(_lib.lib().vca_features(self._ctx, first, count, out.ctypes.data_as(ctypes.c_void_p)),
+              "vca_features", self._ctx)
+        return out
+
+    def analyze(self, y: torch.Tensor, u: torch.Tensor, v: torch.Tensor) -> np.ndarray:
+        first = self.submit(y, u, v)
+        return self.features(first, self.submitted - first)
+
+    def block_coeffs(self, frame: int) -> np.ndarray:
+        """int16 [C_Y + C_U + C_V, K, K] of a frame of the most recent call."""
+        total = sum(self.counts)
+        out = np.zeros((total, self.k, self.k), np.int16)
+        check(_lib.lib().vca_block_coeffs(self._ctx, frame, out.ctypes.data_as(ctypes.c_void_p),
+                                          out.size), "vca_block_coeffs", self._ctx)
+        return out
+
+    def block_stats(self, frame: int) -> tuple[np.ndarray, np.ndarray]:
+        """(H float64, DC int32), each [C_Y + C_U + C_V], of a frame of the last launch."""
+        total = sum(self.counts)
+        h = np.zeros(total, np.float64)
+        dc = np.zeros(total, np.int32)
+        check(_lib.lib().vca_block_stats(self._ctx, frame, h.ctypes.data_as(ctypes.c_void_p),
+                                         dc.ctypes.data_as(ctypes.c_void_p), total),
+              "vca_block_stats", self._ctx)
+        return h, dc
+
+    def timing(self, reset: bool = False) -> dict:
+        """Kernel times measured with HIP events on the context's stream."""
+        t = _lib.VcaTiming()
+        check(_lib.lib().vca_get_timing(self._ctx, ctypes.byref(t), int(reset)), "vca_get_timing",
+              self._ctx)
+        return {f: getattr(t, f) for f, _ in t._fields_}
+
+    def reset(self) -> None:
+        check(_lib.lib().vca_reset(self._ctx), "vca_reset", self._ctx)

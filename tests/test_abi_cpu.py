@@ -1,0 +1,92 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/vca.h declares, and rejects bad configurations before it
+touches a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2304_12384_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vca.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vca_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert names, "no declarations parsed"
+    assert sorted(_lib.EXPORTS) == names
+    L = _lib.lib()
+    for n in names:
+        assert getattr(L, n) is not None
+
+
+def test_header_structs_match_binding():
+    assert ctypes.sizeof(_lib.VcaConfig) == 44
+    assert ctypes.sizeof(_lib.VcaFrameFeatures) == 28
+    assert ctypes.sizeof(_lib.VcaFrames) == 3 * 8 + 4 * 8 + 8
+
+
+def test_status_strings():
+    for code, name in [(0, "VCA_OK"), (1, "VCA_ERR_INVALID_ARG"), (2, "VCA_ERR_UNSUPPORTED"),
+                       (3, "VCA_ERR_OOM"), (4, "VCA_ERR_DEVICE"), (5, "VCA_ERR_STATE")]:
+        assert _lib.status_str(code) == name
+
+
+def cfg(**kw):
+    base = dict(width=3840, height=2160, bit_depth=8, chroma_format=420, block_size=32,
+                lowpass_k=0, device=0, flags=0, max_batch=0, feature_capacity=0)
+    base.update(kw)
+    c = _lib.VcaConfig()
+    c.struct_size = kw.pop("struct_size", ctypes.sizeof(_lib.VcaConfig))
+    for k, v in base.items():
+        setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("w,res,counts", [
+    (32, (3840, 2160), (8040, 1980, 1980)), (16, (1920, 1080), (8040, 1980, 1980)),
+    (8, (640, 360), (3600, 880, 880)), (32, (1280, 720), (880, 220, 220))])
+def test_block_counts(w, res, counts):
+    out = (ctypes.c_int32 * 3)()
+    c = cfg(width=res[0], height=res[1], block_size=w)
+    assert _lib.lib().vca_block_counts(ctypes.byref(c), out) == 0
+    assert tuple(out) == counts
+
+
+@pytest.mark.parametrize("bad", [
+    dict(block_size=4), dict(block_size=64), dict(bit_depth=9), dict(chroma_format=444),
+    dict(width=3841), dict(height=0), dict(width=62, block_size=32), dict(lowpass_k=3),
+    dict(lowpass_k=64), dict(max_batch=-1), dict(flags=0x80), dict(struct_size=12),
+    dict(device=-1)])
+def test_bad_config_rejected_before_device(bad):
+    c = cfg(**bad)
+    out = (ctypes.c_int32 * 3)()
+    assert _lib.lib().vca_block_counts(ctypes.byref(c), out) == _lib.VCA_ERR_INVALID_ARG
+    ctx = ctypes.c_void_p(1234)
+    assert _lib.lib().vca_open(ctypes.byref(c), None, ctypes.byref(ctx)) == _lib.VCA_ERR_INVALID_ARG
+    assert not ctx.value
+
+
+def test_null_arguments():
+    L = _lib.lib()
+    assert L.vca_open(None, None, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_analyze_frames(None, None, 0) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_features(None, 0, 0, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_reset(None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_frames_submitted(None) == -1
+    assert L.vca_last_error(None) == b""
+    L.vca_close(None)
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()
