@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -66,6 +67,22 @@ int log2i(int v) {
 }
 
 // ------------------------------------------------------------ kernel params
+// Division by an invariant d (Granlund-Montgomery, round-up multiplier):
+// n / d = (umulhi(n, m) + n) >> l for 0 <= n < 2^31, with l = ceil(log2 d)
+// and m = floor(2^32 (2^l - d) / d) + 1.  Keeps block-id decoding on the
+// scalar unit.
+struct FastDiv {
+  uint32_t m;
+  uint32_t l;
+};
+
+FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) l++;
+  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return FastDiv{(uint32_t)m, l};
+}
+
 struct FwdParams {
   const uint8_t* plane[3];
   int64_t pitch[3];
@@ -73,6 +90,8 @@ struct FwdParams {
   int32_t nbx[3];          // blocks per row of each plane
   int32_t cnt[3];          // blocks per plane
   int32_t per_frame;       // cnt[0] + cnt[1] + cnt[2]
+  FastDiv div_frame;       // / per_frame
+  FastDiv div_nbx[3];      // / nbx[P]
   int32_t n_frames;
   int32_t k;               // low-pass size (w when full)
   const v4i* tab_b1;       // [64] stage-1 B operand (C^T) per lane
@@ -102,95 +121,157 @@ __device__ inline uint32_t perm_b32(uint32_t hi_src, uint32_t lo_src, uint32_t s
   return __builtin_amdgcn_perm(hi_src, lo_src, sel);
 }
 
+__device__ inline uint32_t fastdiv(uint32_t n, FastDiv d) { return (__umulhi(n, d.m) + n) >> d.l; }
+
+// The 16 bytes lane (r + 32 g) loads for block `id` of a launch;
+// lane_off[P] = r * pitch[P] + 16 g.  The block's base address is
+// wave-uniform (scalar); the load uses it with a 32-bit per-lane offset.
+__device__ inline v4i load_block(const FwdParams& p, int id, const uint32_t lane_off[2]) {
+  const int f = (int)fastdiv((uint32_t)id, p.div_frame);
+  int b = id - f * p.per_frame;
+  int P = 0;
+  if (b >= p.cnt[0]) {
+    b -= p.cnt[0];
+    P = 1;
+    if (b >= p.cnt[1]) {
+      b -= p.cnt[1];
+      P = 2;
+    }
+  }
+  const int by = (int)fastdiv((uint32_t)b, p.div_nbx[P]);
+  const int bx = b - by * p.nbx[P];
+  const uint8_t* base = p.plane[P] + f * p.fstride[P] + (int64_t)by * kTile * p.pitch[P] + bx * kTile;
+  return *reinterpret_cast<const v4i*>(base + lane_off[P == 0 ? 0 : 1]);
+}
+
+// Blocks each wavefront keeps in flight ahead of the one it transforms.
+#ifndef VCA_PREFETCH_DEPTH
+#define VCA_PREFETCH_DEPTH 2
+#endif
+
+// Per-wavefront constants of the full-tile transform.
+template <int kRegs>
+struct TileConsts {
+  v4i b1;            // stage-1 B operand (C^T)
+  v4i a2;            // stage-2 A operand (C, contraction order of the accumulator rows)
+  double wt[kRegs];  // weight of the coefficient in each accumulator register
+  int row0_fix;      // +128 on coefficient row 0 (lanes 0..31, register 0)
+};
+
+// Transform, energy and DC of one 32 x 32 block whose 16 bytes per lane are
+// in x (8-bit samples).  Exact split of the horizontal-pass result T
+// (|T| <= 2^14):
+//   T = 256 * T_hi + u,  T_hi = T >> 8 in [-64, 63],  u = T & 255 in [0, 255]
+// so that C T = 256 * C T_hi + C (u - 128) + 128 * C 1.  Both T_hi and u - 128
+// are int8; the last term is 128 * 64 * 32 on coefficient row 0 (the DC row)
+// and 0 elsewhere, i.e. exactly +128 after the 2^11 scaling of the vertical
+// pass.  With the vertical pass's rounding 2^(s2-1) folded into the hi
+// accumulator as 2^(s2-9), both accumulator biases are MFMA inline constants.
+template <int kBits, int kRegs, bool kKeep>
+__device__ __forceinline__ void fwd32_block(const FwdParams& p, const TileConsts<kRegs>& tc,
+                                            v4i x, int id, int lane) {
+  constexpr int kS1 = 5 + kBits - 9;   // log2(32) + B - 9
+  constexpr int kS2 = 5 + 6;           // log2(32) + 6
+  v16i c1, c2;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    c1[j] = 1 << (kS1 - 1);            // rounding of the horizontal pass
+    c2[j] = 1 << (kS2 - 9);            // 256 * 2^(s2-9) = 2^(s2-1): rounding of the vertical pass
+  }
+  const v16i zero = {};
+  x ^= (int)0x80808080;                // x - 128 as int8
+
+  const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, tc.b1, c1, 0, 0, 0);
+
+  v4i tlo, thi;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const uint32_t s0 = (uint32_t)(d1[4 * q + 0] >> kS1);
+    const uint32_t s1 = (uint32_t)(d1[4 * q + 1] >> kS1);
+    const uint32_t s2 = (uint32_t)(d1[4 * q + 2] >> kS1);
+    const uint32_t s3 = (uint32_t)(d1[4 * q + 3] >> kS1);
+    const uint32_t p01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
+    const uint32_t p23 = perm_b32(s3, s2, 0x05010400u);
+    tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
+    thi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
+  }
+  const v16i dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, thi, c2, 0, 0, 0);
+  const v16i dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, tlo, zero, 0, 0, 0);
+
+  double h0 = 0.0, h1 = 0.0;
+  int y0 = 0;
+#pragma unroll
+  for (int j = 0; j < kRegs; j++) {
+    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
+    if (j == 0) {
+      yv += tc.row0_fix;
+      y0 = yv;
+    }
+    if (j & 1)
+      h1 = fma(tc.wt[j], fabs((double)yv), h1);
+    else
+      h0 = fma(tc.wt[j], fabs((double)yv), h0);
+    if (kKeep) {
+      const int kk = p.k;
+      const int g = lane >> 5, r = lane & 31;
+      const int i = 8 * (j >> 2) + 4 * g + (j & 3);
+      if (i < kk && r < kk) {
+        const int out = yv + ((i == 0 && r == 0) ? kDcOffset : 0);
+        p.coeffs[((int64_t)id * kk + i) * kk + r] = (int16_t)out;
+      }
+    }
+  }
+  double h = h0 + h1;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) h += __shfl_xor(h, off);
+  if (lane == 0) {
+    p.blk_h[id] = h;
+    p.blk_dc[id] = y0 + kDcOffset;
+  }
+}
+
 // Full-tile forward kernel, w = 32, 8-bit samples.  One wavefront per block;
-// the grid loops over all blocks of all frames of the launch.
+// the grid loops over all blocks of all frames of the launch, each wavefront
+// keeping VCA_PREFETCH_DEPTH blocks in flight in a register ring (the loop
+// body is unrolled over the ring, so no registers move).
 // kRegs: accumulator registers that hold coefficients inside the K x K corner
 // (16: K = 32, 8: K = 16, 4: K = 8); kKeep: also store the coefficients.
 template <int kBits, int kRegs, bool kKeep>
 __global__ __launch_bounds__(kGroupThreads) void fwd32_kernel(FwdParams p) {
-  constexpr int kS1 = 5 + kBits - 9;   // log2(32) + B - 9
-  constexpr int kS2 = 5 + 6;           // log2(32) + 6
+  constexpr int kDepth = VCA_PREFETCH_DEPTH;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 31;             // tile row loaded by this lane / output column
   const int g = lane >> 5;             // half of the row loaded by this lane
+  const uint32_t lane_off[2] = {(uint32_t)(r * p.pitch[0] + 16 * g),
+                                (uint32_t)(r * p.pitch[1] + 16 * g)};
 
-  const v4i b1 = p.tab_b1[lane];
-  const v4i a2 = p.tab_a2[lane];
-  double wt[kRegs];
+  TileConsts<kRegs> tc;
+  tc.b1 = p.tab_b1[lane];
+  tc.a2 = p.tab_a2[lane];
 #pragma unroll
-  for (int j = 0; j < kRegs; j++) wt[j] = p.tab_w[j * 64 + lane];
+  for (int j = 0; j < kRegs; j++) tc.wt[j] = p.tab_w[j * 64 + lane];
+  tc.row0_fix = g == 0 ? 128 : 0;
 
-  // Stage-1 accumulator bias: +2^(s1-1) rounds, +2^(s1+7) recentres the low
-  // byte so that (acc >> s1) holds T + 128: byte 0 = (T + 128) mod 256 and
-  // byte 1 = (T + 128) >> 8 = T_hi, with T = 256 T_hi + (byte0 - 128).
-  v16i c1, c2;
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    c1[j] = (1 << (kS1 - 1)) + (1 << (kS1 + 7));
-    c2[j] = 1 << (kS2 - 9);            // 256 * 2^(s2-9) = 2^(s2-1): rounding of the hi part
-  }
-  const v16i zero = {};
   const int total = p.n_frames * p.per_frame;
   const int stride = gridDim.x * kWavesPerGroup;
-
-  for (int id = blockIdx.x * kWavesPerGroup + wave; id < total; id += stride) {
-    const int f = id / p.per_frame;
-    int b = id - f * p.per_frame;
-    int P = 0;
-    if (b >= p.cnt[0]) {
-      b -= p.cnt[0];
-      P = 1;
-      if (b >= p.cnt[1]) {
-        b -= p.cnt[1];
-        P = 2;
+  int id = blockIdx.x * kWavesPerGroup + wave;
+  v4i ring[kDepth];
+#pragma unroll
+  for (int s = 0; s < kDepth; s++) {
+    const int nid = id + s * stride;
+    ring[s] = nid < total ? load_block(p, nid, lane_off) : v4i{};
+  }
+  while (id < total) {
+#pragma unroll
+    for (int s = 0; s < kDepth; s++) {
+      if (id < total) {
+        const v4i x = ring[s];
+        const int nid = id + kDepth * stride;
+        if (nid < total) ring[s] = load_block(p, nid, lane_off);
+        fwd32_block<kBits, kRegs, kKeep>(p, tc, x, id, lane);
+        id += stride;
       }
-    }
-    const int by = b / p.nbx[P];
-    const int bx = b - by * p.nbx[P];
-    const uint8_t* src = p.plane[P] + f * p.fstride[P] + (int64_t)(by * kTile + r) * p.pitch[P] +
-                         bx * kTile + 16 * g;
-    v4i x = *reinterpret_cast<const v4i*>(src);
-    x ^= (int)0x80808080;              // x - 128 as int8
-
-    const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, b1, c1, 0, 0, 0);
-
-    v4i tlo, thi;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const uint32_t s0 = (uint32_t)(d1[4 * q + 0] >> kS1);
-      const uint32_t s1 = (uint32_t)(d1[4 * q + 1] >> kS1);
-      const uint32_t s2 = (uint32_t)(d1[4 * q + 2] >> kS1);
-      const uint32_t s3 = (uint32_t)(d1[4 * q + 3] >> kS1);
-      const uint32_t p01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
-      const uint32_t p23 = perm_b32(s3, s2, 0x05010400u);
-      tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);
-      thi[q] = (int)perm_b32(p23, p01, 0x07060302u);
-    }
-    const v16i dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, thi, c2, 0, 0, 0);
-    const v16i dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, tlo, zero, 0, 0, 0);
-
-    double h = 0.0;
-    int y0 = 0;
-#pragma unroll
-    for (int j = 0; j < kRegs; j++) {
-      const int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
-      if (j == 0) y0 = yv;
-      h = fma(wt[j], fabs((double)yv), h);
-      if (kKeep) {
-        const int kk = p.k;
-        const int i = 8 * (j >> 2) + 4 * g + (j & 3);
-        if (i < kk && r < kk) {
-          const int out = yv + ((i == 0 && r == 0) ? kDcOffset : 0);
-          p.coeffs[((int64_t)id * kk + i) * kk + r] = (int16_t)out;
-        }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) h += __shfl_xor(h, off);
-    if (lane == 0) {
-      p.blk_h[id] = h;
-      p.blk_dc[id] = y0 + kDcOffset;
     }
   }
 }
@@ -247,6 +328,7 @@ struct vca_ctx {
   int32_t per_frame = 0;
   int device = 0;
   int num_cus = 0;
+  int groups_per_cu = 0;           // 0: as many as fit (VCA_GROUPS_PER_CU overrides)
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // device tables and state
@@ -438,6 +520,7 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(VCA_ERR_DEVICE);
   c->num_cus = prop.multiProcessorCount;
+  if (const char* e = std::getenv("VCA_GROUPS_PER_CU")) c->groups_per_cu = std::atoi(e);
   if (hip_stream) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   } else {
@@ -484,6 +567,8 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
   if (!fr->y || !fr->u || !fr->v) return fail(ctx, VCA_ERR_INVALID_ARG, "null plane pointer");
   if (fr->pitch_y < (int64_t)cfg.width * bps || fr->pitch_uv < (int64_t)cfg.width / 2 * bps)
     return fail(ctx, VCA_ERR_INVALID_ARG, "pitch smaller than a row");
+  if (fr->pitch_y > (1 << 26) || fr->pitch_uv > (1 << 26))
+    return fail(ctx, VCA_ERR_INVALID_ARG, "pitch above 64 MiB");   // lane offsets are 32-bit
   if (n_frames > 1 && (fr->fstride_y < fr->pitch_y * cfg.height ||
                        fr->fstride_uv < fr->pitch_uv * (cfg.height / 2)))
     return fail(ctx, VCA_ERR_INVALID_ARG, "frame stride smaller than a frame");
@@ -512,7 +597,9 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
       fp.fstride[P] = fs[P];
       fp.nbx[P] = ctx->nbx[P];
       fp.cnt[P] = ctx->cnt[P];
+      fp.div_nbx[P] = make_fastdiv((uint32_t)ctx->nbx[P]);
     }
+    fp.div_frame = make_fastdiv((uint32_t)ctx->per_frame);
     fp.per_frame = ctx->per_frame;
     fp.n_frames = n;
     fp.k = ctx->K;
@@ -524,13 +611,19 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
     fp.coeffs = ctx->coeffs;
     const int64_t waves = (int64_t)n * ctx->per_frame;
     const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
-    const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * 8);
     const bool keep = ctx->coeffs != nullptr;
     const int regs = ctx->K == 32 ? 16 : (ctx->K == 16 ? 8 : 4);
     void (*kern)(FwdParams) = nullptr;
     if (regs == 16) kern = keep ? fwd32_kernel<8, 16, true> : fwd32_kernel<8, 16, false>;
     if (regs == 8) kern = keep ? fwd32_kernel<8, 8, true> : fwd32_kernel<8, 8, false>;
     if (regs == 4) kern = keep ? fwd32_kernel<8, 4, true> : fwd32_kernel<8, 4, false>;
+    // Persistent grid: exactly as many workgroups as can be resident at once,
+    // so no workgroup waits for another to drain before it starts its loop.
+    int resident = 0;
+    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0));
+    resident = std::max(1, resident);
+    if (ctx->groups_per_cu > 0) resident = std::min(resident, ctx->groups_per_cu);
+    const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
     hipEvent_t* ev = nullptr;
     if (cfg.flags & VCA_F_TIMING) {
       if (ctx->ev_used + 3 > ctx->ev_pool.size()) {
