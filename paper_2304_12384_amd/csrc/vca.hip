@@ -1,22 +1,16 @@
-// vca.hip -- MI355X (gfx950) Video Complexity Analyzer: kernels and C ABI.
+// vca.hip -- MI355X (gfx950) Video Complexity Analyzer: plain path and C ABI.
 //
 // Computes the per-frame block-DCT features of Menon et al. (GMSys 2023),
 // Section 2 (E_Y, h, L_Y, E_U, E_V, L_U, L_V) and the low-pass option of the
-// same section.  The definitions implemented are stated in include/vca.h.
+// same section, for 8/10-bit 4:2:0 video and block sizes 8, 16, 32.  The
+// definitions implemented are stated in include/vca.h.
 //
-// Data path per 32 x 32 tile (one wavefront per tile):
-//   1. one 16-byte global load per lane: lane (r + 32 g) reads row r, bytes
-//      16g..16g+15 of the tile (8-bit samples), offset by -128 into int8;
-//   2. horizontal pass T = X' C^T on one v_mfma_i32_32x32x32_i8 with the
-//      rounding bias preloaded in the accumulator;
-//   3. the accumulator (lane = column k, 16 rows per lane) is split into
-//      int8 hi/lo bytes in registers -- exactly the B-operand layout of the
-//      vertical pass, so T never leaves the register file;
-//   4. vertical pass Y = C T as two int8 MFMAs (hi, lo) recombined exactly;
-//   5. per lane: FP64 weighted sum of |Y|; one wavefront reduction gives the
-//      block energy H; lane 0 holds DC (offset corrected by +2^14).
-// A second kernel reduces the per-block H and DC of each frame, in a fixed
-// order, to the seven features (FP64 sums, FP32 output).
+// Kernels:
+//   fwd_kernel     persistent grid over all 32 x 32 tiles of all frames of a
+//                  launch; one wavefront per tile (vca_tile.h) with a
+//                  register ring of tiles in flight; per-block H and DC out.
+//   reduce_kernel  one workgroup per frame: fixed-order FP64 sums of H,
+//                  sqrt(DC) and |H_p - H_{p-1}| into the seven features.
 
 #include <hip/hip_runtime.h>
 
@@ -30,76 +24,37 @@
 #include <vector>
 
 #include "../../include/vca.h"
+#include "vca_tile.h"
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v16i __attribute__((ext_vector_type(16)));
+using namespace vca;
 
 namespace {
 
-constexpr int kTile = 32;           // MFMA tile edge (pixels)
 constexpr int kWavesPerGroup = 4;   // wavefronts per workgroup
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
-constexpr int kDcOffset = 1 << 14;  // DC lost by the -2^(B-1) sample offset, exact for all w, B
 
-// ---------------------------------------------------------------- the matrix
-// Integer stand-ins for 64*sqrt(2)*cos(pi*t/64), t = 0..32 (H.265 core
-// transform values; t = 32 is the zero of the cosine).
-constexpr int kCosQuarter[33] = {90, 90, 90, 90, 89, 88, 87, 85, 83, 82, 80, 78, 75, 73, 70, 67, 64,
-                                 61, 57, 54, 50, 46, 43, 38, 36, 31, 25, 22, 18, 13, 9,  4,  0};
-
-// Entry (k, n) of the 32-point matrix via the quadrant of the angle k(2n+1).
-int mat32(int k, int n) {
-  if (k == 0) return 64;
-  int t = (k * (2 * n + 1)) & 127;
-  if (t <= 32) return kCosQuarter[t];
-  if (t <= 64) return -kCosQuarter[64 - t];
-  if (t <= 96) return -kCosQuarter[t - 64];
-  return kCosQuarter[128 - t];
-}
-
-// w-point matrix: the 32-point one restricted to every (32/w)-th row.
-int matw(int w, int k, int n) { return mat32(k * (kTile / w), n); }
-
-int log2i(int v) {
-  int s = 0;
-  while ((1 << s) < v) s++;
-  return s;
-}
-
-// ------------------------------------------------------------ kernel params
-// Division by an invariant d (Granlund-Montgomery, round-up multiplier):
-// n / d = (umulhi(n, m) + n) >> l for 0 <= n < 2^31, with l = ceil(log2 d)
-// and m = floor(2^32 (2^l - d) / d) + 1.  Keeps block-id decoding on the
-// scalar unit.
-struct FastDiv {
-  uint32_t m;
-  uint32_t l;
-};
-
-FastDiv make_fastdiv(uint32_t d) {
-  uint32_t l = 0;
-  while ((1ull << l) < d) l++;
-  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
-  return FastDiv{(uint32_t)m, l};
-}
+// Tiles each wavefront keeps in flight ahead of the one it transforms.
+#ifndef VCA_PREFETCH_DEPTH
+#define VCA_PREFETCH_DEPTH 2
+#endif
 
 struct FwdParams {
   const uint8_t* plane[3];
-  int64_t pitch[3];
-  int64_t fstride[3];
-  int32_t nbx[3];          // blocks per row of each plane
-  int32_t cnt[3];          // blocks per plane
-  int32_t per_frame;       // cnt[0] + cnt[1] + cnt[2]
-  FastDiv div_frame;       // / per_frame
-  FastDiv div_nbx[3];      // / nbx[P]
+  int32_t pitch[3];        // bytes between rows
+  int64_t fstride[3];      // bytes between frames
+  int32_t nbx[3], nby[3];  // blocks per row / column of each plane
+  int32_t ntx[3];          // tiles per row
+  int32_t tcnt[3];         // tiles per plane
+  int32_t boff[3];         // index of the plane's first block within a frame
+  int32_t tiles_per_frame;
+  int32_t per_frame;       // blocks per frame
+  FastDiv div_tpf;         // / tiles_per_frame
+  FastDiv div_ntx[3];      // / ntx[P]
   int32_t n_frames;
-  int32_t k;               // low-pass size (w when full)
-  const v4i* tab_b1;       // [64] stage-1 B operand (C^T) per lane
-  const v4i* tab_a2;       // [64] stage-2 A operand (C, rows permuted) per lane
-  const double* tab_w;     // [16][64] weight per (accumulator register, lane)
-  double* blk_h;           // [n_frames][per_frame]
-  int32_t* blk_dc;         // [n_frames][per_frame]
-  int16_t* coeffs;         // optional [n_frames][per_frame][k][k]
+  const v4i* tab_b1;
+  const v4i* tab_a2;
+  const double* tab_w;
+  TileOut out;
 };
 
 struct ReduceParams {
@@ -116,160 +71,64 @@ struct ReduceParams {
   double inv_norm[3];      // 1 / (C_P w^2)
 };
 
-// ------------------------------------------------------------------ kernels
-__device__ inline uint32_t perm_b32(uint32_t hi_src, uint32_t lo_src, uint32_t sel) {
-  return __builtin_amdgcn_perm(hi_src, lo_src, sel);
-}
-
-__device__ inline uint32_t fastdiv(uint32_t n, FastDiv d) { return (__umulhi(n, d.m) + n) >> d.l; }
-
-// The 16 bytes lane (r + 32 g) loads for block `id` of a launch;
-// lane_off[P] = r * pitch[P] + 16 g.  The block's base address is
-// wave-uniform (scalar); the load uses it with a 32-bit per-lane offset.
-__device__ inline v4i load_block(const FwdParams& p, int id, const uint32_t lane_off[2]) {
-  const int f = (int)fastdiv((uint32_t)id, p.div_frame);
-  int b = id - f * p.per_frame;
+// Tile `id` of a launch (frame-major, then Y, U, V, then raster order).
+template <int kBits, int kW>
+__device__ inline TileWork decode_tile(const FwdParams& p, int id) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kBpt = kTile / kW;
+  const int f = (int)fastdiv((uint32_t)id, p.div_tpf);
+  int t = id - f * p.tiles_per_frame;
   int P = 0;
-  if (b >= p.cnt[0]) {
-    b -= p.cnt[0];
+  if (t >= p.tcnt[0]) {
+    t -= p.tcnt[0];
     P = 1;
-    if (b >= p.cnt[1]) {
-      b -= p.cnt[1];
+    if (t >= p.tcnt[1]) {
+      t -= p.tcnt[1];
       P = 2;
     }
   }
-  const int by = (int)fastdiv((uint32_t)b, p.div_nbx[P]);
-  const int bx = b - by * p.nbx[P];
-  const uint8_t* base = p.plane[P] + f * p.fstride[P] + (int64_t)by * kTile * p.pitch[P] + bx * kTile;
-  return *reinterpret_cast<const v4i*>(base + lane_off[P == 0 ? 0 : 1]);
+  const int ty = (int)fastdiv((uint32_t)t, p.div_ntx[P]);
+  const int tx = t - ty * p.ntx[P];
+  const int by0 = ty * kBpt, bx0 = tx * kBpt;
+  TileWork w;
+  w.pitch = p.pitch[P];
+  w.base = p.plane[P] + f * p.fstride[P] + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
+  w.vr = min(kBpt, p.nby[P] - by0);
+  w.vc = min(kBpt, p.nbx[P] - bx0);
+  w.out0 = f * p.per_frame + p.boff[P] + by0 * p.nbx[P] + bx0;
+  w.out_row = p.nbx[P];
+  return w;
 }
 
-// Blocks each wavefront keeps in flight ahead of the one it transforms.
-#ifndef VCA_PREFETCH_DEPTH
-#define VCA_PREFETCH_DEPTH 2
-#endif
-
-// Per-wavefront constants of the full-tile transform.
-template <int kRegs>
-struct TileConsts {
-  v4i b1;            // stage-1 B operand (C^T)
-  v4i a2;            // stage-2 A operand (C, contraction order of the accumulator rows)
-  double wt[kRegs];  // weight of the coefficient in each accumulator register
-  int row0_fix;      // +128 on coefficient row 0 (lanes 0..31, register 0)
-};
-
-// Transform, energy and DC of one 32 x 32 block whose 16 bytes per lane are
-// in x (8-bit samples).  Exact split of the horizontal-pass result T
-// (|T| <= 2^14):
-//   T = 256 * T_hi + u,  T_hi = T >> 8 in [-64, 63],  u = T & 255 in [0, 255]
-// so that C T = 256 * C T_hi + C (u - 128) + 128 * C 1.  Both T_hi and u - 128
-// are int8; the last term is 128 * 64 * 32 on coefficient row 0 (the DC row)
-// and 0 elsewhere, i.e. exactly +128 after the 2^11 scaling of the vertical
-// pass.  With the vertical pass's rounding 2^(s2-1) folded into the hi
-// accumulator as 2^(s2-9), both accumulator biases are MFMA inline constants.
-template <int kBits, int kRegs, bool kKeep>
-__device__ __forceinline__ void fwd32_block(const FwdParams& p, const TileConsts<kRegs>& tc,
-                                            v4i x, int id, int lane) {
-  constexpr int kS1 = 5 + kBits - 9;   // log2(32) + B - 9
-  constexpr int kS2 = 5 + 6;           // log2(32) + 6
-  v16i c1, c2;
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    c1[j] = 1 << (kS1 - 1);            // rounding of the horizontal pass
-    c2[j] = 1 << (kS2 - 9);            // 256 * 2^(s2-9) = 2^(s2-1): rounding of the vertical pass
-  }
-  const v16i zero = {};
-  x ^= (int)0x80808080;                // x - 128 as int8
-
-  const v16i d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, tc.b1, c1, 0, 0, 0);
-
-  v4i tlo, thi;
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    const uint32_t s0 = (uint32_t)(d1[4 * q + 0] >> kS1);
-    const uint32_t s1 = (uint32_t)(d1[4 * q + 1] >> kS1);
-    const uint32_t s2 = (uint32_t)(d1[4 * q + 2] >> kS1);
-    const uint32_t s3 = (uint32_t)(d1[4 * q + 3] >> kS1);
-    const uint32_t p01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
-    const uint32_t p23 = perm_b32(s3, s2, 0x05010400u);
-    tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
-    thi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
-  }
-  const v16i dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, thi, c2, 0, 0, 0);
-  const v16i dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, tlo, zero, 0, 0, 0);
-
-  double h0 = 0.0, h1 = 0.0;
-  int y0 = 0;
-#pragma unroll
-  for (int j = 0; j < kRegs; j++) {
-    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
-    if (j == 0) {
-      yv += tc.row0_fix;
-      y0 = yv;
-    }
-    if (j & 1)
-      h1 = fma(tc.wt[j], fabs((double)yv), h1);
-    else
-      h0 = fma(tc.wt[j], fabs((double)yv), h0);
-    if (kKeep) {
-      const int kk = p.k;
-      const int g = lane >> 5, r = lane & 31;
-      const int i = 8 * (j >> 2) + 4 * g + (j & 3);
-      if (i < kk && r < kk) {
-        const int out = yv + ((i == 0 && r == 0) ? kDcOffset : 0);
-        p.coeffs[((int64_t)id * kk + i) * kk + r] = (int16_t)out;
-      }
-    }
-  }
-  double h = h0 + h1;
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) h += __shfl_xor(h, off);
-  if (lane == 0) {
-    p.blk_h[id] = h;
-    p.blk_dc[id] = y0 + kDcOffset;
-  }
-}
-
-// Full-tile forward kernel, w = 32, 8-bit samples.  One wavefront per block;
-// the grid loops over all blocks of all frames of the launch, each wavefront
-// keeping VCA_PREFETCH_DEPTH blocks in flight in a register ring (the loop
-// body is unrolled over the ring, so no registers move).
-// kRegs: accumulator registers that hold coefficients inside the K x K corner
-// (16: K = 32, 8: K = 16, 4: K = 8); kKeep: also store the coefficients.
-template <int kBits, int kRegs, bool kKeep>
-__global__ __launch_bounds__(kGroupThreads) void fwd32_kernel(FwdParams p) {
+// Persistent forward kernel: each wavefront walks tiles id, id + S, ...
+// (S = all wavefronts of the grid), keeping VCA_PREFETCH_DEPTH tiles in
+// flight in a register ring (the loop body is unrolled over the ring, so no
+// registers move).
+template <int kBits, int kW, int kK, bool kKeep>
+__global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
   constexpr int kDepth = VCA_PREFETCH_DEPTH;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r = lane & 31;             // tile row loaded by this lane / output column
-  const int g = lane >> 5;             // half of the row loaded by this lane
-  const uint32_t lane_off[2] = {(uint32_t)(r * p.pitch[0] + 16 * g),
-                                (uint32_t)(r * p.pitch[1] + 16 * g)};
+  TileConsts<kW, kK> tc;
+  tc.load(p.tab_b1, p.tab_a2, p.tab_w, lane);
 
-  TileConsts<kRegs> tc;
-  tc.b1 = p.tab_b1[lane];
-  tc.a2 = p.tab_a2[lane];
-#pragma unroll
-  for (int j = 0; j < kRegs; j++) tc.wt[j] = p.tab_w[j * 64 + lane];
-  tc.row0_fix = g == 0 ? 128 : 0;
-
-  const int total = p.n_frames * p.per_frame;
+  const int total = p.n_frames * p.tiles_per_frame;
   const int stride = gridDim.x * kWavesPerGroup;
   int id = blockIdx.x * kWavesPerGroup + wave;
-  v4i ring[kDepth];
+  TileData ring[kDepth];
 #pragma unroll
   for (int s = 0; s < kDepth; s++) {
     const int nid = id + s * stride;
-    ring[s] = nid < total ? load_block(p, nid, lane_off) : v4i{};
+    if (nid < total) ring[s] = load_tile<kBits, kW>(decode_tile<kBits, kW>(p, nid), lane);
   }
   while (id < total) {
 #pragma unroll
     for (int s = 0; s < kDepth; s++) {
       if (id < total) {
-        const v4i x = ring[s];
+        const TileData d = ring[s];
         const int nid = id + kDepth * stride;
-        if (nid < total) ring[s] = load_block(p, nid, lane_off);
-        fwd32_block<kBits, kRegs, kKeep>(p, tc, x, id, lane);
+        if (nid < total) ring[s] = load_tile<kBits, kW>(decode_tile<kBits, kW>(p, nid), lane);
+        fwd_tile<kBits, kW, kK, kKeep>(p.out, tc, d, decode_tile<kBits, kW>(p, id), lane);
         id += stride;
       }
     }
@@ -325,7 +184,11 @@ struct vca_ctx {
   int K = 0;
   int32_t cnt[3] = {0, 0, 0};
   int32_t nbx[3] = {0, 0, 0};
+  int32_t nby[3] = {0, 0, 0};
+  int32_t ntx[3] = {0, 0, 0};
+  int32_t tcnt[3] = {0, 0, 0};
   int32_t per_frame = 0;
+  int32_t tiles_per_frame = 0;
   int device = 0;
   int num_cus = 0;
   int groups_per_cu = 0;           // 0: as many as fit (VCA_GROUPS_PER_CU overrides)
@@ -338,6 +201,7 @@ struct vca_ctx {
   double* blk_h = nullptr;
   int32_t* blk_dc = nullptr;
   int16_t* coeffs = nullptr;
+  int32_t* err_flag = nullptr;
   double* state[2] = {nullptr, nullptr};
   float* ring = nullptr;
   int cur_state = 0;
@@ -409,30 +273,32 @@ vca_status dev_alloc(vca_ctx* c, T** p, size_t count) {
   return VCA_OK;
 }
 
-// Per-lane operand and weight tables for the 32 x 32 tile.
-void build_tables(int w, int K, std::vector<int8_t>& b1, std::vector<int8_t>& a2,
-                  std::vector<double>& wt) {
-  b1.assign(64 * 16, 0);
-  a2.assign(64 * 16, 0);
-  wt.assign(16 * 64, 0.0);
-  for (int lane = 0; lane < 64; lane++) {
-    const int c = lane & 31, g = lane >> 5;
-    for (int j = 0; j < 16; j++) {
-      // stage 1: B[n][k] = C[k][n] with n = 16 g + j (the bytes each lane loads)
-      b1[lane * 16 + j] = (int8_t)matw(w, c, 16 * g + j);
-      // stage 2: A[i][m] = C[i][m] with m = the row held by accumulator register j
-      const int m = 8 * (j >> 2) + 4 * g + (j & 3);
-      a2[lane * 16 + j] = (int8_t)matw(w, c, m);
-      // weight of output (i, k) held by register j of lane (k + 32 g)
-      const int i = m;
-      double wv = 0.0;
-      if (i < K && c < K && !(i == 0 && c == 0)) {
-        const double q = (double)((i + 1) * (c + 1)) / (double)(w * w);
-        wv = std::exp(std::fabs(q * q - 1.0));
-      }
-      wt[j * 64 + lane] = wv;
-    }
-  }
+// Kernel for (bit depth, w, K, coefficient export).
+using FwdKernel = void (*)(FwdParams);
+
+template <int B, int W, int K>
+FwdKernel pick_keep(bool keep) {
+  return keep ? fwd_kernel<B, W, K, true> : fwd_kernel<B, W, K, false>;
+}
+
+template <int B, int W>
+FwdKernel pick_k(int K, bool keep) {
+  if (K == W) return pick_keep<B, W, W>(keep);
+  if (K == W / 2) return pick_keep<B, W, W / 2>(keep);
+  if (K == W / 4) return pick_keep<B, W, W / 4>(keep);
+  return nullptr;
+}
+
+template <int B>
+FwdKernel pick_w(int w, int K, bool keep) {
+  if (w == 32) return pick_k<B, 32>(K, keep);
+  if (w == 16) return pick_k<B, 16>(K, keep);
+  if (w == 8) return pick_k<B, 8>(K, keep);
+  return nullptr;
+}
+
+FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep) {
+  return bits == 8 ? pick_w<8>(w, K, keep) : (bits == 10 ? pick_w<10>(w, K, keep) : nullptr);
 }
 
 }  // namespace
@@ -471,8 +337,8 @@ void vca_close(vca_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void* bufs[] = {ctx->tab_b1, ctx->tab_a2, ctx->tab_w, ctx->blk_h, ctx->blk_dc,
-                    ctx->coeffs, ctx->state[0], ctx->state[1], ctx->ring};
+    void* bufs[] = {ctx->tab_b1, ctx->tab_a2, ctx->tab_w, ctx->blk_h,    ctx->blk_dc,
+                    ctx->coeffs, ctx->err_flag, ctx->state[0], ctx->state[1], ctx->ring};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -486,7 +352,6 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   *out = nullptr;
   vca_status s = check_config(cfg);
   if (s != VCA_OK) return s;
-  if (cfg->block_size != 32 || cfg->bit_depth != 8) return VCA_ERR_UNSUPPORTED;
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return VCA_ERR_DEVICE;
@@ -507,9 +372,17 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   const int w = cfg->block_size;
   c->K = cfg->lowpass_k == 0 ? w : cfg->lowpass_k;
   vca_block_counts(cfg, c->cnt);
-  c->nbx[0] = cfg->width / w;
-  c->nbx[1] = c->nbx[2] = cfg->width / 2 / w;
+  const int bpt = kTile / w;
+  for (int P = 0; P < 3; P++) {
+    const int pw = P == 0 ? cfg->width : cfg->width / 2;
+    const int ph = P == 0 ? cfg->height : cfg->height / 2;
+    c->nbx[P] = pw / w;
+    c->nby[P] = ph / w;
+    c->ntx[P] = (c->nbx[P] + bpt - 1) / bpt;
+    c->tcnt[P] = c->ntx[P] * ((c->nby[P] + bpt - 1) / bpt);
+  }
   c->per_frame = c->cnt[0] + c->cnt[1] + c->cnt[2];
+  c->tiles_per_frame = c->tcnt[0] + c->tcnt[1] + c->tcnt[2];
   c->device = cfg->device;
 
   auto bail = [&](vca_status st) {
@@ -537,12 +410,14 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   if ((s = dev_alloc(c, &c->state[0], c->cnt[0])) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->state[1], c->cnt[0])) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->ring, (size_t)c->cfg.feature_capacity * 7)) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->err_flag, 1)) != VCA_OK) return bail(s);
+  if (hipMemset(c->err_flag, 0, sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
   if (cfg->flags & VCA_F_KEEP_COEFFS)
     if ((s = dev_alloc(c, &c->coeffs, mb * c->per_frame * c->K * c->K)) != VCA_OK) return bail(s);
 
   std::vector<int8_t> b1, a2;
   std::vector<double> wt;
-  build_tables(w, c->K, b1, a2, wt);
+  build_tile_tables(w, c->K, b1, a2, wt);
   if (hipMemcpy(c->tab_b1, b1.data(), b1.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_a2, a2.data(), a2.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_w, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice) !=
@@ -567,8 +442,8 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
   if (!fr->y || !fr->u || !fr->v) return fail(ctx, VCA_ERR_INVALID_ARG, "null plane pointer");
   if (fr->pitch_y < (int64_t)cfg.width * bps || fr->pitch_uv < (int64_t)cfg.width / 2 * bps)
     return fail(ctx, VCA_ERR_INVALID_ARG, "pitch smaller than a row");
-  if (fr->pitch_y > (1 << 26) || fr->pitch_uv > (1 << 26))
-    return fail(ctx, VCA_ERR_INVALID_ARG, "pitch above 64 MiB");   // lane offsets are 32-bit
+  if (fr->pitch_y >= (1 << 23) || fr->pitch_uv >= (1 << 23))
+    return fail(ctx, VCA_ERR_INVALID_ARG, "pitch of 8 MiB or more");   // 24-bit lane offsets
   if (n_frames > 1 && (fr->fstride_y < fr->pitch_y * cfg.height ||
                        fr->fstride_uv < fr->pitch_uv * (cfg.height / 2)))
     return fail(ctx, VCA_ERR_INVALID_ARG, "frame stride smaller than a frame");
@@ -591,32 +466,35 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
                               static_cast<const uint8_t*>(fr->v)};
     const int64_t fs[3] = {fr->fstride_y, fr->fstride_uv, fr->fstride_uv};
     const int64_t pt[3] = {fr->pitch_y, fr->pitch_uv, fr->pitch_uv};
+    int32_t boff = 0;
     for (int P = 0; P < 3; P++) {
       fp.plane[P] = base[P] + fs[P] * done;
-      fp.pitch[P] = pt[P];
+      fp.pitch[P] = (int32_t)pt[P];
       fp.fstride[P] = fs[P];
       fp.nbx[P] = ctx->nbx[P];
-      fp.cnt[P] = ctx->cnt[P];
-      fp.div_nbx[P] = make_fastdiv((uint32_t)ctx->nbx[P]);
+      fp.nby[P] = ctx->nby[P];
+      fp.ntx[P] = ctx->ntx[P];
+      fp.tcnt[P] = ctx->tcnt[P];
+      fp.boff[P] = boff;
+      boff += ctx->cnt[P];
+      fp.div_ntx[P] = make_fastdiv((uint32_t)ctx->ntx[P]);
     }
-    fp.div_frame = make_fastdiv((uint32_t)ctx->per_frame);
+    fp.tiles_per_frame = ctx->tiles_per_frame;
     fp.per_frame = ctx->per_frame;
+    fp.div_tpf = make_fastdiv((uint32_t)ctx->tiles_per_frame);
     fp.n_frames = n;
-    fp.k = ctx->K;
     fp.tab_b1 = ctx->tab_b1;
     fp.tab_a2 = ctx->tab_a2;
     fp.tab_w = ctx->tab_w;
-    fp.blk_h = ctx->blk_h;
-    fp.blk_dc = ctx->blk_dc;
-    fp.coeffs = ctx->coeffs;
-    const int64_t waves = (int64_t)n * ctx->per_frame;
+    fp.out.blk_h = ctx->blk_h;
+    fp.out.blk_dc = ctx->blk_dc;
+    fp.out.coeffs = ctx->coeffs;
+    fp.out.err_flag = ctx->err_flag;
+    fp.out.validate = (cfg.flags & VCA_F_VALIDATE) && cfg.bit_depth == 10 ? 1 : 0;
+    const int64_t waves = (int64_t)n * ctx->tiles_per_frame;
     const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
-    const bool keep = ctx->coeffs != nullptr;
-    const int regs = ctx->K == 32 ? 16 : (ctx->K == 16 ? 8 : 4);
-    void (*kern)(FwdParams) = nullptr;
-    if (regs == 16) kern = keep ? fwd32_kernel<8, 16, true> : fwd32_kernel<8, 16, false>;
-    if (regs == 8) kern = keep ? fwd32_kernel<8, 8, true> : fwd32_kernel<8, 8, false>;
-    if (regs == 4) kern = keep ? fwd32_kernel<8, 4, true> : fwd32_kernel<8, 4, false>;
+    void (*kern)(FwdParams) = select_fwd_kernel(cfg.bit_depth, cfg.block_size, ctx->K, ctx->coeffs != nullptr);
+    if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
     // Persistent grid: exactly as many workgroups as can be resident at once,
     // so no workgroup waits for another to drain before it starts its loop.
     int resident = 0;
@@ -677,6 +555,11 @@ vca_status vca_features(vca_ctx* ctx, int64_t first, int32_t count, vca_frame_fe
   if (first < ctx->submitted - cap) return fail(ctx, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(ctx->device);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->cfg.flags & VCA_F_VALIDATE) {
+    int32_t bad = 0;
+    HIP_TRY(ctx, hipMemcpy(&bad, ctx->err_flag, sizeof(bad), hipMemcpyDeviceToHost));
+    if (bad) return fail(ctx, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
+  }
   int64_t done = 0;
   while (done < count) {
     const int64_t slot = (first + done) % cap;

@@ -1,0 +1,329 @@
+// vca_tile.h -- the 32 x 32 MFMA tile of the VCA forward transform (gfx950).
+//
+// A tile is a 32 x 32 region of one plane holding (32/w)^2 blocks of w x w
+// (w in {8, 16, 32}).  One wavefront transforms one tile:
+//   * lane (r + 32 g) loads row r, samples 16g..16g+15 of the tile;
+//   * horizontal pass T = X' Cd^T on v_mfma_i32_32x32x32_i8, Cd the
+//     block-diagonal matrix diag(C_w, ..., C_w); 8-bit: X' = X - 128 as one
+//     int8 byte; 10-bit: X = 256 t + lo, t in [0, 4], two int8 products;
+//   * the accumulator (lane = column k, register j = row
+//     m_j = 8 (j/4) + 4 g + j%4) is already the B-operand layout of the
+//     vertical pass once its 16-bit values are split into int8 bytes;
+//   * vertical pass Y = Cd T on two int8 MFMAs (hi and lo bytes of T);
+//   * per lane, FP64 sums of W |Y| per block row; a butterfly over the
+//     lanes of a block column gives the block energy H; DC is read in place.
+// Transform definition (Section 2 of the paper names the block-DCT features;
+// the integer transform is the H.265 core transform): per block
+//   T = floor((X C^T + 2^(s1-1)) / 2^s1),  s1 = log2 w + B - 9
+//   Y = floor((C T   + 2^(s2-1)) / 2^s2),  s2 = log2 w + 6.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+namespace vca {
+
+constexpr int kTile = 32;           // MFMA tile edge (samples)
+constexpr int kDcOffset = 1 << 14;  // DC removed by the -2^(B-1) sample offset, exact for all w, B
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+// Row of coefficient register j in lane half g.
+constexpr int reg_row(int j, int g) { return 8 * (j / 4) + 4 * g + (j % 4); }
+
+// Register j holds a coefficient inside some block's K x K corner.
+constexpr bool reg_used(int j, int w, int K) {
+  return (reg_row(j, 0) % w) < K || (reg_row(j, 1) % w) < K;
+}
+
+// Register j holds the first row (i % w == 0) of a block for lanes with g = 0.
+constexpr bool reg_block_row0(int j, int w) { return j % 4 == 0 && (8 * (j / 4)) % w == 0; }
+
+// ---------------------------------------------------------------- host side
+// Integer stand-ins for 64*sqrt(2)*cos(pi*t/64), t = 0..32 (H.265 core
+// transform values; t = 32 is the zero of the cosine).
+constexpr int kCosQuarter[33] = {90, 90, 90, 90, 89, 88, 87, 85, 83, 82, 80, 78, 75, 73, 70, 67, 64,
+                                 61, 57, 54, 50, 46, 43, 38, 36, 31, 25, 22, 18, 13, 9,  4,  0};
+
+// Entry (k, n) of the 32-point matrix via the quadrant of the angle k(2n+1).
+inline int mat32(int k, int n) {
+  if (k == 0) return 64;
+  const int t = (k * (2 * n + 1)) & 127;
+  if (t <= 32) return kCosQuarter[t];
+  if (t <= 64) return -kCosQuarter[64 - t];
+  if (t <= 96) return -kCosQuarter[t - 64];
+  return kCosQuarter[128 - t];
+}
+
+// w-point matrix: the 32-point one restricted to every (32/w)-th row.
+inline int matw(int w, int k, int n) { return mat32(k * (kTile / w), n); }
+
+// Entry (a, b) of the 32 x 32 block-diagonal matrix diag(C_w, ..., C_w).
+inline int matd(int w, int a, int b) { return a / w == b / w ? matw(w, a % w, b % w) : 0; }
+
+// Energy weight of coefficient (i, k) of a w x w block (1-based frequencies).
+inline double weight(int w, int i, int k) {
+  const double q = (double)((i + 1) * (k + 1)) / (double)(w * w);
+  return std::exp(std::fabs(q * q - 1.0));
+}
+
+// Per-lane MFMA operands and weights of the tile for block size w and
+// low-pass size K: b1 = stage-1 B operand (16 bytes per lane), a2 = stage-2
+// A operand (16 bytes per lane), wt[j * 64 + lane] = weight of the
+// coefficient in register j of the lane (0 outside the K x K corners and at
+// every DC).
+inline void build_tile_tables(int w, int K, std::vector<int8_t>& b1, std::vector<int8_t>& a2,
+                              std::vector<double>& wt) {
+  b1.assign(64 * 16, 0);
+  a2.assign(64 * 16, 0);
+  wt.assign(16 * 64, 0.0);
+  for (int lane = 0; lane < 64; lane++) {
+    const int c = lane & 31, g = lane >> 5;
+    for (int j = 0; j < 16; j++) {
+      // stage 1: B[n][k] = Cd[k][n], n = 16 g + j (the samples each lane loads)
+      b1[lane * 16 + j] = (int8_t)matd(w, c, 16 * g + j);
+      // stage 2: A[i][m] = Cd[i][m], m = the row held by accumulator register j
+      const int m = reg_row(j, g);
+      a2[lane * 16 + j] = (int8_t)matd(w, c, m);
+      // weight of output (i, k) = (m, c) held by register j of lane (c + 32 g)
+      const int ii = m % w, kk = c % w;
+      wt[j * 64 + lane] = (ii < K && kk < K && !(ii == 0 && kk == 0)) ? weight(w, ii, kk) : 0.0;
+    }
+  }
+}
+
+// Division by an invariant d (Granlund-Montgomery, round-up multiplier):
+// n / d = (umulhi(n, m) + n) >> l for 0 <= n < 2^31, with l = ceil(log2 d)
+// and m = floor(2^32 (2^l - d) / d) + 1.  Keeps tile-id decoding scalar.
+struct FastDiv {
+  uint32_t m;
+  uint32_t l;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) l++;
+  const uint64_t m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return FastDiv{(uint32_t)m, l};
+}
+
+// -------------------------------------------------------------- device side
+__device__ inline uint32_t fastdiv(uint32_t n, FastDiv d) { return (__umulhi(n, d.m) + n) >> d.l; }
+
+__device__ inline uint32_t perm_b32(uint32_t hi_src, uint32_t lo_src, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi_src, lo_src, sel);
+}
+
+// Wave-uniform description of one tile.
+struct TileWork {
+  const uint8_t* base;  // row 0, column 0 of the tile
+  int32_t pitch;        // bytes between rows (< 2^23)
+  int32_t vr, vc;       // complete blocks of the tile inside the plane's block grid
+  int32_t out0;         // output index of the tile's block (0, 0)
+  int32_t out_row;      // output index step between block rows
+};
+
+// Raw samples of one lane: 8-bit uses a (16 samples), 10-bit a and b
+// (8 uint16 samples each).
+struct TileData {
+  v4i a;
+  v4i b;
+};
+
+// Per-wavefront constants.
+template <int kW, int kK>
+struct TileConsts {
+  v4i b1;             // stage-1 B operand
+  v4i a2;             // stage-2 A operand
+  double wt[16];      // weights (only registers in use are loaded)
+  int row0_fix;       // +128 on each block's first coefficient row (lanes g = 0)
+
+  __device__ void load(const v4i* tab_b1, const v4i* tab_a2, const double* tab_w, int lane) {
+    b1 = tab_b1[lane];
+    a2 = tab_a2[lane];
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (reg_used(j, kW, kK)) wt[j] = tab_w[j * 64 + lane];
+    row0_fix = lane < 32 ? 128 : 0;
+  }
+};
+
+// Loads a lane's samples.  Rows and 16-byte pieces outside the tile's valid
+// blocks are redirected to row 0 / the lane's first valid piece: a 16-byte
+// piece that starts inside the block grid lies inside the row's pitch (a
+// multiple of 16 bytes), so every access stays in bounds; the redirected
+// data only feeds blocks that are discarded.
+template <int kBits, int kW>
+__device__ __forceinline__ TileData load_tile(const TileWork& t, int lane) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kBpt = kTile / kW;
+  const int r = lane & 31, g = lane >> 5;
+  TileData d;
+  if (t.vr == kBpt && t.vc == kBpt) {
+    const uint32_t off = __umul24((uint32_t)r, (uint32_t)t.pitch) + 16 * g * kBps;
+    d.a = *reinterpret_cast<const v4i*>(t.base + off);
+    if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(t.base + off + 16);
+  } else {
+    const int rows = t.vr * kW, cols = t.vc * kW;
+    const uint32_t roff = __umul24((uint32_t)(r < rows ? r : 0), (uint32_t)t.pitch);
+    const int c0 = 16 * g < cols ? 16 * g : 0;
+    d.a = *reinterpret_cast<const v4i*>(t.base + roff + c0 * kBps);
+    if (kBits != 8) {
+      const int c1 = 16 * g + 8 < cols ? 16 * g + 8 : c0;
+      d.b = *reinterpret_cast<const v4i*>(t.base + roff + c1 * kBps);
+    }
+  }
+  return d;
+}
+
+// Outputs of the forward tile.
+struct TileOut {
+  double* blk_h;      // block energies
+  int32_t* blk_dc;    // block DC coefficients
+  int16_t* coeffs;    // optional K x K coefficients per block
+  int32_t* err_flag;  // set to 1 when a 10-bit sample exceeds 1023 (validation on)
+  int32_t validate;
+};
+
+// Transform, energies and DC of one tile.  Exact split of the
+// horizontal-pass result T (-2^14 <= T < 2^15 for every w and B):
+//   T = 256 T_hi + u,  T_hi = T >> 8 in [-64, 127],  u = T & 255,
+// C T = 256 C T_hi + C (u - 128) + 128 C 1, the last term being 128 * 64 w
+// on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
+// scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
+// accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
+template <int kBits, int kW, int kK, bool kKeep>
+__device__ __forceinline__ void fwd_tile(const TileOut& o, const TileConsts<kW, kK>& tc,
+                                         const TileData& d, const TileWork& t, int lane) {
+  constexpr int kS1 = ilog2c(kW) + kBits - 9;
+  constexpr int kS2 = ilog2c(kW) + 6;
+  constexpr int kBpt = kTile / kW;
+  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;   // 8-bit samples are offset by -128
+  const int g = lane >> 5, r = lane & 31;
+  v16i c1, c2;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    c1[j] = 1 << (kS1 - 1);            // rounding of the horizontal pass
+    c2[j] = 1 << (kS2 - 9);            // 256 * 2^(s2-9) = 2^(s2-1)
+  }
+  const v16i zero = {};
+
+  v16i d1;
+  if (kBits == 8) {
+    const v4i x = d.a ^ (int)0x80808080;   // x - 128 as int8
+    d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, tc.b1, c1, 0, 0, 0);
+  } else {
+    // 10-bit samples need no offset: x = 256 t + lo with lo the sign-extended
+    // low byte and t = (x + 128) >> 8 in [0, 4], both int8.  The raw
+    // horizontal-pass result stays within [-2^14, 2^15) (its first column
+    // is at most 32 * 1023), so the T >> 8 byte below still fits int8, and
+    // DC needs no correction.  A pair of samples x0 | x1 << 16 gives t0 and
+    // t1 in bytes 0 and 2 of ((pair + 0x00800080) >> 8).
+    v4i lo, hi;
+    uint32_t tv[8];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      tv[q] = ((uint32_t)d.a[q] + 0x00800080u) >> 8;
+      tv[4 + q] = ((uint32_t)d.b[q] + 0x00800080u) >> 8;
+    }
+    lo[0] = (int)perm_b32((uint32_t)d.a[1], (uint32_t)d.a[0], 0x06040200u);
+    lo[1] = (int)perm_b32((uint32_t)d.a[3], (uint32_t)d.a[2], 0x06040200u);
+    lo[2] = (int)perm_b32((uint32_t)d.b[1], (uint32_t)d.b[0], 0x06040200u);
+    lo[3] = (int)perm_b32((uint32_t)d.b[3], (uint32_t)d.b[2], 0x06040200u);
+#pragma unroll
+    for (int q = 0; q < 4; q++) hi[q] = (int)perm_b32(tv[2 * q + 1], tv[2 * q], 0x06040200u);
+    if (o.validate) {
+      uint32_t any = 0;
+#pragma unroll
+      for (int q = 0; q < 4; q++) any |= (uint32_t)d.a[q] | (uint32_t)d.b[q];
+      if (any & 0xFC00FC00u) *o.err_flag = 1;
+    }
+    const v16i dh1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, tc.b1, zero, 0, 0, 0);
+    const v16i dl1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, tc.b1, c1, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 16; j++) d1[j] = (int)((uint32_t)dh1[j] * 256u + (uint32_t)dl1[j]);
+  }
+
+  v4i tlo, thi;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const uint32_t s0 = (uint32_t)(d1[4 * q + 0] >> kS1);
+    const uint32_t s1 = (uint32_t)(d1[4 * q + 1] >> kS1);
+    const uint32_t s2 = (uint32_t)(d1[4 * q + 2] >> kS1);
+    const uint32_t s3 = (uint32_t)(d1[4 * q + 3] >> kS1);
+    const uint32_t p01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
+    const uint32_t p23 = perm_b32(s3, s2, 0x05010400u);
+    tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
+    thi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
+  }
+  const v16i dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, thi, c2, 0, 0, 0);
+  const v16i dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, tlo, zero, 0, 0, 0);
+
+  // FP64 energy per block row (two partial sums when the tile is one block).
+  constexpr int kAcc = kBpt == 1 ? 2 : kBpt;
+  double h[kAcc];
+  int dcv[kBpt];
+#pragma unroll
+  for (int a = 0; a < kAcc; a++) h[a] = 0.0;
+#pragma unroll
+  for (int b = 0; b < kBpt; b++) dcv[b] = 0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    if (!reg_used(j, kW, kK)) continue;
+    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
+    const int br = (8 * (j / 4)) / kW;
+    if (reg_block_row0(j, kW)) {
+      yv += tc.row0_fix;
+      dcv[br] = yv;
+    }
+    const int a = kBpt == 1 ? (j & 1) : br;
+    h[a] = fma(tc.wt[j], fabs((double)yv), h[a]);
+    if (kKeep) {
+      const int i = reg_row(j, g);
+      const int ii = i % kW, kk = r % kW, bc = r / kW;
+      if (ii < kK && kk < kK && br < t.vr && bc < t.vc) {
+        const int out = yv + ((ii == 0 && kk == 0) ? kDcAdd : 0);
+        o.coeffs[((int64_t)(t.out0 + br * t.out_row + bc) * kK + ii) * kK + kk] = (int16_t)out;
+      }
+    }
+  }
+  double hb[kBpt];
+  if (kBpt == 1) {
+    hb[0] = h[0] + h[1];
+  } else {
+#pragma unroll
+    for (int b = 0; b < kBpt; b++) hb[b] = h[b];
+  }
+  // Butterfly over the lanes of one block column: offsets 1 .. w/2 inside the
+  // 32-lane half, then 32 across the halves.
+#pragma unroll
+  for (int off = 1; off < kW; off <<= 1) {
+#pragma unroll
+    for (int b = 0; b < kBpt; b++) hb[b] += __shfl_xor(hb[b], off);
+  }
+#pragma unroll
+  for (int b = 0; b < kBpt; b++) hb[b] += __shfl_xor(hb[b], 32);
+  // Lane bc * w (g = 0) holds the DC of block (br, bc) in dcv[br].
+  if (g == 0 && (r % kW) == 0) {
+    const int bc = r / kW;
+    if (bc < t.vc) {
+#pragma unroll
+      for (int b = 0; b < kBpt; b++) {
+        if (b < t.vr) {
+          const int idx = t.out0 + b * t.out_row + bc;
+          o.blk_h[idx] = hb[b];
+          o.blk_dc[idx] = dcv[b] + kDcAdd;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace vca

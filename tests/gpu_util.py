@@ -8,8 +8,15 @@ FEATURE_RTOL = 1e-5   # relative bound on E, h and L against the FP64 oracle
 
 
 def to_device(video, device="cuda"):
+    """Uploads planes; 10-bit samples travel as int16 (same bytes as uint16)."""
     import torch
-    return tuple(torch.from_numpy(np.ascontiguousarray(p)).to(device) for p in (video.y, video.u, video.v))
+    out = []
+    for p in (video.y, video.u, video.v):
+        a = np.ascontiguousarray(p)
+        if a.dtype == np.uint16:
+            a = a.view(np.int16)
+        out.append(torch.from_numpy(a).to(device))
+    return tuple(out)
 
 
 def assert_features_close(gpu: np.ndarray, ref: np.ndarray, rtol: float = FEATURE_RTOL):

@@ -1,0 +1,143 @@
+"""GPU parity for every block size, low-pass size and bit depth, partial
+edge tiles, and the 10-bit precision-stress content (hi/lo split worst
+cases), all against the CPU oracle through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import assert_features_close, print_case, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2304_12384_amd as vca_mod
+    return vca_mod
+
+
+@pytest.fixture(scope="module")
+def patches():
+    return synth.patches_video()
+
+
+def check_bit_exact(vca, video, w, k, max_batch=None):
+    n = video.n_frames
+    an = vca.Analyzer(video.width, video.height, bit_depth=video.bit_depth, block_size=w,
+                      lowpass_k=k, keep_coeffs=True, max_batch=max_batch or n)
+    y, u, v = to_device(video)
+    an.submit(y, u, v)
+    coeffs = [an.block_coeffs(t) for t in range(n)]
+    stats = [an.block_stats(t) for t in range(n)]
+    feats = an.features(0, n)
+    an.close()
+    cfg = oracle.Config(video.width, video.height, video.bit_depth, w, k)
+    ref = oracle.analyze(cfg, video.y, video.u, video.v, threads=8, want_blocks=True,
+                         want_coeffs=True)
+    for t in range(n):
+        bad = coeffs[t].astype(np.int32) != ref.coeffs[t]
+        assert not bad.any(), f"frame {t}: {int(bad.sum())} coefficients differ (first block " \
+                              f"{np.argwhere(bad)[0]})"
+        assert (stats[t][1] == ref.block_dc[t]).all()
+        np.testing.assert_allclose(stats[t][0], ref.block_h[t], rtol=1e-12, atol=0)
+    assert_features_close(feats, ref.features)
+
+
+@pytest.mark.parametrize("w", [16, 8])
+@pytest.mark.parametrize("kdiv", [1, 2, 4])
+def test_block_sizes_720p(vca, patches, w, kdiv):
+    k = w // kdiv
+    print_case(test="block_sizes_720p", w=w, k=k)
+    check_bit_exact(vca, patches.frames(0, 4), w, 0 if kdiv == 1 else k)
+
+
+@pytest.mark.parametrize("w", [32, 16])
+@pytest.mark.parametrize("res", [(1920, 1080), (3840, 2160)])
+def test_10bit_stress_bit_exact(vca, w, res):
+    width, height = res
+    print_case(test="10bit_stress", w=w, width=width, height=height)
+    video = synth.stress_video(width, height, 2, cell=w, stream=w)
+    check_bit_exact(vca, video, w, 0)
+
+
+@pytest.mark.parametrize("w,k", [(32, 16), (32, 8), (16, 8), (8, 4), (8, 2)])
+def test_10bit_lowpass_bit_exact(vca, w, k):
+    print_case(test="10bit_lowpass", w=w, k=k)
+    video = synth.stress_video(1280, 720, 2, cell=w, stream=100 + w + k)
+    check_bit_exact(vca, video, w, k)
+
+
+@pytest.mark.parametrize("bits", [8, 10])
+@pytest.mark.parametrize("w", [32, 16, 8])
+@pytest.mark.parametrize("size", [(104, 72), (1000, 568), (648, 488)])
+def test_partial_edge_tiles(vca, bits, w, size):
+    """Block grids that end inside a 32 x 32 tile (odd block counts, ragged
+    planes) with padded pitches; margins hold out-of-range values."""
+    width, height = size
+    if width // 2 < w or height // 2 < w:
+        pytest.skip("plane smaller than a block")
+    print_case(test="partial_tiles", bits=bits, w=w, width=width, height=height)
+    rng = np.random.default_rng(width * 7 + height + w + bits)
+    n = 2
+    maxv = (1 << bits) - 1
+    dt = np.uint8 if bits == 8 else np.uint16
+    bps = 1 if bits == 8 else 2
+    pitch = ((width * bps + 15) // 16 * 16 + 16) // bps
+    cpitch = ((width // 2 * bps + 15) // 16 * 16 + 16) // bps
+    y = rng.integers(0, maxv + 1, size=(n, height, pitch)).astype(dt)
+    u = rng.integers(0, maxv + 1, size=(n, height // 2, cpitch)).astype(dt)
+    v = rng.integers(0, maxv + 1, size=(n, height // 2, cpitch)).astype(dt)
+    crop = synth.Video(np.ascontiguousarray(y[:, :, :width]), np.ascontiguousarray(u[:, :, :width // 2]),
+                       np.ascontiguousarray(v[:, :, :width // 2]), bits)
+    dev = [torch.from_numpy(a.view(np.int16) if bits == 10 else a).cuda() for a in (y, u, v)]
+    for k in (0, w // 2):
+        an = vca.Analyzer(width, height, bit_depth=bits, block_size=w, lowpass_k=k,
+                          keep_coeffs=True, max_batch=n)
+        an.submit(dev[0][:, :, :width], dev[1][:, :, :width // 2], dev[2][:, :, :width // 2])
+        co = [an.block_coeffs(t) for t in range(n)]
+        f = an.features(0, n)
+        an.close()
+        cfg = oracle.Config(width, height, bits, w, k)
+        ref = oracle.analyze(cfg, crop.y, crop.u, crop.v, want_coeffs=True)
+        for t in range(n):
+            assert (co[t].astype(np.int32) == ref.coeffs[t]).all(), f"k={k} frame {t}"
+        assert_features_close(f, ref.features)
+
+
+def test_10bit_scene_features(vca):
+    """10-bit moving scenes (features, h across a cut) in one chunked call."""
+    print_case(test="10bit_scene")
+    sv = synth.scene_video(1920, 1080, 12, scene_len=6, bit_depth=10, stream=3)
+    video = sv.frames()
+    an = vca.Analyzer(1920, 1080, bit_depth=10, block_size=16, max_batch=5)
+    an.submit(*to_device(video))
+    f = an.features(0, 12)
+    an.close()
+    ref = oracle.analyze(oracle.Config(1920, 1080, 10, 16), video.y, video.u, video.v,
+                         threads=8).features
+    assert_features_close(f, ref)
+
+
+def test_10bit_validation(vca):
+    from paper_2304_12384_amd import VcaError
+    print_case(test="10bit_validation")
+    rng = np.random.default_rng(9)
+    width, height = 208, 136            # w=32: luma grid 192 x 128, margins outside
+    y = rng.integers(0, 1024, size=(2, height, width)).astype(np.uint16)
+    u = rng.integers(0, 1024, size=(2, height // 2, width // 2)).astype(np.uint16)
+    y[1, 130, 200] = 4000               # outside the block grid: ignored
+    dev = [torch.from_numpy(a.view(np.int16)).cuda() for a in (y, u, u.copy())]
+    an = vca.Analyzer(width, height, bit_depth=10, block_size=32, validate=True)
+    an.submit(*dev)
+    assert an.features(0, 2).shape == (2, 7)
+    y[1, 40, 40] = 1024                 # inside a block: rejected
+    dev[0] = torch.from_numpy(y.view(np.int16)).cuda()
+    an.submit(*dev)
+    with pytest.raises(VcaError):
+        an.features(2, 2)
+    an.close()
