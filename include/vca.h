@@ -143,6 +143,23 @@ vca_status vca_block_stats(vca_ctx* ctx, int64_t frame, double* h_host, int32_t*
  * afterwards.  VCA_ERR_STATE if the context was opened without the flag. */
 vca_status vca_get_timing(vca_ctx* ctx, vca_timing* out, int32_t reset);
 
+/* Autotuner of the launch shape: times the forward kernel on the given
+ * frames (at most max_batch of them) for every candidate -- tiles in flight
+ * per wavefront 1..3 times workgroups per compute unit 1..(as many as fit) --
+ * with `reps` timed launches each, and keeps the fastest for this context.
+ * The choice is also cached for the process (and in the text file named by
+ * the environment variable VCA_TUNE_CACHE, if set) under the key (device,
+ * bit depth, w, K, resolution); later vca_open calls with the same key use
+ * it.  Features, h state and frame numbering are unchanged; the per-block
+ * exports of the previous call are overwritten.  Not available with
+ * VCA_F_KEEP_COEFFS (VCA_ERR_STATE). */
+vca_status vca_tune(vca_ctx* ctx, const vca_frames* frames, int32_t n_frames, int32_t reps);
+
+/* Launch shape in use: tiles in flight per wavefront (0: untuned default),
+ * workgroups per compute unit (0: as many as fit), and the tuned kernel time
+ * in ms.  Any output pointer may be NULL. */
+vca_status vca_tuned_launch(const vca_ctx* ctx, int32_t* depth, int32_t* groups_per_cu, double* ms);
+
 /* Forgets the previous frame: the next analysed frame gets h = 0.  Frame
  * numbering continues. */
 vca_status vca_reset(vca_ctx* ctx);
@@ -152,6 +169,59 @@ int64_t vca_frames_submitted(const vca_ctx* ctx);
 
 /* Waits for outstanding work and frees the context.  NULL-safe. */
 void vca_close(vca_ctx* ctx);
+
+/* ------------------------------------------------------------ batched form
+ * Many independent streams -- each with its own resolution, block size,
+ * low-pass size, bit depth and frame count -- analysed by ONE persistent
+ * kernel launch over all their tiles plus one reduction launch, both
+ * captured into a hipGraph on the first call with a given frame-count
+ * signature and replayed afterwards (only the per-stream descriptor tables
+ * are uploaded per call).  Per stream the results are identical to a
+ * vca_ctx opened with the same configuration and fed the same frames. */
+typedef struct vca_batch vca_batch; /* opaque; owned by the library */
+
+/* Opens a batch of n_streams streams (cfgs[s] configures stream s; all on
+ * the same device; VCA_F_KEEP_COEFFS is not supported).  max_batch = 0 means
+ * 300 frames per stream and launch, feature_capacity = 0 means 4096. */
+vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_stream,
+                          vca_batch** out);
+
+/* Enqueues frames[s] (n_frames[s] >= 0 frames) for every stream s; returns
+ * without waiting.  Streams whose count exceeds their max_batch are
+ * processed in several rounds.  Frame buffers must stay valid until the
+ * stream's work is done (vca_batch_features waits). */
+vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames);
+
+/* Features of frames [first, first + count) of stream `stream`; waits. */
+vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32_t count,
+                              vca_frame_features* out_host);
+
+/* Autotuner of the batched launch shape (as vca_tune, over the first round
+ * of the given frames of every stream); cached under the batch's stream
+ * list.  Features and h state are unchanged. */
+vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames,
+                          int32_t reps);
+
+/* Launch shape of the batch (see vca_tuned_launch). */
+vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* groups_per_cu,
+                                  double* ms);
+
+/* Device time of the batch's launches (both kernels), measured with HIP
+ * events on its stream when any stream was opened with VCA_F_TIMING. */
+vca_status vca_batch_timing(vca_batch* b, double* total_ms, int64_t* launches, int64_t* frames,
+                            int32_t reset);
+
+/* Forgets the previous frame of one stream (stream >= 0) or of all (-1). */
+vca_status vca_reset_batch(vca_batch* b, int32_t stream);
+
+/* Frames submitted so far to a stream (-1 for a bad argument). */
+int64_t vca_batch_submitted(const vca_batch* b, int32_t stream);
+
+/* Message of the batch's last failure (owned by the batch). */
+const char* vca_batch_last_error(const vca_batch* b);
+
+/* Waits for outstanding work and frees the batch.  NULL-safe. */
+void vca_close_batch(vca_batch* b);
 
 /* Static string naming a status code. */
 const char* vca_status_str(vca_status s);

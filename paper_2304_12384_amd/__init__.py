@@ -6,6 +6,6 @@ Adaptive Video Streaming", Section 2, computed by hand-written HIP kernels
 behind the C ABI in include/vca.h.
 """
 from ._lib import VcaError, EXPORTS, LIB_PATH
-from .analyzer import Analyzer, FEATURE_NAMES, block_counts
+from .analyzer import Analyzer, Batch, FEATURE_NAMES, block_counts
 
-__all__ = ["Analyzer", "FEATURE_NAMES", "block_counts", "VcaError", "EXPORTS", "LIB_PATH"]
+__all__ = ["Analyzer", "Batch", "FEATURE_NAMES", "block_counts", "VcaError", "EXPORTS", "LIB_PATH"]

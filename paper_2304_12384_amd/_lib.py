@@ -25,8 +25,11 @@ VCA_F_TIMING = 0x4
 # Every symbol include/vca.h declares.
 EXPORTS = (
     "vca_block_counts", "vca_open", "vca_analyze_frames", "vca_features", "vca_block_coeffs",
-    "vca_block_stats", "vca_get_timing", "vca_reset", "vca_frames_submitted", "vca_close", "vca_status_str",
-    "vca_last_error",
+    "vca_block_stats", "vca_get_timing", "vca_tune", "vca_tuned_launch", "vca_reset",
+    "vca_frames_submitted", "vca_close", "vca_status_str", "vca_last_error",
+    "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_tune_batch",
+    "vca_batch_tuned_launch", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
+    "vca_batch_last_error", "vca_close_batch",
 )
 
 
@@ -85,7 +88,19 @@ def lib() -> ctypes.CDLL:
             "vca_block_coeffs": (St, [P, ctypes.c_int64, P, ctypes.c_size_t]),
             "vca_block_stats": (St, [P, ctypes.c_int64, P, P, ctypes.c_size_t]),
             "vca_get_timing": (St, [P, ctypes.POINTER(VcaTiming), ctypes.c_int32]),
+            "vca_tune": (St, [P, ctypes.POINTER(VcaFrames), ctypes.c_int32, ctypes.c_int32]),
+            "vca_tuned_launch": (St, [P, P, P, P]),
             "vca_reset": (St, [P]),
+            "vca_open_batch": (St, [ctypes.POINTER(VcaConfig), ctypes.c_int32, P, ctypes.POINTER(P)]),
+            "vca_analyze_batch": (St, [P, ctypes.POINTER(VcaFrames), P]),
+            "vca_batch_features": (St, [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P]),
+            "vca_tune_batch": (St, [P, ctypes.POINTER(VcaFrames), P, ctypes.c_int32]),
+            "vca_batch_tuned_launch": (St, [P, P, P, P]),
+            "vca_batch_timing": (St, [P, P, P, P, ctypes.c_int32]),
+            "vca_reset_batch": (St, [P, ctypes.c_int32]),
+            "vca_batch_submitted": (ctypes.c_int64, [P, ctypes.c_int32]),
+            "vca_batch_last_error": (ctypes.c_char_p, [P]),
+            "vca_close_batch": (None, [P]),
             "vca_frames_submitted": (ctypes.c_int64, [P]),
             "vca_close": (None, [P]),
             "vca_status_str": (ctypes.c_char_p, [ctypes.c_int]),
@@ -103,7 +118,11 @@ def status_str(status: int) -> str:
     return lib().vca_status_str(status).decode()
 
 
-def check(status: int, what: str, ctx=None) -> None:
+def check(status: int, what: str, ctx=None, batch=None) -> None:
     if status != VCA_OK:
-        detail = lib().vca_last_error(ctx).decode() if ctx else ""
+        detail = ""
+        if ctx:
+            detail = lib().vca_last_error(ctx).decode()
+        elif batch:
+            detail = lib().vca_batch_last_error(batch).decode()
         raise VcaError(status, what, detail)

@@ -156,3 +156,140 @@ class Analyzer:
 
     def reset(self) -> None:
         check(_lib.lib().vca_reset(self._ctx), "vca_reset", self._ctx)
+
+    def tune(self, y: torch.Tensor, u: torch.Tensor, v: torch.Tensor, reps: int = 3) -> dict:
+        """Autotunes the launch shape on these frames (see vca_tune)."""
+        fr = _frames(self, y, u, v)
+        check(_lib.lib().vca_tune(self._ctx, ctypes.byref(fr), y.shape[0], reps), "vca_tune", self._ctx)
+        return self.tuned_launch()
+
+    def tuned_launch(self) -> dict:
+        d, g, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        check(_lib.lib().vca_tuned_launch(self._ctx, ctypes.byref(d), ctypes.byref(g), ctypes.byref(ms)),
+              "vca_tuned_launch", self._ctx)
+        return {"depth": d.value, "groups_per_cu": g.value, "ms": ms.value}
+
+
+def _frames(owner, y, u, v) -> VcaFrames:
+    """Validated frame descriptor of device planes for a stream of `owner`'s
+    geometry (width, height, bit_depth attributes)."""
+    bps = 1 if owner.bit_depth == 8 else 2
+    y, py, fy = _plane_geometry(y, bps)
+    u, pu, fu = _plane_geometry(u, bps)
+    v, pv, fv = _plane_geometry(v, bps)
+    if pu != pv or fu != fv:
+        raise ValueError("U and V must share pitch and frame stride")
+    n = y.shape[0]
+    if u.shape[0] != n or v.shape[0] != n:
+        raise ValueError("planes hold different frame counts")
+    if y.shape[1:] != (owner.height, owner.width):
+        raise ValueError(f"luma shape {tuple(y.shape[1:])} != {(owner.height, owner.width)}")
+    if u.shape[1:] != (owner.height // 2, owner.width // 2) or v.shape[1:] != u.shape[1:]:
+        raise ValueError("chroma planes must be [n, H/2, W/2]")
+    return VcaFrames(y.data_ptr(), u.data_ptr(), v.data_ptr(), py, pu, fy, fu, 1)
+
+
+class _StreamGeom:
+    def __init__(self, width, height, bit_depth):
+        self.width, self.height, self.bit_depth = width, height, bit_depth
+
+
+class Batch:
+    """Wraps one ``vca_batch``: many streams analysed by one persistent,
+    graph-replayed launch.
+
+    >>> b = Batch([dict(width=1920, height=1080, block_size=16), dict(width=640, height=360)])
+    >>> b.submit([(y0, u0, v0), (y1, u1, v1)])
+    >>> b.features(0, 0, n0)
+    """
+
+    def __init__(self, streams: list, *, device: int | None = None, timing: bool = False,
+                 stream: torch.cuda.Stream | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        n = len(streams)
+        cfgs = (VcaConfig * n)()
+        self.geoms = []
+        for s, d in enumerate(streams):
+            flags = (_lib.VCA_F_TIMING if timing else 0) | (_lib.VCA_F_VALIDATE if d.get("validate") else 0)
+            cfgs[s] = _config(d["width"], d["height"], d.get("bit_depth", 8), d.get("block_size", 32),
+                              d.get("lowpass_k", 0), device, flags, d.get("max_batch", 0),
+                              d.get("feature_capacity", 0))
+            self.geoms.append(_StreamGeom(d["width"], d["height"], d.get("bit_depth", 8)))
+        self.n = n
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._b = ctypes.c_void_p()
+        check(_lib.lib().vca_open_batch(cfgs, n, ctypes.c_void_p(self.stream.cuda_stream),
+                                        ctypes.byref(self._b)), "vca_open_batch")
+        self._keep = []
+
+    def close(self) -> None:
+        if self._b:
+            _lib.lib().vca_close_batch(self._b)
+            self._b = ctypes.c_void_p()
+        self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _descr(self, frames):
+        if len(frames) != self.n:
+            raise ValueError(f"expected {self.n} frame sets")
+        fr = (VcaFrames * self.n)()
+        counts = (ctypes.c_int32 * self.n)()
+        keep = []
+        for s, f in enumerate(frames):
+            if f is None:
+                fr[s] = VcaFrames(None, None, None, 0, 0, 0, 0, 1)
+                counts[s] = 0
+                continue
+            y, u, v = f
+            fr[s] = _frames(self.geoms[s], y, u, v)
+            counts[s] = y.shape[0] if y.dim() == 3 else 1
+            keep += [y, u, v]
+        return fr, counts, keep
+
+    def submitted(self, s: int) -> int:
+        return int(_lib.lib().vca_batch_submitted(self._b, s))
+
+    def submit(self, frames: list) -> list:
+        """frames[s] = (y, u, v) device planes of stream s, or None.  Returns
+        the index of each stream's first submitted frame (asynchronous)."""
+        fr, counts, keep = self._descr(frames)
+        first = [self.submitted(s) for s in range(self.n)]
+        check(_lib.lib().vca_analyze_batch(self._b, fr, counts), "vca_analyze_batch", batch=self._b)
+        self._keep = keep
+        return first
+
+    def features(self, s: int, first: int, count: int) -> np.ndarray:
+        out = np.zeros((count, 7), np.float32)
+        check(_lib.lib().vca_batch_features(self._b, s, first, count,
+                                            out.ctypes.data_as(ctypes.c_void_p)),
+              "vca_batch_features", batch=self._b)
+        return out
+
+    def tune(self, frames: list, reps: int = 3) -> dict:
+        fr, counts, keep = self._descr(frames)
+        check(_lib.lib().vca_tune_batch(self._b, fr, counts, reps), "vca_tune_batch", batch=self._b)
+        return self.tuned_launch()
+
+    def tuned_launch(self) -> dict:
+        d, g, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        check(_lib.lib().vca_batch_tuned_launch(self._b, ctypes.byref(d), ctypes.byref(g),
+                                                ctypes.byref(ms)), "vca_batch_tuned_launch",
+              batch=self._b)
+        return {"depth": d.value, "groups_per_cu": g.value, "ms": ms.value}
+
+    def timing(self, reset: bool = False) -> dict:
+        ms, n, fr = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        check(_lib.lib().vca_batch_timing(self._b, ctypes.byref(ms), ctypes.byref(n),
+                                          ctypes.byref(fr), int(reset)), "vca_batch_timing",
+              batch=self._b)
+        return {"ms": ms.value, "launches": n.value, "frames": fr.value}
+
+    def reset(self, stream: int = -1) -> None:
+        check(_lib.lib().vca_reset_batch(self._b, stream), "vca_reset_batch", batch=self._b)

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "vca.hip")
+SRCS = [os.path.join(HERE, "csrc", n) for n in ("vca.hip", "vca_batch.hip")]
 LIB = os.path.join(HERE, "libvca.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -20,7 +20,7 @@ FLAGS = [
 
 def build(verbose: bool = False, extra=()) -> str:
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, SRC, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *extra, *SRCS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -9,8 +9,9 @@
 //   fwd_kernel     persistent grid over all 32 x 32 tiles of all frames of a
 //                  launch; one wavefront per tile (vca_tile.h) with a
 //                  register ring of tiles in flight; per-block H and DC out.
-//   reduce_kernel  one workgroup per frame: fixed-order FP64 sums of H,
-//                  sqrt(DC) and |H_p - H_{p-1}| into the seven features.
+//   reduce_kernel  one workgroup per frame (vca_reduce.h).
+// Launch shape (ring depth, workgroups per CU) comes from vca_tune's
+// measurements when the context was tuned, else from fixed defaults.
 
 #include <hip/hip_runtime.h>
 
@@ -24,6 +25,8 @@
 #include <vector>
 
 #include "../../include/vca.h"
+#include "vca_host.h"
+#include "vca_reduce.h"
 #include "vca_tile.h"
 
 using namespace vca;
@@ -32,11 +35,7 @@ namespace {
 
 constexpr int kWavesPerGroup = 4;   // wavefronts per workgroup
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
-
-// Tiles each wavefront keeps in flight ahead of the one it transforms.
-#ifndef VCA_PREFETCH_DEPTH
-#define VCA_PREFETCH_DEPTH 2
-#endif
+constexpr int kDefaultDepth = 2;    // tiles in flight per wavefront when untuned
 
 struct FwdParams {
   const uint8_t* plane[3];
@@ -55,20 +54,6 @@ struct FwdParams {
   const v4i* tab_a2;
   const double* tab_w;
   TileOut out;
-};
-
-struct ReduceParams {
-  const double* blk_h;
-  const int32_t* blk_dc;
-  const double* state_in;  // luma H of the frame before frame 0, or null (h = 0)
-  double* state_out;       // receives luma H of the last frame
-  float* ring;             // [capacity][7]
-  int64_t first_frame;     // global index of frame 0 of this launch
-  int64_t capacity;
-  int32_t cnt[3];
-  int32_t per_frame;
-  int32_t n_frames;
-  double inv_norm[3];      // 1 / (C_P w^2)
 };
 
 // Tile `id` of a launch (frame-major, then Y, U, V, then raster order).
@@ -101,12 +86,11 @@ __device__ inline TileWork decode_tile(const FwdParams& p, int id) {
 }
 
 // Persistent forward kernel: each wavefront walks tiles id, id + S, ...
-// (S = all wavefronts of the grid), keeping VCA_PREFETCH_DEPTH tiles in
-// flight in a register ring (the loop body is unrolled over the ring, so no
-// registers move).
-template <int kBits, int kW, int kK, bool kKeep>
+// (S = all wavefronts of the grid), keeping kDepth tiles in flight in a
+// register ring (the loop body is unrolled over the ring, so no registers
+// move).
+template <int kBits, int kW, int kK, bool kKeep, int kDepth>
 __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
-  constexpr int kDepth = VCA_PREFETCH_DEPTH;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   TileConsts<kW, kK> tc;
@@ -135,45 +119,41 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
   }
 }
 
-// One workgroup per frame: fixed-order FP64 sums of H, sqrt(DC) and |dH|.
-__global__ __launch_bounds__(256) void reduce_kernel(ReduceParams p) {
-  __shared__ double red[7][256];
-  const int f = blockIdx.x;
-  const int t = threadIdx.x;
-  const double* H = p.blk_h + (int64_t)f * p.per_frame;
-  const int32_t* DC = p.blk_dc + (int64_t)f * p.per_frame;
-  const double* prev = f > 0 ? H - p.per_frame : p.state_in;
-  double s[7] = {0, 0, 0, 0, 0, 0, 0};   // H_Y H_U H_V L_Y L_U L_V dH
-  const int e0 = p.cnt[0], e1 = p.cnt[0] + p.cnt[1];
-  for (int b = t; b < p.per_frame; b += 256) {
-    const int P = b < e0 ? 0 : (b < e1 ? 1 : 2);
-    const double hb = H[b];
-    s[P] += hb;
-    s[3 + P] += sqrt((double)DC[b]);
-    if (P == 0 && prev) s[6] += fabs(hb - prev[b]);
-  }
-#pragma unroll
-  for (int q = 0; q < 7; q++) red[q][t] = s[q];
-  __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (t < w) {
-#pragma unroll
-      for (int q = 0; q < 7; q++) red[q][t] += red[q][t + w];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    float* o = p.ring + ((p.first_frame + f) % p.capacity) * 7;
-    o[0] = (float)(red[0][0] * p.inv_norm[0]);
-    o[1] = (float)(red[6][0] * p.inv_norm[0]);
-    o[2] = (float)(red[3][0] * p.inv_norm[0]);
-    o[3] = (float)(red[1][0] * p.inv_norm[1]);
-    o[4] = (float)(red[2][0] * p.inv_norm[2]);
-    o[5] = (float)(red[4][0] * p.inv_norm[1]);
-    o[6] = (float)(red[5][0] * p.inv_norm[2]);
-  }
-  if (f == p.n_frames - 1)
-    for (int b = t; b < p.cnt[0]; b += 256) p.state_out[b] = H[b];
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) {
+  reduce_frame(p, blockIdx.x);
+}
+
+// Kernel for (bit depth, w, K, coefficient export, ring depth).  Coefficient
+// export (tests only) always uses depth 1.
+using FwdKernel = void (*)(FwdParams);
+
+template <int B, int W, int K>
+FwdKernel pick_depth(bool keep, int depth) {
+  if (keep) return fwd_kernel<B, W, K, true, 1>;
+  if (depth == 1) return fwd_kernel<B, W, K, false, 1>;
+  if (depth == 3) return fwd_kernel<B, W, K, false, 3>;
+  return fwd_kernel<B, W, K, false, 2>;
+}
+
+template <int B, int W>
+FwdKernel pick_k(int K, bool keep, int depth) {
+  if (K == W) return pick_depth<B, W, W>(keep, depth);
+  if (K == W / 2) return pick_depth<B, W, W / 2>(keep, depth);
+  if (K == W / 4) return pick_depth<B, W, W / 4>(keep, depth);
+  return nullptr;
+}
+
+template <int B>
+FwdKernel pick_w(int w, int K, bool keep, int depth) {
+  if (w == 32) return pick_k<B, 32>(K, keep, depth);
+  if (w == 16) return pick_k<B, 16>(K, keep, depth);
+  if (w == 8) return pick_k<B, 8>(K, keep, depth);
+  return nullptr;
+}
+
+FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, int depth) {
+  return bits == 8 ? pick_w<8>(w, K, keep, depth)
+                   : (bits == 10 ? pick_w<10>(w, K, keep, depth) : nullptr);
 }
 
 }  // namespace
@@ -181,17 +161,11 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceParams p) {
 // =================================================================== host side
 struct vca_ctx {
   vca_config cfg{};
-  int K = 0;
-  int32_t cnt[3] = {0, 0, 0};
-  int32_t nbx[3] = {0, 0, 0};
-  int32_t nby[3] = {0, 0, 0};
-  int32_t ntx[3] = {0, 0, 0};
-  int32_t tcnt[3] = {0, 0, 0};
-  int32_t per_frame = 0;
-  int32_t tiles_per_frame = 0;
+  Geometry geo;
   int device = 0;
   int num_cus = 0;
-  int groups_per_cu = 0;           // 0: as many as fit (VCA_GROUPS_PER_CU overrides)
+  int env_groups_per_cu = 0;       // VCA_GROUPS_PER_CU caps workgroups per CU
+  LaunchChoice tuned;              // set by vca_tune
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // device tables and state
@@ -209,8 +183,6 @@ struct vca_ctx {
   int64_t submitted = 0;
   int64_t last_chunk_first = -1;  // global index of frame 0 of the most recent launch
   int32_t last_chunk_len = 0;
-  int64_t last_call_first = -1;
-  int32_t last_call_len = 0;
   // VCA_F_TIMING: one (start, middle, end) event triple per launch pair
   std::vector<hipEvent_t> ev_pool;
   std::vector<int32_t> ev_frames;
@@ -219,18 +191,6 @@ struct vca_ctx {
 };
 
 namespace {
-
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int now = -1;
-    if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
-  }
-};
 
 vca_status fail(vca_ctx* c, vca_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -247,24 +207,6 @@ vca_status hip_fail(vca_ctx* c, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);   \
   } while (0)
 
-vca_status check_config(const vca_config* cfg) {
-  if (!cfg) return VCA_ERR_INVALID_ARG;
-  if (cfg->struct_size != sizeof(vca_config)) return VCA_ERR_INVALID_ARG;
-  const int w = cfg->block_size;
-  if (w != 8 && w != 16 && w != 32) return VCA_ERR_INVALID_ARG;
-  if (cfg->bit_depth != 8 && cfg->bit_depth != 10) return VCA_ERR_INVALID_ARG;
-  if (cfg->chroma_format != 420) return VCA_ERR_INVALID_ARG;
-  if (cfg->width <= 0 || cfg->height <= 0 || cfg->width % 2 || cfg->height % 2)
-    return VCA_ERR_INVALID_ARG;
-  if (cfg->width / 2 < w || cfg->height / 2 < w) return VCA_ERR_INVALID_ARG;
-  const int k = cfg->lowpass_k;
-  if (k != 0 && k != w && k != w / 2 && k != w / 4) return VCA_ERR_INVALID_ARG;
-  if (cfg->max_batch < 0 || cfg->feature_capacity < 0 || cfg->device < 0)
-    return VCA_ERR_INVALID_ARG;
-  if (cfg->flags & ~(VCA_F_KEEP_COEFFS | VCA_F_VALIDATE | VCA_F_TIMING)) return VCA_ERR_INVALID_ARG;
-  return VCA_OK;
-}
-
 template <typename T>
 vca_status dev_alloc(vca_ctx* c, T** p, size_t count) {
   hipError_t e = hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
@@ -273,32 +215,65 @@ vca_status dev_alloc(vca_ctx* c, T** p, size_t count) {
   return VCA_OK;
 }
 
-// Kernel for (bit depth, w, K, coefficient export).
-using FwdKernel = void (*)(FwdParams);
-
-template <int B, int W, int K>
-FwdKernel pick_keep(bool keep) {
-  return keep ? fwd_kernel<B, W, K, true> : fwd_kernel<B, W, K, false>;
+// Forward-launch parameters for frames [done, done + n) of a call.
+FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done, int32_t n) {
+  const Geometry& g = ctx->geo;
+  FwdParams fp{};
+  const uint8_t* base[3] = {static_cast<const uint8_t*>(fr->y), static_cast<const uint8_t*>(fr->u),
+                            static_cast<const uint8_t*>(fr->v)};
+  const int64_t fs[3] = {fr->fstride_y, fr->fstride_uv, fr->fstride_uv};
+  const int64_t pt[3] = {fr->pitch_y, fr->pitch_uv, fr->pitch_uv};
+  for (int P = 0; P < 3; P++) {
+    fp.plane[P] = base[P] + fs[P] * done;
+    fp.pitch[P] = (int32_t)pt[P];
+    fp.fstride[P] = fs[P];
+    fp.nbx[P] = g.nbx[P];
+    fp.nby[P] = g.nby[P];
+    fp.ntx[P] = g.ntx[P];
+    fp.tcnt[P] = g.tcnt[P];
+    fp.boff[P] = g.boff[P];
+    fp.div_ntx[P] = make_fastdiv((uint32_t)g.ntx[P]);
+  }
+  fp.tiles_per_frame = g.tiles_per_frame;
+  fp.per_frame = g.per_frame;
+  fp.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
+  fp.n_frames = n;
+  fp.tab_b1 = ctx->tab_b1;
+  fp.tab_a2 = ctx->tab_a2;
+  fp.tab_w = ctx->tab_w;
+  fp.out.blk_h = ctx->blk_h;
+  fp.out.blk_dc = ctx->blk_dc;
+  fp.out.coeffs = ctx->coeffs;
+  fp.out.err_flag = ctx->err_flag;
+  fp.out.validate = (ctx->cfg.flags & VCA_F_VALIDATE) && ctx->cfg.bit_depth == 10 ? 1 : 0;
+  return fp;
 }
 
-template <int B, int W>
-FwdKernel pick_k(int K, bool keep) {
-  if (K == W) return pick_keep<B, W, W>(keep);
-  if (K == W / 2) return pick_keep<B, W, W / 2>(keep);
-  if (K == W / 4) return pick_keep<B, W, W / 4>(keep);
-  return nullptr;
+// Enqueues one forward launch with the given ring depth and workgroup cap.
+vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu) {
+  const bool keep = ctx->coeffs != nullptr;
+  FwdKernel kern = select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, depth);
+  if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
+  // Persistent grid: at most as many workgroups as can be resident at once,
+  // so no workgroup waits for another to drain before it starts its loop.
+  int resident = 0;
+  HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0));
+  resident = std::max(1, resident);
+  if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
+  const int64_t waves = (int64_t)fp.n_frames * fp.tiles_per_frame;
+  const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
+  const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);
+  HIP_TRY(ctx, hipGetLastError());
+  return VCA_OK;
 }
 
-template <int B>
-FwdKernel pick_w(int w, int K, bool keep) {
-  if (w == 32) return pick_k<B, 32>(K, keep);
-  if (w == 16) return pick_k<B, 16>(K, keep);
-  if (w == 8) return pick_k<B, 8>(K, keep);
-  return nullptr;
-}
-
-FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep) {
-  return bits == 8 ? pick_w<8>(w, K, keep) : (bits == 10 ? pick_w<10>(w, K, keep) : nullptr);
+std::string tune_key(const vca_ctx* ctx) {
+  char key[160];
+  std::snprintf(key, sizeof(key), "gfx950/cu%d/plain/b%d/w%d/k%d/%dx%d", ctx->num_cus,
+                ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, ctx->cfg.width,
+                ctx->cfg.height);
+  return key;
 }
 
 }  // namespace
@@ -309,10 +284,9 @@ vca_status vca_block_counts(const vca_config* cfg, int32_t counts[3]) {
   if (!counts) return VCA_ERR_INVALID_ARG;
   vca_status s = check_config(cfg);
   if (s != VCA_OK) return s;
-  const int w = cfg->block_size;
-  counts[0] = (cfg->width / w) * (cfg->height / w);
-  counts[1] = (cfg->width / 2 / w) * (cfg->height / 2 / w);
-  counts[2] = counts[1];
+  Geometry g;
+  g.init(*cfg);
+  for (int P = 0; P < 3; P++) counts[P] = g.cnt[P];
   return VCA_OK;
 }
 
@@ -337,7 +311,7 @@ void vca_close(vca_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void* bufs[] = {ctx->tab_b1, ctx->tab_a2, ctx->tab_w, ctx->blk_h,    ctx->blk_dc,
+    void* bufs[] = {ctx->tab_b1, ctx->tab_a2,   ctx->tab_w,    ctx->blk_h,    ctx->blk_dc,
                     ctx->coeffs, ctx->err_flag, ctx->state[0], ctx->state[1], ctx->ring};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
@@ -362,27 +336,11 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   c->cfg = *cfg;
   if (c->cfg.max_batch == 0) c->cfg.max_batch = 256;
   if (c->cfg.feature_capacity == 0) c->cfg.feature_capacity = 65536;
-  const int w0 = cfg->block_size;
-  const int64_t per_frame0 =
-      (int64_t)(cfg->width / w0) * (cfg->height / w0) + 2 * (int64_t)(cfg->width / 2 / w0) * (cfg->height / 2 / w0);
-  if ((int64_t)c->cfg.max_batch * per_frame0 > (int64_t)INT32_MAX / 2) {
+  c->geo.init(*cfg);
+  if ((int64_t)c->cfg.max_batch * c->geo.per_frame > (int64_t)INT32_MAX / 2) {
     delete c;
     return VCA_ERR_INVALID_ARG;   // block ids of one launch must fit int32
   }
-  const int w = cfg->block_size;
-  c->K = cfg->lowpass_k == 0 ? w : cfg->lowpass_k;
-  vca_block_counts(cfg, c->cnt);
-  const int bpt = kTile / w;
-  for (int P = 0; P < 3; P++) {
-    const int pw = P == 0 ? cfg->width : cfg->width / 2;
-    const int ph = P == 0 ? cfg->height : cfg->height / 2;
-    c->nbx[P] = pw / w;
-    c->nby[P] = ph / w;
-    c->ntx[P] = (c->nbx[P] + bpt - 1) / bpt;
-    c->tcnt[P] = c->ntx[P] * ((c->nby[P] + bpt - 1) / bpt);
-  }
-  c->per_frame = c->cnt[0] + c->cnt[1] + c->cnt[2];
-  c->tiles_per_frame = c->tcnt[0] + c->tcnt[1] + c->tcnt[2];
   c->device = cfg->device;
 
   auto bail = [&](vca_status st) {
@@ -393,7 +351,7 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return bail(VCA_ERR_DEVICE);
   c->num_cus = prop.multiProcessorCount;
-  if (const char* e = std::getenv("VCA_GROUPS_PER_CU")) c->groups_per_cu = std::atoi(e);
+  if (const char* e = std::getenv("VCA_GROUPS_PER_CU")) c->env_groups_per_cu = std::atoi(e);
   if (hip_stream) {
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   } else {
@@ -402,27 +360,29 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
     c->own_stream = true;
   }
   const size_t mb = (size_t)c->cfg.max_batch;
+  const int K = c->geo.K;
   if ((s = dev_alloc(c, &c->tab_b1, 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_a2, 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_w, 16 * 64)) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->blk_h, mb * c->per_frame)) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->blk_dc, mb * c->per_frame)) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->state[0], c->cnt[0])) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->state[1], c->cnt[0])) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->blk_h, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->blk_dc, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->state[0], c->geo.cnt[0])) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->state[1], c->geo.cnt[0])) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->ring, (size_t)c->cfg.feature_capacity * 7)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->err_flag, 1)) != VCA_OK) return bail(s);
   if (hipMemset(c->err_flag, 0, sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
   if (cfg->flags & VCA_F_KEEP_COEFFS)
-    if ((s = dev_alloc(c, &c->coeffs, mb * c->per_frame * c->K * c->K)) != VCA_OK) return bail(s);
+    if ((s = dev_alloc(c, &c->coeffs, mb * c->geo.per_frame * K * K)) != VCA_OK) return bail(s);
 
   std::vector<int8_t> b1, a2;
   std::vector<double> wt;
-  build_tile_tables(w, c->K, b1, a2, wt);
+  build_tile_tables(cfg->block_size, K, b1, a2, wt);
   if (hipMemcpy(c->tab_b1, b1.data(), b1.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_a2, a2.data(), a2.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_w, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice) !=
           hipSuccess)
     return bail(VCA_ERR_DEVICE);
+  TuneCache::get().find(tune_key(c), &c->tuned);
   *out = c;
   return VCA_OK;
 }
@@ -438,70 +398,17 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
   if (!fr->on_device) return fail(ctx, VCA_ERR_UNSUPPORTED, "host-resident frames");
   if (n_frames == 0) return VCA_OK;
   const vca_config& cfg = ctx->cfg;
-  const int bps = cfg.bit_depth == 8 ? 1 : 2;
-  if (!fr->y || !fr->u || !fr->v) return fail(ctx, VCA_ERR_INVALID_ARG, "null plane pointer");
-  if (fr->pitch_y < (int64_t)cfg.width * bps || fr->pitch_uv < (int64_t)cfg.width / 2 * bps)
-    return fail(ctx, VCA_ERR_INVALID_ARG, "pitch smaller than a row");
-  if (fr->pitch_y >= (1 << 23) || fr->pitch_uv >= (1 << 23))
-    return fail(ctx, VCA_ERR_INVALID_ARG, "pitch of 8 MiB or more");   // 24-bit lane offsets
-  if (n_frames > 1 && (fr->fstride_y < fr->pitch_y * cfg.height ||
-                       fr->fstride_uv < fr->pitch_uv * (cfg.height / 2)))
-    return fail(ctx, VCA_ERR_INVALID_ARG, "frame stride smaller than a frame");
-  const uintptr_t align = (uintptr_t)fr->y | (uintptr_t)fr->u | (uintptr_t)fr->v |
-                          (uintptr_t)fr->pitch_y | (uintptr_t)fr->pitch_uv |
-                          (uintptr_t)fr->fstride_y | (uintptr_t)fr->fstride_uv;
-  if (align & 15) return fail(ctx, VCA_ERR_INVALID_ARG, "planes, pitches and strides need 16-byte alignment");
+  if (const char* msg = check_frames(cfg, fr, n_frames)) return fail(ctx, VCA_ERR_INVALID_ARG, msg);
   if ((cfg.flags & VCA_F_KEEP_COEFFS) && n_frames > cfg.max_batch)
     return fail(ctx, VCA_ERR_INVALID_ARG, "VCA_F_KEEP_COEFFS: n_frames exceeds max_batch");
 
   DeviceGuard guard(ctx->device);
-  const int w = cfg.block_size;
-  const double ww = (double)w * w;
-  ctx->last_call_first = ctx->submitted;
-  ctx->last_call_len = n_frames;
+  const double ww = (double)cfg.block_size * cfg.block_size;
+  const int depth = ctx->tuned.depth > 0 ? ctx->tuned.depth : kDefaultDepth;
+  const int gpc = ctx->env_groups_per_cu > 0 ? ctx->env_groups_per_cu : ctx->tuned.groups_per_cu;
   for (int32_t done = 0; done < n_frames;) {
     const int32_t n = std::min<int32_t>(cfg.max_batch, n_frames - done);
-    FwdParams fp{};
-    const uint8_t* base[3] = {static_cast<const uint8_t*>(fr->y), static_cast<const uint8_t*>(fr->u),
-                              static_cast<const uint8_t*>(fr->v)};
-    const int64_t fs[3] = {fr->fstride_y, fr->fstride_uv, fr->fstride_uv};
-    const int64_t pt[3] = {fr->pitch_y, fr->pitch_uv, fr->pitch_uv};
-    int32_t boff = 0;
-    for (int P = 0; P < 3; P++) {
-      fp.plane[P] = base[P] + fs[P] * done;
-      fp.pitch[P] = (int32_t)pt[P];
-      fp.fstride[P] = fs[P];
-      fp.nbx[P] = ctx->nbx[P];
-      fp.nby[P] = ctx->nby[P];
-      fp.ntx[P] = ctx->ntx[P];
-      fp.tcnt[P] = ctx->tcnt[P];
-      fp.boff[P] = boff;
-      boff += ctx->cnt[P];
-      fp.div_ntx[P] = make_fastdiv((uint32_t)ctx->ntx[P]);
-    }
-    fp.tiles_per_frame = ctx->tiles_per_frame;
-    fp.per_frame = ctx->per_frame;
-    fp.div_tpf = make_fastdiv((uint32_t)ctx->tiles_per_frame);
-    fp.n_frames = n;
-    fp.tab_b1 = ctx->tab_b1;
-    fp.tab_a2 = ctx->tab_a2;
-    fp.tab_w = ctx->tab_w;
-    fp.out.blk_h = ctx->blk_h;
-    fp.out.blk_dc = ctx->blk_dc;
-    fp.out.coeffs = ctx->coeffs;
-    fp.out.err_flag = ctx->err_flag;
-    fp.out.validate = (cfg.flags & VCA_F_VALIDATE) && cfg.bit_depth == 10 ? 1 : 0;
-    const int64_t waves = (int64_t)n * ctx->tiles_per_frame;
-    const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
-    void (*kern)(FwdParams) = select_fwd_kernel(cfg.bit_depth, cfg.block_size, ctx->K, ctx->coeffs != nullptr);
-    if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
-    // Persistent grid: exactly as many workgroups as can be resident at once,
-    // so no workgroup waits for another to drain before it starts its loop.
-    int resident = 0;
-    HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0));
-    resident = std::max(1, resident);
-    if (ctx->groups_per_cu > 0) resident = std::min(resident, ctx->groups_per_cu);
-    const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
+    const FwdParams fp = make_fwd_params(ctx, fr, done, n);
     hipEvent_t* ev = nullptr;
     if (cfg.flags & VCA_F_TIMING) {
       if (ctx->ev_used + 3 > ctx->ev_pool.size()) {
@@ -516,8 +423,8 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
       ctx->ev_used += 3;
       HIP_TRY(ctx, hipEventRecord(ev[0], ctx->stream));
     }
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);
-    HIP_TRY(ctx, hipGetLastError());
+    vca_status s = launch_fwd(ctx, fp, depth, gpc);
+    if (s != VCA_OK) return s;
     if (ev) HIP_TRY(ctx, hipEventRecord(ev[1], ctx->stream));
 
     ReduceParams rp{};
@@ -529,12 +436,12 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
     rp.first_frame = ctx->submitted;
     rp.capacity = cfg.feature_capacity;
     for (int P = 0; P < 3; P++) {
-      rp.cnt[P] = ctx->cnt[P];
-      rp.inv_norm[P] = 1.0 / ((double)ctx->cnt[P] * ww);
+      rp.cnt[P] = ctx->geo.cnt[P];
+      rp.inv_norm[P] = 1.0 / ((double)ctx->geo.cnt[P] * ww);
     }
-    rp.per_frame = ctx->per_frame;
+    rp.per_frame = ctx->geo.per_frame;
     rp.n_frames = n;
-    hipLaunchKernelGGL(reduce_kernel, dim3(n), dim3(256), 0, ctx->stream, rp);
+    hipLaunchKernelGGL(reduce_kernel, dim3(n), dim3(kReduceThreads), 0, ctx->stream, rp);
     HIP_TRY(ctx, hipGetLastError());
     if (ev) HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
     ctx->cur_state ^= 1;
@@ -544,6 +451,64 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
     ctx->submitted += n;
     done += n;
   }
+  return VCA_OK;
+}
+
+vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_t reps) {
+  if (!ctx || !fr || n_frames <= 0 || reps <= 0)
+    return fail(ctx, VCA_ERR_INVALID_ARG, "bad vca_tune arguments");
+  if (!fr->on_device) return fail(ctx, VCA_ERR_UNSUPPORTED, "host-resident frames");
+  if (const char* msg = check_frames(ctx->cfg, fr, n_frames)) return fail(ctx, VCA_ERR_INVALID_ARG, msg);
+  if (ctx->coeffs) return fail(ctx, VCA_ERR_STATE, "contexts with VCA_F_KEEP_COEFFS are not tuned");
+  DeviceGuard guard(ctx->device);
+  const int32_t n = std::min<int32_t>(n_frames, ctx->cfg.max_batch);
+  const FwdParams fp = make_fwd_params(ctx, fr, 0, n);
+  hipEvent_t a, b;
+  HIP_TRY(ctx, hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(ctx, VCA_ERR_DEVICE, "hipEventCreate");
+  }
+  LaunchChoice best;
+  best.ms = 1e30;
+  vca_status st = VCA_OK;
+  for (int depth = 1; depth <= 3 && st == VCA_OK; depth++) {
+    int resident = 0;
+    FwdKernel kern = select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, depth);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0) != hipSuccess)
+      resident = 1;
+    for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
+      st = launch_fwd(ctx, fp, depth, gpc);   // warm-up
+      if (st != VCA_OK) break;
+      if (hipEventRecord(a, ctx->stream) != hipSuccess) {
+        st = fail(ctx, VCA_ERR_DEVICE, "hipEventRecord");
+        break;
+      }
+      for (int r = 0; r < reps && st == VCA_OK; r++) st = launch_fwd(ctx, fp, depth, gpc);
+      if (st != VCA_OK) break;
+      if (hipEventRecord(b, ctx->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
+        st = fail(ctx, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      ms /= reps;
+      if (ms < best.ms) best = LaunchChoice{depth, gpc, ms};
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (st != VCA_OK) return st;
+  ctx->tuned = best;
+  TuneCache::get().put(tune_key(ctx), best);
+  return VCA_OK;
+}
+
+vca_status vca_tuned_launch(const vca_ctx* ctx, int32_t* depth, int32_t* groups_per_cu, double* ms) {
+  if (!ctx) return VCA_ERR_INVALID_ARG;
+  if (depth) *depth = ctx->tuned.depth;
+  if (groups_per_cu) *groups_per_cu = ctx->tuned.groups_per_cu;
+  if (ms) *ms = ctx->tuned.ms;
   return VCA_OK;
 }
 
@@ -600,7 +565,7 @@ vca_status vca_block_coeffs(vca_ctx* ctx, int64_t frame, int16_t* out, size_t ca
   if (!ctx->coeffs) return fail(ctx, VCA_ERR_STATE, "context opened without VCA_F_KEEP_COEFFS");
   if (frame < ctx->last_chunk_first || frame >= ctx->last_chunk_first + ctx->last_chunk_len)
     return fail(ctx, VCA_ERR_STATE, "frame not in the most recent call");
-  const size_t per = (size_t)ctx->per_frame * ctx->K * ctx->K;
+  const size_t per = (size_t)ctx->geo.per_frame * ctx->geo.K * ctx->geo.K;
   if (capacity < per) return fail(ctx, VCA_ERR_INVALID_ARG, "output buffer too small");
   DeviceGuard guard(ctx->device);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -614,16 +579,15 @@ vca_status vca_block_stats(vca_ctx* ctx, int64_t frame, double* h_out, int32_t* 
   if (!ctx || (!h_out && !dc_out)) return fail(ctx, VCA_ERR_INVALID_ARG, "null argument");
   if (frame < ctx->last_chunk_first || frame >= ctx->last_chunk_first + ctx->last_chunk_len)
     return fail(ctx, VCA_ERR_STATE, "frame not in the most recent launch");
-  if (capacity < (size_t)ctx->per_frame) return fail(ctx, VCA_ERR_INVALID_ARG, "output buffer too small");
+  const int32_t per = ctx->geo.per_frame;
+  if (capacity < (size_t)per) return fail(ctx, VCA_ERR_INVALID_ARG, "output buffer too small");
   DeviceGuard guard(ctx->device);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  const int64_t off = (frame - ctx->last_chunk_first) * ctx->per_frame;
+  const int64_t off = (frame - ctx->last_chunk_first) * per;
   if (h_out)
-    HIP_TRY(ctx, hipMemcpy(h_out, ctx->blk_h + off, ctx->per_frame * sizeof(double),
-                           hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(h_out, ctx->blk_h + off, per * sizeof(double), hipMemcpyDeviceToHost));
   if (dc_out)
-    HIP_TRY(ctx, hipMemcpy(dc_out, ctx->blk_dc + off, ctx->per_frame * sizeof(int32_t),
-                           hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemcpy(dc_out, ctx->blk_dc + off, per * sizeof(int32_t), hipMemcpyDeviceToHost));
   return VCA_OK;
 }
 

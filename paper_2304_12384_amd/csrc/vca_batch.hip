@@ -1,0 +1,754 @@
+// vca_batch.hip -- batched form of the VCA forward path (gfx950).
+//
+// Many independent video streams of different resolution, block size, bit
+// depth and frame count are analysed by ONE persistent launch: every
+// wavefront walks a flat list of 32 x 32 tiles covering all streams (a
+// stream's tiles are contiguous), decodes each tile through the stream's
+// descriptor, and dispatches to the tile code of the stream's
+// (bit depth, w, K) class (vca_tile.h).  A second launch reduces every
+// (stream, frame) pair to its seven features (vca_reduce.h).  Both launches
+// are captured once into a hipGraph per frame-count signature and replayed;
+// per call only the descriptor tables (frame pointers, state buffers) are
+// uploaded.  The ring depth and workgroups per CU come from vca_tune_batch.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vca.h"
+#include "vca_host.h"
+#include "vca_reduce.h"
+#include "vca_tile.h"
+
+using namespace vca;
+
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kKinds = 18;          // bit depth {8, 10} x w {32, 16, 8} x K {w, w/2, w/4}
+
+inline int kind_of(int bits, int w, int K) {
+  const int wi = w == 32 ? 0 : (w == 16 ? 1 : 2);
+  const int ki = K == w ? 0 : (K == w / 2 ? 1 : 2);
+  return ((bits == 10 ? 1 : 0) * 3 + wi) * 3 + ki;
+}
+
+// Device-side description of one stream for one launch.
+struct StreamDesc {
+  const uint8_t* plane[3];
+  int64_t fstride[3];
+  int32_t pitch[3];
+  int32_t nbx[3], nby[3], ntx[3], tcnt[3], boff[3];
+  int32_t tiles_per_frame, per_frame;
+  FastDiv div_tpf, div_ntx[3];
+  int32_t kind;
+  int32_t tile_begin, tile_end;  // the stream's tiles in the launch's flat list
+  int32_t blk_base;              // block index of the stream's frame 0
+  int32_t validate;
+  int32_t pad;
+};
+
+struct BatchParams {
+  const StreamDesc* streams;
+  int32_t n_streams;
+  int32_t total_tiles;
+  const v4i* tab_b1;     // [kKinds][64]
+  const v4i* tab_a2;     // [kKinds][64]
+  const double* tab_w;   // [kKinds][16][64]
+  double* blk_h;
+  int32_t* blk_dc;
+  int32_t* err_flag;
+};
+
+struct BatchReduceParams {
+  const ReduceParams* red;    // per stream; red[s].frame_begin = first workgroup of s
+  int32_t n_streams;
+};
+
+template <int kBits, int kW>
+__device__ inline TileWork decode_stream_tile(const StreamDesc& sd, int t) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kBpt = kTile / kW;
+  const int f = (int)fastdiv((uint32_t)t, sd.div_tpf);
+  t -= f * sd.tiles_per_frame;
+  int P = 0;
+  if (t >= sd.tcnt[0]) {
+    t -= sd.tcnt[0];
+    P = 1;
+    if (t >= sd.tcnt[1]) {
+      t -= sd.tcnt[1];
+      P = 2;
+    }
+  }
+  const int ty = (int)fastdiv((uint32_t)t, sd.div_ntx[P]);
+  const int tx = t - ty * sd.ntx[P];
+  const int by0 = ty * kBpt, bx0 = tx * kBpt;
+  TileWork w;
+  w.pitch = sd.pitch[P];
+  w.base = sd.plane[P] + f * sd.fstride[P] + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
+  w.vr = min(kBpt, sd.nby[P] - by0);
+  w.vc = min(kBpt, sd.nbx[P] - bx0);
+  w.out0 = sd.blk_base + f * sd.per_frame + sd.boff[P] + by0 * sd.nbx[P] + bx0;
+  w.out_row = sd.nbx[P];
+  return w;
+}
+
+// Loads the samples of flat tile id (stream s) with the stream's geometry.
+__device__ inline TileData load_batch_tile(const StreamDesc& sd, int id, int lane) {
+  const int t = id - sd.tile_begin;
+  switch (sd.kind / 3) {
+    case 0: return load_tile<8, 32>(decode_stream_tile<8, 32>(sd, t), lane);
+    case 1: return load_tile<8, 16>(decode_stream_tile<8, 16>(sd, t), lane);
+    case 2: return load_tile<8, 8>(decode_stream_tile<8, 8>(sd, t), lane);
+    case 3: return load_tile<10, 32>(decode_stream_tile<10, 32>(sd, t), lane);
+    case 4: return load_tile<10, 16>(decode_stream_tile<10, 16>(sd, t), lane);
+    default: return load_tile<10, 8>(decode_stream_tile<10, 8>(sd, t), lane);
+  }
+}
+
+template <int kBits, int kW, int kK>
+__device__ __forceinline__ void run_tile(const StreamDesc& sd, const TileOut& o,
+                                         const TileConsts<8, 8>& tc, const TileData& d, int id,
+                                         int lane) {
+  fwd_tile<kBits, kW, kK, false>(o, tc, d, decode_stream_tile<kBits, kW>(sd, id - sd.tile_begin),
+                                 lane);
+}
+
+__device__ inline void process_batch_tile(const StreamDesc& sd, const TileOut& o,
+                                          const TileConsts<8, 8>& tc, const TileData& d, int id,
+                                          int lane) {
+  switch (sd.kind) {
+    case 0: run_tile<8, 32, 32>(sd, o, tc, d, id, lane); break;
+    case 1: run_tile<8, 32, 16>(sd, o, tc, d, id, lane); break;
+    case 2: run_tile<8, 32, 8>(sd, o, tc, d, id, lane); break;
+    case 3: run_tile<8, 16, 16>(sd, o, tc, d, id, lane); break;
+    case 4: run_tile<8, 16, 8>(sd, o, tc, d, id, lane); break;
+    case 5: run_tile<8, 16, 4>(sd, o, tc, d, id, lane); break;
+    case 6: run_tile<8, 8, 8>(sd, o, tc, d, id, lane); break;
+    case 7: run_tile<8, 8, 4>(sd, o, tc, d, id, lane); break;
+    case 8: run_tile<8, 8, 2>(sd, o, tc, d, id, lane); break;
+    case 9: run_tile<10, 32, 32>(sd, o, tc, d, id, lane); break;
+    case 10: run_tile<10, 32, 16>(sd, o, tc, d, id, lane); break;
+    case 11: run_tile<10, 32, 8>(sd, o, tc, d, id, lane); break;
+    case 12: run_tile<10, 16, 16>(sd, o, tc, d, id, lane); break;
+    case 13: run_tile<10, 16, 8>(sd, o, tc, d, id, lane); break;
+    case 14: run_tile<10, 16, 4>(sd, o, tc, d, id, lane); break;
+    case 15: run_tile<10, 8, 8>(sd, o, tc, d, id, lane); break;
+    case 16: run_tile<10, 8, 4>(sd, o, tc, d, id, lane); break;
+    default: run_tile<10, 8, 2>(sd, o, tc, d, id, lane); break;
+  }
+}
+
+// Stream holding flat tile id, searched forward from s (ids of a wavefront
+// only grow, so the search is amortised O(1)).
+__device__ inline int advance_stream(const BatchParams& p, int s, int id) {
+  while (s < p.n_streams - 1 && id >= p.streams[s].tile_end) s++;
+  return s;
+}
+
+template <int kDepth>
+__global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int stride = gridDim.x * kWaves;
+  TileOut o;
+  o.blk_h = p.blk_h;
+  o.blk_dc = p.blk_dc;
+  o.coeffs = nullptr;
+  o.err_flag = p.err_flag;
+
+  int id = blockIdx.x * kWaves + wave;
+  TileData ring[kDepth];
+  int ring_s[kDepth];
+  int s_load = 0;                      // stream of the next tile to load
+#pragma unroll
+  for (int q = 0; q < kDepth; q++) {
+    const int nid = id + q * stride;
+    ring_s[q] = 0;
+    if (nid < p.total_tiles) {
+      s_load = advance_stream(p, s_load, nid);
+      ring_s[q] = s_load;
+      ring[q] = load_batch_tile(p.streams[s_load], nid, lane);
+    }
+  }
+  int cur_kind = -1;
+  TileConsts<8, 8> tc;
+  while (id < p.total_tiles) {
+#pragma unroll
+    for (int q = 0; q < kDepth; q++) {
+      if (id < p.total_tiles) {
+        const TileData d = ring[q];
+        const int s = ring_s[q];
+        const int nid = id + kDepth * stride;
+        if (nid < p.total_tiles) {
+          s_load = advance_stream(p, s_load, nid);
+          ring_s[q] = s_load;
+          ring[q] = load_batch_tile(p.streams[s_load], nid, lane);
+        }
+        const StreamDesc& sd = p.streams[s];
+        const int kind = __builtin_amdgcn_readfirstlane(sd.kind);
+        if (kind != cur_kind) {
+          tc.load(p.tab_b1 + kind * 64, p.tab_a2 + kind * 64, p.tab_w + kind * 16 * 64, lane);
+          cur_kind = kind;
+        }
+        o.validate = sd.validate;
+        process_batch_tile(sd, o, tc, d, id, lane);
+        id += stride;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kReduceThreads) void batch_reduce_kernel(BatchReduceParams p) {
+  // stream of this workgroup: the last s with red[s].frame_begin <= blockIdx.x
+  int lo = 0, hi = p.n_streams - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (p.red[mid].frame_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  reduce_frame(p.red[lo], b - p.red[lo].frame_begin);
+}
+
+using BatchKernel = void (*)(BatchParams);
+
+BatchKernel batch_kernel_for(int depth) {
+  if (depth == 1) return batch_fwd_kernel<1>;
+  if (depth == 3) return batch_fwd_kernel<3>;
+  return batch_fwd_kernel<2>;
+}
+
+}  // namespace
+
+struct vca_batch {
+  int n = 0;
+  std::vector<vca_config> cfgs;
+  std::vector<Geometry> geos;
+  int device = 0;
+  int num_cus = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t capture = nullptr;   // private stream the graph is captured on
+  // tables for every kind
+  v4i* tab_b1 = nullptr;
+  v4i* tab_a2 = nullptr;
+  double* tab_w = nullptr;
+  // per-stream device state
+  double* blk_h = nullptr;
+  int32_t* blk_dc = nullptr;
+  std::vector<int64_t> blk_base;   // per stream, into blk_h / blk_dc
+  double* state = nullptr;
+  std::vector<int64_t> state_off;  // per stream: two buffers of C_Y doubles
+  float* rings = nullptr;
+  std::vector<int64_t> ring_off;   // per stream, in floats
+  int32_t* err_flag = nullptr;
+  std::vector<int> cur_state;
+  std::vector<char> has_prev;
+  std::vector<int64_t> submitted;
+  // descriptors (device + pinned staging)
+  StreamDesc* d_streams = nullptr;
+  ReduceParams* d_red = nullptr;
+  StreamDesc* h_streams = nullptr;
+  ReduceParams* h_red = nullptr;
+  hipEvent_t uploaded = nullptr;   // staging buffers reusable once this completes
+  bool upload_pending = false;
+  // graph of the last launch signature
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int32_t> graph_sig;
+  bool use_graph = true;
+  LaunchChoice tuned;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int64_t> ev_frames;
+  size_t ev_used = 0;
+  std::string err;
+};
+
+namespace {
+
+vca_status bfail(vca_batch* b, vca_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  return s;
+}
+
+#define BHIP_TRY(b, expr)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return bfail((b), VCA_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+vca_status balloc(vca_batch* b, T** p, size_t count) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipErrorOutOfMemory) return bfail(b, VCA_ERR_OOM, "hipMalloc: out of device memory");
+  if (e != hipSuccess) return bfail(b, VCA_ERR_DEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return VCA_OK;
+}
+
+void drop_graph(vca_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_sig.clear();
+}
+
+// Fills the staging descriptors for one round: stream s analyses frames
+// [off[s], off[s] + cnt[s]) of its call.  Returns the number of tiles and of
+// frames of the round.
+void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, const int32_t* cnt,
+                      int32_t* total_tiles, int32_t* total_frames) {
+  int32_t tiles = 0, frames = 0;
+  for (int s = 0; s < b->n; s++) {
+    const Geometry& g = b->geos[s];
+    const vca_config& c = b->cfgs[s];
+    StreamDesc& sd = b->h_streams[s];
+    std::memset(&sd, 0, sizeof(sd));
+    const uint8_t* base[3] = {static_cast<const uint8_t*>(fr[s].y), static_cast<const uint8_t*>(fr[s].u),
+                              static_cast<const uint8_t*>(fr[s].v)};
+    const int64_t fs[3] = {fr[s].fstride_y, fr[s].fstride_uv, fr[s].fstride_uv};
+    const int64_t pt[3] = {fr[s].pitch_y, fr[s].pitch_uv, fr[s].pitch_uv};
+    for (int P = 0; P < 3; P++) {
+      sd.plane[P] = cnt[s] > 0 ? base[P] + fs[P] * off[s] : nullptr;
+      sd.fstride[P] = fs[P];
+      sd.pitch[P] = (int32_t)pt[P];
+      sd.nbx[P] = g.nbx[P];
+      sd.nby[P] = g.nby[P];
+      sd.ntx[P] = g.ntx[P];
+      sd.tcnt[P] = g.tcnt[P];
+      sd.boff[P] = g.boff[P];
+      sd.div_ntx[P] = make_fastdiv((uint32_t)g.ntx[P]);
+    }
+    sd.tiles_per_frame = g.tiles_per_frame;
+    sd.per_frame = g.per_frame;
+    sd.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
+    sd.kind = kind_of(c.bit_depth, c.block_size, g.K);
+    sd.tile_begin = tiles;
+    tiles += cnt[s] * g.tiles_per_frame;
+    sd.tile_end = tiles;
+    sd.blk_base = (int32_t)b->blk_base[s];
+    sd.validate = (c.flags & VCA_F_VALIDATE) && c.bit_depth == 10 ? 1 : 0;
+
+    ReduceParams& rp = b->h_red[s];
+    std::memset(&rp, 0, sizeof(rp));
+    const double ww = (double)c.block_size * c.block_size;
+    rp.blk_h = b->blk_h + b->blk_base[s];
+    rp.blk_dc = b->blk_dc + b->blk_base[s];
+    double* st = b->state + b->state_off[s];
+    rp.state_in = b->has_prev[s] ? st + (int64_t)b->cur_state[s] * g.cnt[0] : nullptr;
+    rp.state_out = st + (int64_t)(b->cur_state[s] ^ 1) * g.cnt[0];
+    rp.ring = b->rings + b->ring_off[s];
+    rp.first_frame = b->submitted[s];
+    rp.capacity = c.feature_capacity;
+    for (int P = 0; P < 3; P++) {
+      rp.cnt[P] = g.cnt[P];
+      rp.inv_norm[P] = 1.0 / ((double)g.cnt[P] * ww);
+    }
+    rp.per_frame = g.per_frame;
+    rp.n_frames = cnt[s];
+    rp.frame_begin = frames;
+    frames += cnt[s];
+  }
+  *total_tiles = tiles;
+  *total_frames = frames;
+}
+
+vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_tiles, int32_t total_frames,
+                            int depth, int gpc) {
+  BatchKernel kern = batch_kernel_for(depth);
+  int resident = 0;
+  BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kThreads, 0));
+  resident = std::max(1, resident);
+  if (gpc > 0) resident = std::min(resident, gpc);
+  const int64_t groups = ((int64_t)total_tiles + kWaves - 1) / kWaves;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)b->num_cus * resident));
+  BatchParams bp{};
+  bp.streams = b->d_streams;
+  bp.n_streams = b->n;
+  bp.total_tiles = total_tiles;
+  bp.tab_b1 = b->tab_b1;
+  bp.tab_a2 = b->tab_a2;
+  bp.tab_w = b->tab_w;
+  bp.blk_h = b->blk_h;
+  bp.blk_dc = b->blk_dc;
+  bp.err_flag = b->err_flag;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, bp);
+  BHIP_TRY(b, hipGetLastError());
+  if (total_frames > 0) {
+    BatchReduceParams rp{b->d_red, b->n};
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(total_frames), dim3(kReduceThreads), 0, st, rp);
+    BHIP_TRY(b, hipGetLastError());
+  }
+  return VCA_OK;
+}
+
+// Copies the staging descriptors to the device on the batch's stream.
+vca_status upload_descriptors(vca_batch* b) {
+  BHIP_TRY(b, hipMemcpyAsync(b->d_streams, b->h_streams, sizeof(StreamDesc) * b->n,
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipMemcpyAsync(b->d_red, b->h_red, sizeof(ReduceParams) * b->n,
+                             hipMemcpyHostToDevice, b->stream));
+  BHIP_TRY(b, hipEventRecord(b->uploaded, b->stream));
+  b->upload_pending = true;
+  return VCA_OK;
+}
+
+vca_status wait_staging(vca_batch* b) {
+  if (b->upload_pending) {
+    BHIP_TRY(b, hipEventSynchronize(b->uploaded));
+    b->upload_pending = false;
+  }
+  return VCA_OK;
+}
+
+std::string batch_tune_key(const vca_batch* b) {
+  std::string k = "gfx950/cu" + std::to_string(b->num_cus) + "/batch";
+  for (int s = 0; s < b->n; s++) {
+    const vca_config& c = b->cfgs[s];
+    k += "/" + std::to_string(c.bit_depth) + "b" + std::to_string(c.block_size) + "w" +
+         std::to_string(b->geos[s].K) + "k" + std::to_string(c.width) + "x" + std::to_string(c.height);
+  }
+  // keys stay short: hash the stream list
+  uint64_t h = 1469598103934665603ull;
+  for (char ch : k) h = (h ^ (uint8_t)ch) * 1099511628211ull;
+  char buf[96];
+  std::snprintf(buf, sizeof(buf), "gfx950/cu%d/batch/n%d/%016llx", b->num_cus, b->n,
+                (unsigned long long)h);
+  return buf;
+}
+
+vca_status check_batch_frames(vca_batch* b, const vca_frames* fr, const int32_t* n_frames) {
+  if (!fr || !n_frames) return bfail(b, VCA_ERR_INVALID_ARG, "null argument");
+  for (int s = 0; s < b->n; s++) {
+    if (n_frames[s] < 0) return bfail(b, VCA_ERR_INVALID_ARG, "negative frame count");
+    if (n_frames[s] == 0) continue;
+    if (!fr[s].on_device) return bfail(b, VCA_ERR_UNSUPPORTED, "host-resident frames");
+    if (const char* msg = check_frames(b->cfgs[s], &fr[s], n_frames[s]))
+      return bfail(b, VCA_ERR_INVALID_ARG, "stream " + std::to_string(s) + ": " + msg);
+  }
+  return VCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void vca_close_batch(vca_batch* b) {
+  if (!b) return;
+  {
+    DeviceGuard g(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    void* bufs[] = {b->tab_b1, b->tab_a2, b->tab_w,   b->blk_h,     b->blk_dc,
+                    b->state,  b->rings,  b->err_flag, b->d_streams, b->d_red};
+    for (void* p : bufs)
+      if (p) (void)hipFree(p);
+    if (b->h_streams) (void)hipHostFree(b->h_streams);
+    if (b->h_red) (void)hipHostFree(b->h_red);
+    if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  }
+  delete b;
+}
+
+vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_stream,
+                          vca_batch** out) {
+  if (!out) return VCA_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!cfgs || n_streams <= 0) return VCA_ERR_INVALID_ARG;
+  for (int s = 0; s < n_streams; s++) {
+    vca_status st = check_config(&cfgs[s]);
+    if (st != VCA_OK) return st;
+    if (cfgs[s].flags & VCA_F_KEEP_COEFFS) return VCA_ERR_UNSUPPORTED;
+    if (cfgs[s].device != cfgs[0].device) return VCA_ERR_INVALID_ARG;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return VCA_ERR_DEVICE;
+  if (cfgs[0].device >= ndev) return VCA_ERR_INVALID_ARG;
+
+  vca_batch* b = new (std::nothrow) vca_batch();
+  if (!b) return VCA_ERR_OOM;
+  b->n = n_streams;
+  b->device = cfgs[0].device;
+  b->cfgs.assign(cfgs, cfgs + n_streams);
+  b->geos.resize(n_streams);
+  b->blk_base.resize(n_streams);
+  b->state_off.resize(n_streams);
+  b->ring_off.resize(n_streams);
+  b->cur_state.assign(n_streams, 0);
+  b->has_prev.assign(n_streams, 0);
+  b->submitted.assign(n_streams, 0);
+  int64_t blk = 0, st_total = 0, ring_total = 0;
+  for (int s = 0; s < n_streams; s++) {
+    vca_config& c = b->cfgs[s];
+    if (c.max_batch == 0) c.max_batch = 300;
+    if (c.feature_capacity == 0) c.feature_capacity = 4096;
+    b->geos[s].init(c);
+    if (c.flags & VCA_F_TIMING) b->timing = true;
+    b->blk_base[s] = blk;
+    blk += (int64_t)c.max_batch * b->geos[s].per_frame;
+    b->state_off[s] = st_total;
+    st_total += 2 * (int64_t)b->geos[s].cnt[0];
+    b->ring_off[s] = ring_total;
+    ring_total += (int64_t)c.feature_capacity * 7;
+  }
+  auto bail = [&](vca_status st) {
+    vca_close_batch(b);
+    return st;
+  };
+  if (blk > (int64_t)INT32_MAX / 2) return bail(VCA_ERR_INVALID_ARG);   // block ids fit int32
+  DeviceGuard guard(b->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess) return bail(VCA_ERR_DEVICE);
+  b->num_cus = prop.multiProcessorCount;
+  if (hip_stream) {
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(VCA_ERR_DEVICE);
+    b->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
+    return bail(VCA_ERR_DEVICE);
+  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess)
+    return bail(VCA_ERR_DEVICE);
+  vca_status s;
+  if ((s = balloc(b, &b->tab_b1, kKinds * 64)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->tab_a2, kKinds * 64)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->tab_w, kKinds * 16 * 64)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->blk_h, (size_t)blk)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->blk_dc, (size_t)blk)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->state, (size_t)st_total)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->rings, (size_t)ring_total)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->err_flag, 1)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->d_streams, n_streams)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->d_red, n_streams)) != VCA_OK) return bail(s);
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->h_streams), sizeof(StreamDesc) * n_streams, 0) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(ReduceParams) * n_streams, 0) != hipSuccess)
+    return bail(VCA_ERR_OOM);
+  if (hipMemset(b->err_flag, 0, sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
+  // operand and weight tables of every kind
+  std::vector<int8_t> b1all(kKinds * 64 * 16), a2all(kKinds * 64 * 16);
+  std::vector<double> wall(kKinds * 16 * 64);
+  for (int bits : {8, 10})
+    for (int w : {32, 16, 8})
+      for (int kd : {1, 2, 4}) {
+        const int kind = kind_of(bits, w, w / kd);
+        std::vector<int8_t> b1, a2;
+        std::vector<double> wt;
+        build_tile_tables(w, w / kd, b1, a2, wt);
+        std::copy(b1.begin(), b1.end(), b1all.begin() + kind * 64 * 16);
+        std::copy(a2.begin(), a2.end(), a2all.begin() + kind * 64 * 16);
+        std::copy(wt.begin(), wt.end(), wall.begin() + kind * 16 * 64);
+      }
+  if (hipMemcpy(b->tab_b1, b1all.data(), b1all.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->tab_a2, a2all.data(), a2all.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->tab_w, wall.data(), wall.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(VCA_ERR_DEVICE);
+  if (const char* e = std::getenv("VCA_BATCH_NO_GRAPH")) b->use_graph = !(e[0] == '1');
+  TuneCache::get().find(batch_tune_key(b), &b->tuned);
+  *out = b;
+  return VCA_OK;
+}
+
+vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames) {
+  if (!b) return VCA_ERR_INVALID_ARG;
+  vca_status st = check_batch_frames(b, frames, n_frames);
+  if (st != VCA_OK) return st;
+  DeviceGuard guard(b->device);
+  const int depth = b->tuned.depth > 0 ? b->tuned.depth : 2;
+  const int gpc = b->tuned.groups_per_cu;
+  std::vector<int32_t> off(b->n, 0), cnt(b->n, 0);
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < b->n; s++) {
+      cnt[s] = std::min<int32_t>(b->cfgs[s].max_batch, n_frames[s] - off[s]);
+      any |= cnt[s] > 0;
+    }
+    if (!any) break;
+    if ((st = wait_staging(b)) != VCA_OK) return st;
+    int32_t tiles = 0, nfr = 0;
+    fill_descriptors(b, frames, off.data(), cnt.data(), &tiles, &nfr);
+    if ((st = upload_descriptors(b)) != VCA_OK) return st;
+    hipEvent_t* ev = nullptr;
+    if (b->timing) {
+      if (b->ev_used + 2 > b->ev_pool.size()) {
+        for (int e = 0; e < 2; e++) {
+          hipEvent_t h;
+          BHIP_TRY(b, hipEventCreate(&h));
+          b->ev_pool.push_back(h);
+        }
+      }
+      ev = &b->ev_pool[b->ev_used];
+      b->ev_frames.push_back(nfr);
+      b->ev_used += 2;
+      BHIP_TRY(b, hipEventRecord(ev[0], b->stream));
+    }
+    if (b->use_graph) {
+      std::vector<int32_t> sig(cnt);
+      sig.push_back(depth);
+      sig.push_back(gpc);
+      if (!b->exec || sig != b->graph_sig) {
+        drop_graph(b);
+        BHIP_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+        st = enqueue_launches(b, b->capture, tiles, nfr, depth, gpc);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->capture, &g);
+        if (st != VCA_OK) {
+          if (g) (void)hipGraphDestroy(g);
+          return st;
+        }
+        if (ec != hipSuccess) return bfail(b, VCA_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        b->graph = g;
+        BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_sig = sig;
+      }
+      BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    } else {
+      if ((st = enqueue_launches(b, b->stream, tiles, nfr, depth, gpc)) != VCA_OK) return st;
+    }
+    if (ev) BHIP_TRY(b, hipEventRecord(ev[1], b->stream));
+    for (int s = 0; s < b->n; s++) {
+      if (cnt[s] <= 0) continue;
+      b->cur_state[s] ^= 1;
+      b->has_prev[s] = 1;
+      b->submitted[s] += cnt[s];
+      off[s] += cnt[s];
+    }
+  }
+  return VCA_OK;
+}
+
+vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames, int32_t reps) {
+  if (!b || reps <= 0) return bfail(b, VCA_ERR_INVALID_ARG, "bad vca_tune_batch arguments");
+  vca_status st = check_batch_frames(b, frames, n_frames);
+  if (st != VCA_OK) return st;
+  DeviceGuard guard(b->device);
+  std::vector<int32_t> off(b->n, 0), cnt(b->n, 0);
+  for (int s = 0; s < b->n; s++) cnt[s] = std::min<int32_t>(b->cfgs[s].max_batch, n_frames[s]);
+  if ((st = wait_staging(b)) != VCA_OK) return st;
+  int32_t tiles = 0, nfr = 0;
+  fill_descriptors(b, frames, off.data(), cnt.data(), &tiles, &nfr);
+  if ((st = upload_descriptors(b)) != VCA_OK) return st;
+  hipEvent_t e0, e1;
+  BHIP_TRY(b, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, VCA_ERR_DEVICE, "hipEventCreate");
+  }
+  LaunchChoice best;
+  best.ms = 1e30;
+  for (int depth = 1; depth <= 3 && st == VCA_OK; depth++) {
+    int resident = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batch_kernel_for(depth), kThreads, 0) != hipSuccess)
+      resident = 1;
+    for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
+      // forward launch only (no reduction: features and h state are untouched)
+      st = enqueue_launches(b, b->stream, tiles, 0, depth, gpc);
+      if (st != VCA_OK) break;
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
+      for (int r = 0; r < reps && st == VCA_OK; r++) st = enqueue_launches(b, b->stream, tiles, 0, depth, gpc);
+      if (st != VCA_OK) break;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (ms < best.ms) best = LaunchChoice{depth, gpc, ms};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != VCA_OK) return st;
+  b->tuned = best;
+  TuneCache::get().put(batch_tune_key(b), best);
+  return VCA_OK;
+}
+
+vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* groups_per_cu, double* ms) {
+  if (!b) return VCA_ERR_INVALID_ARG;
+  if (depth) *depth = b->tuned.depth;
+  if (groups_per_cu) *groups_per_cu = b->tuned.groups_per_cu;
+  if (ms) *ms = b->tuned.ms;
+  return VCA_OK;
+}
+
+vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32_t count,
+                              vca_frame_features* out) {
+  if (!b || stream < 0 || stream >= b->n || count < 0 || first < 0 || (count > 0 && !out))
+    return bfail(b, VCA_ERR_INVALID_ARG, "bad vca_batch_features arguments");
+  if (first + count > b->submitted[stream]) return bfail(b, VCA_ERR_STATE, "frame not yet submitted");
+  const int64_t cap = b->cfgs[stream].feature_capacity;
+  if (first < b->submitted[stream] - cap) return bfail(b, VCA_ERR_STATE, "frame left the feature ring");
+  DeviceGuard guard(b->device);
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  int32_t bad = 0;
+  BHIP_TRY(b, hipMemcpy(&bad, b->err_flag, sizeof(bad), hipMemcpyDeviceToHost));
+  if (bad) return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
+  const float* ring = b->rings + b->ring_off[stream];
+  int64_t done = 0;
+  while (done < count) {
+    const int64_t slot = (first + done) % cap;
+    const int64_t n = std::min<int64_t>(count - done, cap - slot);
+    BHIP_TRY(b, hipMemcpy(reinterpret_cast<float*>(out) + done * 7, ring + slot * 7,
+                          (size_t)n * 7 * sizeof(float), hipMemcpyDeviceToHost));
+    done += n;
+  }
+  return VCA_OK;
+}
+
+vca_status vca_batch_timing(vca_batch* b, double* total_ms, int64_t* launches, int64_t* frames,
+                            int32_t reset) {
+  if (!b) return VCA_ERR_INVALID_ARG;
+  if (!b->timing) return bfail(b, VCA_ERR_STATE, "no stream opened with VCA_F_TIMING");
+  DeviceGuard guard(b->device);
+  BHIP_TRY(b, hipStreamSynchronize(b->stream));
+  double ms = 0.0;
+  int64_t n = 0, fr = 0;
+  for (size_t i = 0; i + 2 <= b->ev_used; i += 2) {
+    float t = 0.f;
+    BHIP_TRY(b, hipEventElapsedTime(&t, b->ev_pool[i], b->ev_pool[i + 1]));
+    ms += t;
+    n++;
+    fr += b->ev_frames[i / 2];
+  }
+  if (total_ms) *total_ms = ms;
+  if (launches) *launches = n;
+  if (frames) *frames = fr;
+  if (reset) {
+    b->ev_used = 0;
+    b->ev_frames.clear();
+  }
+  return VCA_OK;
+}
+
+vca_status vca_reset_batch(vca_batch* b, int32_t stream) {
+  if (!b || stream < -1 || stream >= b->n) return VCA_ERR_INVALID_ARG;
+  for (int s = 0; s < b->n; s++)
+    if (stream < 0 || s == stream) b->has_prev[s] = 0;
+  return VCA_OK;
+}
+
+int64_t vca_batch_submitted(const vca_batch* b, int32_t stream) {
+  if (!b || stream < 0 || stream >= b->n) return -1;
+  return b->submitted[stream];
+}
+
+const char* vca_batch_last_error(const vca_batch* b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// vca_host.h -- host-side helpers shared by the plain and batched paths:
+// configuration checks, plane/tile geometry, device allocation, error
+// reporting, and the launch-parameter autotuner's cache.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "../../include/vca.h"
+#include "vca_reduce.h"
+#include "vca_tile.h"
+
+namespace vca {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int now = -1;
+    if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline vca_status check_config(const vca_config* cfg) {
+  if (!cfg) return VCA_ERR_INVALID_ARG;
+  if (cfg->struct_size != sizeof(vca_config)) return VCA_ERR_INVALID_ARG;
+  const int w = cfg->block_size;
+  if (w != 8 && w != 16 && w != 32) return VCA_ERR_INVALID_ARG;
+  if (cfg->bit_depth != 8 && cfg->bit_depth != 10) return VCA_ERR_INVALID_ARG;
+  if (cfg->chroma_format != 420) return VCA_ERR_INVALID_ARG;
+  if (cfg->width <= 0 || cfg->height <= 0 || cfg->width % 2 || cfg->height % 2)
+    return VCA_ERR_INVALID_ARG;
+  if (cfg->width / 2 < w || cfg->height / 2 < w) return VCA_ERR_INVALID_ARG;
+  const int k = cfg->lowpass_k;
+  if (k != 0 && k != w && k != w / 2 && k != w / 4) return VCA_ERR_INVALID_ARG;
+  if (cfg->max_batch < 0 || cfg->feature_capacity < 0 || cfg->device < 0)
+    return VCA_ERR_INVALID_ARG;
+  if (cfg->flags & ~(VCA_F_KEEP_COEFFS | VCA_F_VALIDATE | VCA_F_TIMING)) return VCA_ERR_INVALID_ARG;
+  return VCA_OK;
+}
+
+// Block and tile geometry of one video configuration.
+struct Geometry {
+  int w = 0, K = 0, bits = 0;
+  int32_t nbx[3] = {0, 0, 0}, nby[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+  int32_t ntx[3] = {0, 0, 0}, tcnt[3] = {0, 0, 0}, boff[3] = {0, 0, 0};
+  int32_t per_frame = 0;        // blocks per frame
+  int32_t tiles_per_frame = 0;  // 32 x 32 tiles per frame
+
+  void init(const vca_config& cfg) {
+    w = cfg.block_size;
+    K = cfg.lowpass_k == 0 ? w : cfg.lowpass_k;
+    bits = cfg.bit_depth;
+    const int bpt = kTile / w;
+    per_frame = tiles_per_frame = 0;
+    for (int P = 0; P < 3; P++) {
+      const int pw = P == 0 ? cfg.width : cfg.width / 2;
+      const int ph = P == 0 ? cfg.height : cfg.height / 2;
+      nbx[P] = pw / w;
+      nby[P] = ph / w;
+      cnt[P] = nbx[P] * nby[P];
+      ntx[P] = (nbx[P] + bpt - 1) / bpt;
+      tcnt[P] = ntx[P] * ((nby[P] + bpt - 1) / bpt);
+      boff[P] = per_frame;
+      per_frame += cnt[P];
+      tiles_per_frame += tcnt[P];
+    }
+  }
+};
+
+// Checks a frame descriptor against a configuration (16-byte alignment,
+// pitches, strides).  Returns a message, or nullptr when the frames are valid.
+inline const char* check_frames(const vca_config& cfg, const vca_frames* fr, int32_t n_frames) {
+  const int bps = cfg.bit_depth == 8 ? 1 : 2;
+  if (!fr->on_device) return "host-resident frames are not supported";
+  if (!fr->y || !fr->u || !fr->v) return "null plane pointer";
+  if (fr->pitch_y < (int64_t)cfg.width * bps || fr->pitch_uv < (int64_t)cfg.width / 2 * bps)
+    return "pitch smaller than a row";
+  if (fr->pitch_y >= (1 << 23) || fr->pitch_uv >= (1 << 23))
+    return "pitch of 8 MiB or more";  // lane offsets are 24-bit products
+  if (n_frames > 1 && (fr->fstride_y < fr->pitch_y * cfg.height ||
+                       fr->fstride_uv < fr->pitch_uv * (cfg.height / 2)))
+    return "frame stride smaller than a frame";
+  const uintptr_t align = (uintptr_t)fr->y | (uintptr_t)fr->u | (uintptr_t)fr->v |
+                          (uintptr_t)fr->pitch_y | (uintptr_t)fr->pitch_uv |
+                          (uintptr_t)fr->fstride_y | (uintptr_t)fr->fstride_uv;
+  if (align & 15) return "planes, pitches and strides need 16-byte alignment";
+  return nullptr;
+}
+
+// Launch parameters chosen by the autotuner (depth 0 = not tuned).
+struct LaunchChoice {
+  int depth = 0;          // tiles in flight per wavefront (1..3)
+  int groups_per_cu = 0;  // 0: as many as fit
+  double ms = 0.0;
+};
+
+// Process-wide cache of tuned launch choices, optionally persisted to the
+// text file named by VCA_TUNE_CACHE (one "key depth groups ms" per line).
+class TuneCache {
+ public:
+  static TuneCache& get() {
+    static TuneCache c;
+    return c;
+  }
+  bool find(const std::string& key, LaunchChoice* out) {
+    std::lock_guard<std::mutex> lk(mu_);
+    load_once();
+    auto it = map_.find(key);
+    if (it == map_.end()) return false;
+    *out = it->second;
+    return true;
+  }
+  void put(const std::string& key, const LaunchChoice& c) {
+    std::lock_guard<std::mutex> lk(mu_);
+    load_once();
+    map_[key] = c;
+    const char* path = std::getenv("VCA_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE* f = std::fopen(path, "w")) {
+      for (const auto& kv : map_)
+        std::fprintf(f, "%s %d %d %.6f\n", kv.first.c_str(), kv.second.depth,
+                     kv.second.groups_per_cu, kv.second.ms);
+      std::fclose(f);
+    }
+  }
+
+ private:
+  void load_once() {
+    if (loaded_) return;
+    loaded_ = true;
+    const char* path = std::getenv("VCA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    LaunchChoice c;
+    while (std::fscanf(f, "%255s %d %d %lf", key, &c.depth, &c.groups_per_cu, &c.ms) == 4)
+      if (c.depth >= 1 && c.depth <= 3 && c.groups_per_cu >= 0) map_[key] = c;
+    std::fclose(f);
+  }
+  std::mutex mu_;
+  bool loaded_ = false;
+  std::map<std::string, LaunchChoice> map_;
+};
+
+}  // namespace vca

@@ -199,9 +199,11 @@ struct TileOut {
 // on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
 // scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
 // accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
-template <int kBits, int kW, int kK, bool kKeep>
-__device__ __forceinline__ void fwd_tile(const TileOut& o, const TileConsts<kW, kK>& tc,
-                                         const TileData& d, const TileWork& t, int lane) {
+// Consts: TileConsts<kW, kK>, or TileConsts<8, 8> (all registers loaded)
+// when one wavefront serves tiles of several block sizes.
+template <int kBits, int kW, int kK, bool kKeep, class Consts>
+__device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, const TileData& d,
+                                         const TileWork& t, int lane) {
   constexpr int kS1 = ilog2c(kW) + kBits - 9;
   constexpr int kS2 = ilog2c(kW) + 6;
   constexpr int kBpt = kTile / kW;

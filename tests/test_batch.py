@@ -1,0 +1,140 @@
+"""Batched form: one persistent, graph-replayed launch over many uneven
+streams gives, per stream, exactly the features of the plain path (itself
+bit-exact against the oracle), and matches the oracle on spot checks."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.device import generated_scene_video
+from tests.gpu_util import assert_features_close, print_case, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def vca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2304_12384_amd as vca_mod
+    return vca_mod
+
+
+STREAMS = [
+    dict(width=640, height=360, block_size=8, n=7),
+    dict(width=1280, height=720, block_size=32, lowpass_k=16, n=12),
+    dict(width=1920, height=1080, block_size=16, n=5),
+    dict(width=640, height=360, block_size=32, n=9),
+    dict(width=2560, height=1440, block_size=8, lowpass_k=4, n=3),
+    dict(width=3840, height=2160, block_size=32, n=4),
+    dict(width=1056, height=568, block_size=16, lowpass_k=8, n=6),
+    dict(width=1920, height=1080, block_size=16, bit_depth=10, n=3),
+    dict(width=1280, height=720, block_size=8, bit_depth=10, lowpass_k=2, n=2),
+]
+
+
+def make_frames(d, seed):
+    if d.get("bit_depth", 8) == 10:
+        return to_device(synth.stress_video(d["width"], d["height"], d["n"], cell=d["block_size"],
+                                            stream=seed))
+    dv = generated_scene_video(d["width"], d["height"], d["n"], seed=seed, scene_len=4)
+    return dv.y, dv.u, dv.v
+
+
+@pytest.fixture(scope="module")
+def frames(vca):
+    return [make_frames(d, 1000 + i) for i, d in enumerate(STREAMS)]
+
+
+def plain_features(vca, d, planes, calls):
+    an = vca.Analyzer(d["width"], d["height"], bit_depth=d.get("bit_depth", 8),
+                      block_size=d["block_size"], lowpass_k=d.get("lowpass_k", 0))
+    for _ in range(calls):
+        an.submit(*planes)
+    f = an.features(0, calls * d["n"])
+    an.close()
+    return f
+
+
+def test_batch_graph_replays_match_plain(vca, frames):
+    print_case(test="batch_vs_plain", streams=len(STREAMS))
+    calls = 3
+    b = vca.Batch(STREAMS)
+    for c in range(calls):
+        b.submit(list(frames))
+        # eager work and a synchronisation between graph replays
+        x = torch.arange(1 << 20, device="cuda", dtype=torch.float32)
+        assert float((x * 2).sum()) > 0
+        torch.cuda.synchronize()
+    got = [b.features(s, 0, calls * d["n"]) for s, d in enumerate(STREAMS)]
+    b.close()
+    for s, d in enumerate(STREAMS):
+        ref = plain_features(vca, d, frames[s], calls)
+        assert got[s].tobytes() == ref.tobytes(), f"stream {s} ({d}) differs from the plain path"
+
+
+def test_batch_oracle_spot_checks(vca, frames):
+    print_case(test="batch_oracle")
+    b = vca.Batch(STREAMS)
+    b.submit(list(frames))
+    for s in (0, 1, 4, 7):
+        d = STREAMS[s]
+        got = b.features(s, 0, d["n"])
+        y, u, v = (p.cpu().numpy() for p in frames[s])
+        if d.get("bit_depth", 8) == 10:
+            y, u, v = (a.view(np.uint16) for a in (y, u, v))
+        cfg = oracle.Config(d["width"], d["height"], d.get("bit_depth", 8), d["block_size"],
+                            d.get("lowpass_k", 0))
+        ref = oracle.analyze(cfg, y, u, v, threads=8).features
+        assert_features_close(got, ref)
+    b.close()
+
+
+def test_batch_rounds_empty_streams_and_signature_change(vca, frames):
+    print_case(test="batch_rounds")
+    small = [dict(d, max_batch=2) for d in STREAMS[:4]]
+    b = vca.Batch(small)
+    sub = [frames[s] for s in range(4)]
+    b.submit(sub)                                     # rounds of 2 frames
+    b.submit([sub[0], None, sub[2], None])            # streams 1 and 3 idle
+    b.submit([None, sub[1], None, sub[3]])
+    for s, d in enumerate(small):
+        n = d["n"]
+        got = b.features(s, 0, 2 * n)
+        ref = plain_features(vca, d, frames[s], 2)
+        assert got.tobytes() == ref.tobytes(), f"stream {s}"
+    b.close()
+
+
+def test_batch_tune_and_no_graph_path(vca, frames, monkeypatch):
+    print_case(test="batch_tune")
+    sub = list(frames[:6])
+    b = vca.Batch(STREAMS[:6])
+    choice = b.tune(sub, reps=1)
+    assert 1 <= choice["depth"] <= 3 and choice["groups_per_cu"] >= 1 and choice["ms"] > 0
+    b.submit(sub)
+    tuned = [b.features(s, 0, d["n"]) for s, d in enumerate(STREAMS[:6])]
+    b.close()
+    monkeypatch.setenv("VCA_BATCH_NO_GRAPH", "1")
+    b2 = vca.Batch(STREAMS[:6])
+    b2.submit(sub)
+    eager = [b2.features(s, 0, d["n"]) for s, d in enumerate(STREAMS[:6])]
+    b2.close()
+    for s in range(6):
+        assert tuned[s].tobytes() == eager[s].tobytes()
+
+
+def test_plain_tune(vca, frames):
+    print_case(test="plain_tune")
+    d = STREAMS[5]
+    an = vca.Analyzer(d["width"], d["height"], block_size=d["block_size"])
+    choice = an.tune(*frames[5], reps=1)
+    assert 1 <= choice["depth"] <= 3 and choice["groups_per_cu"] >= 1
+    an.submit(*frames[5])
+    f = an.features(0, d["n"])
+    an.close()
+    assert f.tobytes() == plain_features(vca, d, frames[5], 1).tobytes()
