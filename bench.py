@@ -64,11 +64,12 @@ def cpu_baseline(sv, frames: int, lowpass_k: int = 0) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
-def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int) -> dict:
+def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool) -> dict:
     import torch
     an = vca.Analyzer(WIDTH, HEIGHT, block_size=BLOCK, lowpass_k=lowpass_k, timing=True,
                       max_batch=MAX_BATCH)
     planes = dev.planes()
+    launch = an.tune(*planes, reps=2) if tune else an.tuned_launch()
     for _ in range(warmup):
         first = an.submit(*planes)
         an.features(first, FRAMES)
@@ -99,6 +100,77 @@ def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int) -> dict:
         "mfma": {"achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
                  "frac": tops / INT8_PEAK_TOPS},
         "last_features": [float(x) for x in feats[-1]],
+        "launch": launch,
+    }
+
+
+def plane_bytes(d: dict) -> int:
+    """Samples inside complete blocks of one frame of a stream (8-bit)."""
+    return algorithmic_bytes_per_frame(d["width"], d["height"], d["block_size"])
+
+
+def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
+    """64 uneven streams (resolution, block size, frame count drawn per
+    stream) in one persistent graph-replayed launch per step, against the same
+    streams analysed one after another by plain contexts."""
+    import torch
+    import synth
+    from synth.device import generated_scene_video
+    descs = synth.batch_streams(64)
+    log(f"generating {len(descs)} streams, {sum(d['n_frames'] for d in descs)} frames on the device")
+    vids = [generated_scene_video(d["width"], d["height"], d["n_frames"], seed=3000 + d["stream"])
+            for d in descs]
+    torch.cuda.synchronize()
+    frames = [v.planes() for v in vids]
+    total_frames = sum(d["n_frames"] for d in descs)
+    total_bytes = sum(plane_bytes(d) * d["n_frames"] for d in descs)
+    cfg = [dict(width=d["width"], height=d["height"], block_size=d["block_size"],
+                max_batch=d["n_frames"]) for d in descs]
+    b = vca.Batch(cfg, timing=True)
+    launch = b.tune(frames, reps=1) if tune else b.tuned_launch()
+    for _ in range(warmup):
+        b.submit(frames)
+    b.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        first = b.submit(frames)
+        for s, d in enumerate(descs):
+            b.features(s, first[s], d["n_frames"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = b.timing(reset=True)
+    b.close()
+    # the same streams through plain contexts, one after another
+    ans = [vca.Analyzer(d["width"], d["height"], block_size=d["block_size"], max_batch=d["n_frames"])
+           for d in descs]
+    for an, fr in zip(ans, frames):
+        an.submit(*fr)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for an, fr in zip(ans, frames):
+            an.submit(*fr)
+        for an, d in zip(ans, descs):
+            an.features(an.submitted - d["n_frames"], d["n_frames"])
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t1
+    for an in ans:
+        an.close()
+    dev_ms = tm["ms"] / max(1, tm["launches"])
+    gbs = total_bytes / (dev_ms * 1e-3) / 1e9
+    return {
+        "streams": len(descs), "frames_per_step": total_frames,
+        "bytes_per_step": total_bytes,
+        "value": steps * total_frames / dt, "unit": "frames/s",
+        "ms_per_step": dt * 1e3 / steps,
+        "device_ms_per_step": dev_ms,
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        "plain_same_streams": {"value": steps * total_frames / dt_plain, "unit": "frames/s",
+                               "ms_per_step": dt_plain * 1e3 / steps},
+        "speedup_vs_plain": dt_plain / dt,
+        "launch": launch,
     }
 
 
@@ -109,7 +181,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-frames", type=int, default=64,
                     help="frames of the oracle's bounded CPU sample (0 skips it)")
-    ap.add_argument("--modes", default="full,lowpass", help="comma list of full, lowpass")
+    ap.add_argument("--modes", default="full,lowpass,batch",
+                    help="comma list of full, lowpass, batch")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the analysis has no multi-GPU path); "
@@ -131,18 +205,30 @@ def main() -> int:
     log(f"frames resident on the device: {dev.nbytes / 1e9:.2f} GB")
 
     results = {}
-    for mode in args.modes.split(","):
+    modes = args.modes.split(",")
+    for mode in (m for m in modes if m in ("full", "lowpass")):
         k = 0 if mode == "full" else 16
         log(f"timing mode={mode} steps={args.steps} warmup={args.warmup}")
-        results[mode] = run_mode(vca, dev, k, args.steps, args.warmup)
+        results[mode] = run_mode(vca, dev, k, args.steps, args.warmup, not args.no_tune)
         log(f"mode={mode}: {results[mode]['fps']:.0f} frames/s, forward kernel "
-            f"{results[mode]['forward_kernel_ms']:.3f} ms/launch")
+            f"{results[mode]['forward_kernel_ms']:.3f} ms/launch, launch {results[mode]['launch']}")
+    batch = None
+    if "batch" in modes:
+        del dev
+        torch.cuda.empty_cache()
+        log("timing the batched form")
+        batch = run_batch(vca, max(2, args.steps // 4), 1, not args.no_tune)
+        log(f"batched: {batch['value']:.0f} frames/s over {batch['streams']} streams, "
+            f"{batch['speedup_vs_plain']:.2f}x the plain path")
 
     cpu = None
     if args.cpu_frames > 0:
         log(f"timing the CPU oracle on {args.cpu_frames} frames")
         cpu = cpu_baseline(sv, args.cpu_frames)
 
+    if not results:
+        print(json.dumps({"metric": METRIC, "batched": batch}), flush=True)
+        return 0
     head = results.get("full") or next(iter(results.values()))
     line = {
         "metric": METRIC,
@@ -165,13 +251,17 @@ def main() -> int:
         "mfma": head["mfma"],
         "forward_kernel_ms": head["forward_kernel_ms"],
         "reduce_kernel_ms": head["reduce_kernel_ms"],
+        "launch": head["launch"],
         "cpu_baseline": cpu,
     }
     if "lowpass" in results and "full" in results:
         lp = results["lowpass"]
         line["lowpass_k16"] = {"value": lp["fps"], "unit": "frames/s",
                                "ms_per_step": lp["ms_per_step"], "roofline": lp["roofline"],
-                               "mfma": lp["mfma"], "forward_kernel_ms": lp["forward_kernel_ms"]}
+                               "mfma": lp["mfma"], "forward_kernel_ms": lp["forward_kernel_ms"],
+                               "launch": lp["launch"]}
+    if batch is not None:
+        line["batched"] = batch
     print(json.dumps(line), flush=True)
     return 0
 

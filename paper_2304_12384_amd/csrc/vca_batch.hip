@@ -2,10 +2,10 @@
 //
 // Many independent video streams of different resolution, block size, bit
 // depth and frame count are analysed by ONE persistent launch: every
-// wavefront walks a flat list of 32 x 32 tiles covering all streams (a
-// stream's tiles are contiguous), decodes each tile through the stream's
-// descriptor, and dispatches to the tile code of the stream's
-// (bit depth, w, K) class (vca_tile.h).  A second launch reduces every
+// wavefront walks a flat list of chunks (runs of kChunk consecutive 32 x 32
+// tiles of one stream; a stream's chunks are contiguous), copies the chunk's
+// stream descriptor into registers, and runs the tile loop specialised for
+// the stream's (bit depth, w, K) class (vca_tile.h).  A second launch reduces every
 // (stream, frame) pair to its seven features (vca_reduce.h).  Both launches
 // are captured once into a hipGraph per frame-count signature and replayed;
 // per call only the descriptor tables (frame pointers, state buffers) are
@@ -49,16 +49,19 @@ struct StreamDesc {
   int32_t tiles_per_frame, per_frame;
   FastDiv div_tpf, div_ntx[3];
   int32_t kind;
-  int32_t tile_begin, tile_end;  // the stream's tiles in the launch's flat list
+  int32_t tiles;                 // tiles of the stream in this launch
+  int32_t chunk_begin, chunk_end;  // the stream's chunks in the launch's flat list
   int32_t blk_base;              // block index of the stream's frame 0
   int32_t validate;
-  int32_t pad;
 };
+
+// Consecutive tiles of one stream handed to a wavefront at a time.
+constexpr int kChunk = 256;
 
 struct BatchParams {
   const StreamDesc* streams;
   int32_t n_streams;
-  int32_t total_tiles;
+  int32_t total_chunks;
   const v4i* tab_b1;     // [kKinds][64]
   const v4i* tab_a2;     // [kKinds][64]
   const double* tab_w;   // [kKinds][16][64]
@@ -100,60 +103,75 @@ __device__ inline TileWork decode_stream_tile(const StreamDesc& sd, int t) {
   return w;
 }
 
-// Loads the samples of flat tile id (stream s) with the stream's geometry.
-__device__ inline TileData load_batch_tile(const StreamDesc& sd, int id, int lane) {
-  const int t = id - sd.tile_begin;
-  switch (sd.kind / 3) {
-    case 0: return load_tile<8, 32>(decode_stream_tile<8, 32>(sd, t), lane);
-    case 1: return load_tile<8, 16>(decode_stream_tile<8, 16>(sd, t), lane);
-    case 2: return load_tile<8, 8>(decode_stream_tile<8, 8>(sd, t), lane);
-    case 3: return load_tile<10, 32>(decode_stream_tile<10, 32>(sd, t), lane);
-    case 4: return load_tile<10, 16>(decode_stream_tile<10, 16>(sd, t), lane);
-    default: return load_tile<10, 8>(decode_stream_tile<10, 8>(sd, t), lane);
+// Tiles [t0, t1) of one stream, with the plain kernel's register ring.
+template <int kBits, int kW, int kK, int kDepth>
+__device__ __forceinline__ void run_chunk(const StreamDesc& sd, const TileOut& o,
+                                          const TileConsts<8, 8>& tc, int t0, int t1, int lane) {
+  TileData ring[kDepth];
+#pragma unroll
+  for (int q = 0; q < kDepth; q++)
+    if (t0 + q < t1) ring[q] = load_tile<kBits, kW>(decode_stream_tile<kBits, kW>(sd, t0 + q), lane);
+  int t = t0;
+  while (t < t1) {
+#pragma unroll
+    for (int q = 0; q < kDepth; q++) {
+      if (t < t1) {
+        const TileData d = ring[q];
+        if (t + kDepth < t1)
+          ring[q] = load_tile<kBits, kW>(decode_stream_tile<kBits, kW>(sd, t + kDepth), lane);
+        fwd_tile<kBits, kW, kK, false>(o, tc, d, decode_stream_tile<kBits, kW>(sd, t), lane);
+        t++;
+      }
+    }
   }
 }
 
-template <int kBits, int kW, int kK>
-__device__ __forceinline__ void run_tile(const StreamDesc& sd, const TileOut& o,
-                                         const TileConsts<8, 8>& tc, const TileData& d, int id,
-                                         int lane) {
-  fwd_tile<kBits, kW, kK, false>(o, tc, d, decode_stream_tile<kBits, kW>(sd, id - sd.tile_begin),
-                                 lane);
-}
-
-__device__ inline void process_batch_tile(const StreamDesc& sd, const TileOut& o,
-                                          const TileConsts<8, 8>& tc, const TileData& d, int id,
-                                          int lane) {
+// kOnly8: every stream of the launch is 8-bit (the 10-bit tile loops are
+// left out, which lowers the kernel's register allocation).
+template <int kDepth, bool kOnly8>
+__device__ inline void dispatch_chunk(const StreamDesc& sd, const TileOut& o,
+                                      const TileConsts<8, 8>& tc, int t0, int t1, int lane) {
+  if (kOnly8) {
+    switch (sd.kind) {
+      case 0: run_chunk<8, 32, 32, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 1: run_chunk<8, 32, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 2: run_chunk<8, 32, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 3: run_chunk<8, 16, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 4: run_chunk<8, 16, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 5: run_chunk<8, 16, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 6: run_chunk<8, 8, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+      case 7: run_chunk<8, 8, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
+      default: run_chunk<8, 8, 2, kDepth>(sd, o, tc, t0, t1, lane); break;
+    }
+    return;
+  }
   switch (sd.kind) {
-    case 0: run_tile<8, 32, 32>(sd, o, tc, d, id, lane); break;
-    case 1: run_tile<8, 32, 16>(sd, o, tc, d, id, lane); break;
-    case 2: run_tile<8, 32, 8>(sd, o, tc, d, id, lane); break;
-    case 3: run_tile<8, 16, 16>(sd, o, tc, d, id, lane); break;
-    case 4: run_tile<8, 16, 8>(sd, o, tc, d, id, lane); break;
-    case 5: run_tile<8, 16, 4>(sd, o, tc, d, id, lane); break;
-    case 6: run_tile<8, 8, 8>(sd, o, tc, d, id, lane); break;
-    case 7: run_tile<8, 8, 4>(sd, o, tc, d, id, lane); break;
-    case 8: run_tile<8, 8, 2>(sd, o, tc, d, id, lane); break;
-    case 9: run_tile<10, 32, 32>(sd, o, tc, d, id, lane); break;
-    case 10: run_tile<10, 32, 16>(sd, o, tc, d, id, lane); break;
-    case 11: run_tile<10, 32, 8>(sd, o, tc, d, id, lane); break;
-    case 12: run_tile<10, 16, 16>(sd, o, tc, d, id, lane); break;
-    case 13: run_tile<10, 16, 8>(sd, o, tc, d, id, lane); break;
-    case 14: run_tile<10, 16, 4>(sd, o, tc, d, id, lane); break;
-    case 15: run_tile<10, 8, 8>(sd, o, tc, d, id, lane); break;
-    case 16: run_tile<10, 8, 4>(sd, o, tc, d, id, lane); break;
-    default: run_tile<10, 8, 2>(sd, o, tc, d, id, lane); break;
+    case 0: run_chunk<8, 32, 32, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 1: run_chunk<8, 32, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 2: run_chunk<8, 32, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 3: run_chunk<8, 16, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 4: run_chunk<8, 16, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 5: run_chunk<8, 16, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 6: run_chunk<8, 8, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 7: run_chunk<8, 8, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 8: run_chunk<8, 8, 2, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 9: run_chunk<10, 32, 32, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 10: run_chunk<10, 32, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 11: run_chunk<10, 32, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 12: run_chunk<10, 16, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 13: run_chunk<10, 16, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 14: run_chunk<10, 16, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 15: run_chunk<10, 8, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
+    case 16: run_chunk<10, 8, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
+    default: run_chunk<10, 8, 2, kDepth>(sd, o, tc, t0, t1, lane); break;
   }
 }
 
-// Stream holding flat tile id, searched forward from s (ids of a wavefront
-// only grow, so the search is amortised O(1)).
-__device__ inline int advance_stream(const BatchParams& p, int s, int id) {
-  while (s < p.n_streams - 1 && id >= p.streams[s].tile_end) s++;
-  return s;
-}
-
-template <int kDepth>
+// Persistent batched kernel: each wavefront walks chunks c, c + S, ... of
+// the flat chunk list (chunks of a stream are contiguous, so the stream
+// search only moves forward).  Per chunk the stream's descriptor is copied
+// into registers once and one specialised tile loop runs.
+template <int kDepth, bool kOnly8>
 __global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -163,46 +181,21 @@ __global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
   o.blk_dc = p.blk_dc;
   o.coeffs = nullptr;
   o.err_flag = p.err_flag;
-
-  int id = blockIdx.x * kWaves + wave;
-  TileData ring[kDepth];
-  int ring_s[kDepth];
-  int s_load = 0;                      // stream of the next tile to load
-#pragma unroll
-  for (int q = 0; q < kDepth; q++) {
-    const int nid = id + q * stride;
-    ring_s[q] = 0;
-    if (nid < p.total_tiles) {
-      s_load = advance_stream(p, s_load, nid);
-      ring_s[q] = s_load;
-      ring[q] = load_batch_tile(p.streams[s_load], nid, lane);
-    }
-  }
   int cur_kind = -1;
   TileConsts<8, 8> tc;
-  while (id < p.total_tiles) {
-#pragma unroll
-    for (int q = 0; q < kDepth; q++) {
-      if (id < p.total_tiles) {
-        const TileData d = ring[q];
-        const int s = ring_s[q];
-        const int nid = id + kDepth * stride;
-        if (nid < p.total_tiles) {
-          s_load = advance_stream(p, s_load, nid);
-          ring_s[q] = s_load;
-          ring[q] = load_batch_tile(p.streams[s_load], nid, lane);
-        }
-        const StreamDesc& sd = p.streams[s];
-        const int kind = __builtin_amdgcn_readfirstlane(sd.kind);
-        if (kind != cur_kind) {
-          tc.load(p.tab_b1 + kind * 64, p.tab_a2 + kind * 64, p.tab_w + kind * 16 * 64, lane);
-          cur_kind = kind;
-        }
-        o.validate = sd.validate;
-        process_batch_tile(sd, o, tc, d, id, lane);
-        id += stride;
-      }
+  int s = 0;
+  for (int c = blockIdx.x * kWaves + wave; c < p.total_chunks; c += stride) {
+    while (s < p.n_streams - 1 && c >= p.streams[s].chunk_end) s++;
+    const StreamDesc sd = p.streams[s];
+    const int kind = __builtin_amdgcn_readfirstlane(sd.kind);
+    if (kind != cur_kind) {
+      tc.load(p.tab_b1 + kind * 64, p.tab_a2 + kind * 64, p.tab_w + kind * 16 * 64, lane);
+      cur_kind = kind;
     }
+    o.validate = sd.validate;
+    const int t0 = (c - sd.chunk_begin) * kChunk;
+    const int t1 = min(t0 + kChunk, sd.tiles);
+    dispatch_chunk<kDepth, kOnly8>(sd, o, tc, t0, t1, lane);
   }
 }
 
@@ -220,10 +213,15 @@ __global__ __launch_bounds__(kReduceThreads) void batch_reduce_kernel(BatchReduc
 
 using BatchKernel = void (*)(BatchParams);
 
-BatchKernel batch_kernel_for(int depth) {
-  if (depth == 1) return batch_fwd_kernel<1>;
-  if (depth == 3) return batch_fwd_kernel<3>;
-  return batch_fwd_kernel<2>;
+BatchKernel batch_kernel_for(int depth, bool only8) {
+  if (only8) {
+    if (depth == 1) return batch_fwd_kernel<1, true>;
+    if (depth == 3) return batch_fwd_kernel<3, true>;
+    return batch_fwd_kernel<2, true>;
+  }
+  if (depth == 1) return batch_fwd_kernel<1, false>;
+  if (depth == 3) return batch_fwd_kernel<3, false>;
+  return batch_fwd_kernel<2, false>;
 }
 
 }  // namespace
@@ -265,6 +263,7 @@ struct vca_batch {
   hipGraphExec_t exec = nullptr;
   std::vector<int32_t> graph_sig;
   bool use_graph = true;
+  bool only8 = true;               // no 10-bit stream: the 8-bit-only kernel serves
   LaunchChoice tuned;
   // timing
   bool timing = false;
@@ -305,11 +304,11 @@ void drop_graph(vca_batch* b) {
 }
 
 // Fills the staging descriptors for one round: stream s analyses frames
-// [off[s], off[s] + cnt[s]) of its call.  Returns the number of tiles and of
+// [off[s], off[s] + cnt[s]) of its call.  Returns the number of chunks and of
 // frames of the round.
 void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, const int32_t* cnt,
-                      int32_t* total_tiles, int32_t* total_frames) {
-  int32_t tiles = 0, frames = 0;
+                      int32_t* total_chunks, int32_t* total_frames) {
+  int32_t chunks = 0, frames = 0;
   for (int s = 0; s < b->n; s++) {
     const Geometry& g = b->geos[s];
     const vca_config& c = b->cfgs[s];
@@ -334,9 +333,10 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
     sd.per_frame = g.per_frame;
     sd.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
     sd.kind = kind_of(c.bit_depth, c.block_size, g.K);
-    sd.tile_begin = tiles;
-    tiles += cnt[s] * g.tiles_per_frame;
-    sd.tile_end = tiles;
+    sd.tiles = cnt[s] * g.tiles_per_frame;
+    sd.chunk_begin = chunks;
+    chunks += (sd.tiles + kChunk - 1) / kChunk;
+    sd.chunk_end = chunks;
     sd.blk_base = (int32_t)b->blk_base[s];
     sd.validate = (c.flags & VCA_F_VALIDATE) && c.bit_depth == 10 ? 1 : 0;
 
@@ -360,23 +360,23 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
     rp.frame_begin = frames;
     frames += cnt[s];
   }
-  *total_tiles = tiles;
+  *total_chunks = chunks;
   *total_frames = frames;
 }
 
-vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_tiles, int32_t total_frames,
+vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_chunks, int32_t total_frames,
                             int depth, int gpc) {
-  BatchKernel kern = batch_kernel_for(depth);
+  BatchKernel kern = batch_kernel_for(depth, b->only8);
   int resident = 0;
   BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kThreads, 0));
   resident = std::max(1, resident);
   if (gpc > 0) resident = std::min(resident, gpc);
-  const int64_t groups = ((int64_t)total_tiles + kWaves - 1) / kWaves;
+  const int64_t groups = ((int64_t)total_chunks + kWaves - 1) / kWaves;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)b->num_cus * resident));
   BatchParams bp{};
   bp.streams = b->d_streams;
   bp.n_streams = b->n;
-  bp.total_tiles = total_tiles;
+  bp.total_chunks = total_chunks;
   bp.tab_b1 = b->tab_b1;
   bp.tab_a2 = b->tab_a2;
   bp.tab_w = b->tab_w;
@@ -498,6 +498,7 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
     if (c.feature_capacity == 0) c.feature_capacity = 4096;
     b->geos[s].init(c);
     if (c.flags & VCA_F_TIMING) b->timing = true;
+    if (c.bit_depth != 8) b->only8 = false;
     b->blk_base[s] = blk;
     blk += (int64_t)c.max_batch * b->geos[s].per_frame;
     b->state_off[s] = st_total;
@@ -580,8 +581,8 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
     }
     if (!any) break;
     if ((st = wait_staging(b)) != VCA_OK) return st;
-    int32_t tiles = 0, nfr = 0;
-    fill_descriptors(b, frames, off.data(), cnt.data(), &tiles, &nfr);
+    int32_t chunks = 0, nfr = 0;
+    fill_descriptors(b, frames, off.data(), cnt.data(), &chunks, &nfr);
     if ((st = upload_descriptors(b)) != VCA_OK) return st;
     hipEvent_t* ev = nullptr;
     if (b->timing) {
@@ -604,7 +605,7 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
       if (!b->exec || sig != b->graph_sig) {
         drop_graph(b);
         BHIP_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-        st = enqueue_launches(b, b->capture, tiles, nfr, depth, gpc);
+        st = enqueue_launches(b, b->capture, chunks, nfr, depth, gpc);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(b->capture, &g);
         if (st != VCA_OK) {
@@ -618,7 +619,7 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
       }
       BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
     } else {
-      if ((st = enqueue_launches(b, b->stream, tiles, nfr, depth, gpc)) != VCA_OK) return st;
+      if ((st = enqueue_launches(b, b->stream, chunks, nfr, depth, gpc)) != VCA_OK) return st;
     }
     if (ev) BHIP_TRY(b, hipEventRecord(ev[1], b->stream));
     for (int s = 0; s < b->n; s++) {
@@ -640,8 +641,8 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
   std::vector<int32_t> off(b->n, 0), cnt(b->n, 0);
   for (int s = 0; s < b->n; s++) cnt[s] = std::min<int32_t>(b->cfgs[s].max_batch, n_frames[s]);
   if ((st = wait_staging(b)) != VCA_OK) return st;
-  int32_t tiles = 0, nfr = 0;
-  fill_descriptors(b, frames, off.data(), cnt.data(), &tiles, &nfr);
+  int32_t chunks = 0, nfr = 0;
+  fill_descriptors(b, frames, off.data(), cnt.data(), &chunks, &nfr);
   if ((st = upload_descriptors(b)) != VCA_OK) return st;
   hipEvent_t e0, e1;
   BHIP_TRY(b, hipEventCreate(&e0));
@@ -653,14 +654,14 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
   best.ms = 1e30;
   for (int depth = 1; depth <= 3 && st == VCA_OK; depth++) {
     int resident = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batch_kernel_for(depth), kThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batch_kernel_for(depth, b->only8), kThreads, 0) != hipSuccess)
       resident = 1;
     for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
       // forward launch only (no reduction: features and h state are untouched)
-      st = enqueue_launches(b, b->stream, tiles, 0, depth, gpc);
+      st = enqueue_launches(b, b->stream, chunks, 0, depth, gpc);
       if (st != VCA_OK) break;
       if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
-      for (int r = 0; r < reps && st == VCA_OK; r++) st = enqueue_launches(b, b->stream, tiles, 0, depth, gpc);
+      for (int r = 0; r < reps && st == VCA_OK; r++) st = enqueue_launches(b, b->stream, chunks, 0, depth, gpc);
       if (st != VCA_OK) break;
       if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
         st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
