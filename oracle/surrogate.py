@@ -55,7 +55,7 @@ def energy_features(x: torch.Tensor, w: int = 32, k: int | None = None, bit_dept
     norm = 1.0 / (cy * w * w)
     E = Hb.sum(dim=(-2, -1)) * norm
     dh = (Hb[:, 1:] - Hb[:, :-1]).abs().sum(dim=(-2, -1)) * norm
-    h = torch.cat([torch.zeros_like(dh[:, :1]), dh], dim=1)
+    h = torch.cat([torch.zeros_like(E[:, :1]), dh], dim=1)     # no predecessor: h = 0
     return E, h
 
 

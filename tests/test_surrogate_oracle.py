@@ -81,3 +81,14 @@ def test_autograd_matches_central_differences(w, k):
         assert fd == pytest.approx(g[idx], rel=1e-5, abs=1e-12)
         checked += 1
     assert checked >= 30
+
+
+def test_single_frame_sequences_have_zero_h():
+    rng = np.random.default_rng(4)
+    x = frames(rng, 3, 1, 32, 64)
+    E, h = surrogate.energy_features(x, 16)
+    assert E.shape == h.shape == (3, 1)
+    assert (h == 0).all() and (E > 0).all()
+    _, _, g = surrogate.reference_gradient(x.numpy(), np.ones((3, 1)), np.ones((3, 1)), w=16)
+    _, _, g_e = surrogate.reference_gradient(x.numpy(), np.ones((3, 1)), np.zeros((3, 1)), w=16)
+    np.testing.assert_array_equal(g, g_e)      # h carries no gradient without a predecessor
