@@ -28,6 +28,7 @@ BLOCK = 32
 MAX_BATCH = 600                 # one forward launch per step
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 INT8_PEAK_TOPS = 5000.0         # MI355X dense int8 MFMA
+FP32_PEAK_TFLOPS = 157.3        # MI355X dense FP32 MFMA
 
 
 def log(msg: str) -> None:
@@ -174,6 +175,104 @@ def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
     }
 
 
+def run_backward(vca, steps: int, warmup: int) -> dict:
+    """Differentiable E_Y and h of 16 pairs of 1920x1080 8-bit-valued luma
+    frames cast to float32, w = 32: one step is the forward and the backward
+    through the autograd Function (dL/dx for given dL/dE, dL/dh).  Kernel
+    times come from HIP events around the two C-ABI calls on the stream they
+    are launched on; the plain integer path on the same frames (all seven
+    features from Y, U and V) is timed beside it."""
+    import ctypes
+    import torch
+    from paper_2304_12384_amd import _lib, grad
+    from synth.device import generated_scene_video
+    n_seq, seq_len, H, W, w = 16, 2, 1080, 1920, 32
+    n = n_seq * seq_len
+    dv = generated_scene_video(W, H, n, seed=4, scene_len=seq_len)
+    x = dv.y.float().reshape(n_seq, seq_len, H, W).contiguous().requires_grad_(True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(12384)
+    gE = torch.randn(n_seq, seq_len, device="cuda", generator=g)
+    gh = torch.randn(n_seq, seq_len, device="cuda", generator=g)
+
+    def step():
+        E, h = vca.energy_features(x, block_size=w)
+        return torch.autograd.grad((E, h), (x,), (gE, gh))[0]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gx = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    # the two C-ABI calls alone, preallocated buffers, events on their stream
+    L = _lib.lib()
+    xd = x.detach()
+    cfg = grad._config(xd, w, 0, 8)
+    ws = torch.empty(L.vca_grad_workspace(ctypes.byref(cfg)), device="cuda", dtype=torch.float64)
+    E = torch.empty(n, device="cuda")
+    h = torch.empty(n, device="cuda")
+    gxb = torch.empty_like(xd)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd_ms = bwd_ms = 0.0
+    reps = max(steps, 5)
+    for i in range(reps + 1):
+        ev[0].record(stream)
+        _lib.check(L.vca_energy_forward(ctypes.byref(cfg), xd.data_ptr(), E.data_ptr(), h.data_ptr(),
+                                        ws.data_ptr(), stream.cuda_stream), "vca_energy_forward")
+        ev[1].record(stream)
+        _lib.check(L.vca_energy_backward(ctypes.byref(cfg), xd.data_ptr(), ws.data_ptr(),
+                                         gE.data_ptr(), gh.data_ptr(), gxb.data_ptr(),
+                                         stream.cuda_stream), "vca_energy_backward")
+        ev[2].record(stream)
+        ev[2].synchronize()
+        if i > 0:                       # the first pass builds the operand tables
+            fwd_ms += ev[0].elapsed_time(ev[1]) / reps
+            bwd_ms += ev[1].elapsed_time(ev[2]) / reps
+    assert torch.equal(gxb, gx), "C-ABI backward differs from the autograd path"
+
+    an = vca.Analyzer(W, H, block_size=w, max_batch=n)
+    for _ in range(warmup):
+        an.features(an.submit(dv.y, dv.u, dv.v), n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        an.features(an.submit(dv.y, dv.u, dv.v), n)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    an.close()
+
+    blocks = (W // w) * (H // w) * n
+    flops_fwd = blocks * 2 * 2 * w ** 3            # Y = C X C^T
+    flops_bwd = blocks * 4 * 2 * w ** 3            # Y again, then C^T S C
+    bytes_fwd = blocks * w * w * 4                 # x read once
+    bytes_bwd = blocks * w * w * 8                 # x read, dL/dx written
+    fw_tf = flops_fwd / (fwd_ms * 1e-3) / 1e12
+    bw_tf = flops_bwd / (bwd_ms * 1e-3) / 1e12
+    return {
+        "value": steps * n / dt, "unit": "frames/s",
+        "workload": f"{n_seq} pairs of {W}x{H} float32 luma (8-bit values), w={w}, "
+                    "forward + backward of E_Y and h",
+        "ms_per_step": dt * 1e3 / steps,
+        "forward_kernel_ms": fwd_ms, "backward_kernel_ms": bwd_ms,
+        "roofline": {"bound": "mfma", "achieved": bw_tf, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": bw_tf / FP32_PEAK_TFLOPS, "traffic": None},
+        "backward_hbm": {"achieved": bytes_bwd / (bwd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s"},
+        "forward_mfma": {"achieved": fw_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": fw_tf / FP32_PEAK_TFLOPS},
+        "forward_hbm": {"achieved": bytes_fwd / (fwd_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s"},
+        "plain_same_frames": {"value": steps * n / dt_plain, "unit": "frames/s",
+                              "what": "integer path, all 7 features of the same frames (YUV)"},
+        "ratio_vs_plain": dt_plain / dt,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,8 +280,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-frames", type=int, default=64,
                     help="frames of the oracle's bounded CPU sample (0 skips it)")
-    ap.add_argument("--modes", default="full,lowpass,batch",
-                    help="comma list of full, lowpass, batch")
+    ap.add_argument("--modes", default="full,lowpass,batch,backward",
+                    help="comma list of full, lowpass, batch, backward")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -198,14 +297,15 @@ def main() -> int:
     import synth
     from synth.device import scene_to_device
 
-    log("generating the 600-frame 2160p synthetic workload")
-    sv = synth.scene_video(WIDTH, HEIGHT, FRAMES)
-    dev = scene_to_device(sv)
-    torch.cuda.synchronize()
-    log(f"frames resident on the device: {dev.nbytes / 1e9:.2f} GB")
-
     results = {}
     modes = args.modes.split(",")
+    sv = dev = None
+    if "full" in modes or "lowpass" in modes or args.cpu_frames > 0:
+        log("generating the 600-frame 2160p synthetic workload")
+        sv = synth.scene_video(WIDTH, HEIGHT, FRAMES)
+        dev = scene_to_device(sv)
+        torch.cuda.synchronize()
+        log(f"frames resident on the device: {dev.nbytes / 1e9:.2f} GB")
     for mode in (m for m in modes if m in ("full", "lowpass")):
         k = 0 if mode == "full" else 16
         log(f"timing mode={mode} steps={args.steps} warmup={args.warmup}")
@@ -221,13 +321,21 @@ def main() -> int:
         log(f"batched: {batch['value']:.0f} frames/s over {batch['streams']} streams, "
             f"{batch['speedup_vs_plain']:.2f}x the plain path")
 
+    backward = None
+    if "backward" in modes:
+        torch.cuda.empty_cache()
+        log("timing the backward form")
+        backward = run_backward(vca, max(3, args.steps // 2), 2)
+        log(f"backward: {backward['value']:.0f} frames/s forward+backward, kernels "
+            f"{backward['forward_kernel_ms']:.3f} + {backward['backward_kernel_ms']:.3f} ms")
+
     cpu = None
     if args.cpu_frames > 0:
         log(f"timing the CPU oracle on {args.cpu_frames} frames")
         cpu = cpu_baseline(sv, args.cpu_frames)
 
     if not results:
-        print(json.dumps({"metric": METRIC, "batched": batch}), flush=True)
+        print(json.dumps({"metric": METRIC, "batched": batch, "backward": backward}), flush=True)
         return 0
     head = results.get("full") or next(iter(results.values()))
     line = {
@@ -262,6 +370,8 @@ def main() -> int:
                                "launch": lp["launch"]}
     if batch is not None:
         line["batched"] = batch
+    if backward is not None:
+        line["backward"] = backward
     print(json.dumps(line), flush=True)
     return 0
 

@@ -223,6 +223,56 @@ const char* vca_batch_last_error(const vca_batch* b);
 /* Waits for outstanding work and frees the batch.  NULL-safe. */
 void vca_close_batch(vca_batch* b);
 
+/* ---------------------------------------------------------- backward form
+ * Differentiable luma texture energy E_Y and its gradient h (Section 2
+ * names both features) for training pre-processing filters toward a target
+ * complexity.  The rounding of the two transform passes is dropped so that
+ * the features are piecewise linear in the samples: per w x w block X of a
+ * float luma plane,
+ *   Y = C_w X C_w^T * 2^-(2 log2 w + B - 3)  (the unrounded composition of
+ *       the two integer passes above; B = bit_depth fixes only the scale),
+ *   H = sum W_ik |Y[i][k]| over (i,k) != (0,0), i,k < K,
+ *   E_t = sum_blocks H_t / (C_Y w^2),
+ *   h_t = sum_blocks |H_t - H_{t-1}| / (C_Y w^2), h = 0 at a sequence start,
+ * and dH/dX = 2^-(2 log2 w + B - 3) C_w^T (W o sign(Y)) C_w, sign(0) = 0.
+ * The transforms run in FP32 (MFMA), block energies and the per-frame sums
+ * in FP64.  Input: n_seq sequences of seq_len consecutive float32 frames. */
+typedef struct {
+  uint32_t struct_size; /* = sizeof(vca_grad_config)                                   */
+  int32_t width;        /* luma width; >= block_size                                   */
+  int32_t height;       /* luma height; >= block_size                                  */
+  int32_t block_size;   /* w: 8, 16 or 32                                              */
+  int32_t lowpass_k;    /* 0 or w: full; else K in {w/2, w/4}                          */
+  int32_t bit_depth;    /* 8 or 10: B of the scale above                               */
+  int32_t n_seq;        /* sequences (h restarts at each); n_seq * seq_len <= 65535    */
+  int32_t seq_len;      /* frames per sequence                                         */
+  int32_t device;       /* HIP device ordinal                                          */
+  int64_t pitch;        /* floats between rows (>= width, multiple of 4)               */
+  int64_t fstride;      /* floats between consecutive frames (multiple of 4)           */
+} vca_grad_config;
+
+/* Doubles of device workspace the two calls below need (the FP64 block
+ * energies of every frame), or -1 for an invalid configuration.  Host only. */
+int64_t vca_grad_workspace(const vca_grad_config* cfg);
+
+/* Forward: reads x (device, 16-byte aligned, cfg's layout), writes E[f] and
+ * h[f] (device, n_seq * seq_len floats each, frame f = s * seq_len + t) and
+ * the block energies into workspace (device, vca_grad_workspace doubles;
+ * keep it for vca_energy_backward).  Enqueued on hip_stream (NULL: the
+ * default stream); returns without waiting. */
+vca_status vca_energy_forward(const vca_grad_config* cfg, const float* x, float* E, float* h,
+                              double* workspace, void* hip_stream);
+
+/* Backward: given dL/dE and dL/dh per frame (device, n_seq * seq_len floats)
+ * and the workspace of the forward call on the same x, writes dL/dx to
+ * grad_x (device, 16-byte aligned, the same layout as x); every sample within
+ * width x height of every frame is written (0 outside the block grid), the
+ * pitch padding is not touched.  Enqueued on hip_stream; returns without
+ * waiting. */
+vca_status vca_energy_backward(const vca_grad_config* cfg, const float* x, const double* workspace,
+                               const float* grad_E, const float* grad_h, float* grad_x,
+                               void* hip_stream);
+
 /* Static string naming a status code. */
 const char* vca_status_str(vca_status s);
 

@@ -7,5 +7,7 @@ behind the C ABI in include/vca.h.
 """
 from ._lib import VcaError, EXPORTS, LIB_PATH
 from .analyzer import Analyzer, Batch, FEATURE_NAMES, block_counts
+from .grad import VCAEnergyFn, energy_features
 
-__all__ = ["Analyzer", "Batch", "FEATURE_NAMES", "block_counts", "VcaError", "EXPORTS", "LIB_PATH"]
+__all__ = ["Analyzer", "Batch", "FEATURE_NAMES", "block_counts", "VcaError", "EXPORTS", "LIB_PATH",
+           "VCAEnergyFn", "energy_features"]

@@ -30,6 +30,7 @@ EXPORTS = (
     "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_tune_batch",
     "vca_batch_tuned_launch", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
     "vca_batch_last_error", "vca_close_batch",
+    "vca_grad_workspace", "vca_energy_forward", "vca_energy_backward",
 )
 
 
@@ -60,6 +61,15 @@ class VcaTiming(ctypes.Structure):
     _fields_ = [("forward_ms", ctypes.c_double), ("reduce_ms", ctypes.c_double),
                 ("forward_launches", ctypes.c_int64), ("reduce_launches", ctypes.c_int64),
                 ("frames", ctypes.c_int64)]
+
+
+class VcaGradConfig(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("block_size", ctypes.c_int32), ("lowpass_k", ctypes.c_int32),
+        ("bit_depth", ctypes.c_int32), ("n_seq", ctypes.c_int32), ("seq_len", ctypes.c_int32),
+        ("device", ctypes.c_int32), ("pitch", ctypes.c_int64), ("fstride", ctypes.c_int64),
+    ]
 
 
 class VcaError(RuntimeError):
@@ -103,6 +113,9 @@ def lib() -> ctypes.CDLL:
             "vca_close_batch": (None, [P]),
             "vca_frames_submitted": (ctypes.c_int64, [P]),
             "vca_close": (None, [P]),
+            "vca_grad_workspace": (ctypes.c_int64, [ctypes.POINTER(VcaGradConfig)]),
+            "vca_energy_forward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P]),
+            "vca_energy_backward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P, P]),
             "vca_status_str": (ctypes.c_char_p, [ctypes.c_int]),
             "vca_last_error": (ctypes.c_char_p, [P]),
         }

@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", n) for n in ("vca.hip", "vca_batch.hip")]
+SRCS = [os.path.join(HERE, "csrc", n) for n in ("vca.hip", "vca_batch.hip", "vca_grad.hip")]
 LIB = os.path.join(HERE, "libvca.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -90,3 +90,49 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def grad_cfg(**kw):
+    base = dict(width=1920, height=1080, block_size=32, lowpass_k=0, bit_depth=8, n_seq=16,
+                seq_len=2, device=0, pitch=1920, fstride=1920 * 1080)
+    base.update(kw)
+    c = _lib.VcaGradConfig()
+    c.struct_size = base.pop("struct_size", ctypes.sizeof(_lib.VcaGradConfig))
+    for k, v in base.items():
+        setattr(c, k, v)
+    return c
+
+
+def test_grad_config_layout_and_workspace():
+    assert ctypes.sizeof(_lib.VcaGradConfig) == 56
+    L = _lib.lib()
+    assert L.vca_grad_workspace(ctypes.byref(grad_cfg())) == 60 * 33 * 32
+    assert L.vca_grad_workspace(ctypes.byref(grad_cfg(block_size=8, lowpass_k=2, n_seq=1,
+                                                      seq_len=3))) == 240 * 135 * 3
+
+
+@pytest.mark.parametrize("bad", [
+    dict(block_size=4), dict(lowpass_k=3), dict(lowpass_k=64), dict(bit_depth=12),
+    dict(width=16), dict(n_seq=0), dict(seq_len=0), dict(pitch=1000), dict(pitch=1922),
+    dict(fstride=1920 * 1000), dict(fstride=1922), dict(n_seq=40000, seq_len=2),
+    dict(struct_size=40), dict(device=-1)])
+def test_bad_grad_config_rejected_before_device(bad):
+    c = grad_cfg(**bad)
+    L = _lib.lib()
+    assert L.vca_grad_workspace(ctypes.byref(c)) == -1
+    p = ctypes.c_void_p(1 << 20)   # never dereferenced: the configuration fails first
+    assert L.vca_energy_forward(ctypes.byref(c), p, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), p, p, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+
+
+def test_grad_null_and_misaligned_arguments():
+    L = _lib.lib()
+    c = grad_cfg()
+    p = ctypes.c_void_p(1 << 20)
+    odd = ctypes.c_void_p((1 << 20) + 4)
+    assert L.vca_grad_workspace(None) == -1
+    assert L.vca_energy_forward(ctypes.byref(c), None, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_forward(ctypes.byref(c), odd, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_forward(ctypes.byref(c), p, p, p, None, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), p, p, p, p, odd, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), p, None, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG

@@ -1,0 +1,164 @@
+"""Backward form: the HIP forward (E_Y, h) and backward (dL/dx) of the
+unrounded luma surrogate against the FP64 oracle surrogate -- its features,
+its float64 autograd gradient, and central finite differences (step 1e-2)."""
+import numpy as np
+import pytest
+
+from oracle import surrogate
+from synth.device import generated_scene_video
+from tests.gpu_util import print_case
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+E_RTOL = 1e-5          # E against FP64: the FP32 transform is exact up to one rounding
+GRAD_RTOL = 1e-4       # dL/dx: FP32 sums of up to w^2 signed terms per pixel
+GRAD_ATOL = 1e-5       # ... relative to the largest reference gradient
+
+
+@pytest.fixture(scope="module")
+def vca():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2304_12384_amd as vca_mod
+    return vca_mod
+
+
+def mixed_frames(n_seq, seq_len, height, width, seed, bit_depth=8, w=32):
+    """Integer-valued float frames: noise texture, a flat region and a linear
+    ramp (both give exactly-zero coefficients), a region repeated from the
+    previous frame (zero block-energy change), and motion elsewhere."""
+    rng = np.random.default_rng(seed)
+    top = (1 << bit_depth) - 1
+    x = rng.integers(0, top + 1, size=(n_seq, seq_len, height, width)).astype(np.float64)
+    q = max(w, (width // 4) // w * w)      # block-aligned regions
+    assert 3 * q <= width
+    x[..., :, :q] = float(top // 3)
+    ramp = np.arange(height)[:, None] * 3 + np.arange(q)[None, :] * 2
+    x[..., :, q:2 * q] = np.minimum(ramp, top)
+    x[:, 1:, :, 2 * q:3 * q] = x[:, :1, :, 2 * q:3 * q]
+    return x
+
+
+def check_features(E, h, x64, w, k, bit_depth):
+    Er, hr = surrogate.energy_features(torch.tensor(x64), w, k or None, bit_depth)
+    Er, hr = Er.numpy(), hr.numpy()
+    E = E.detach().cpu().double().numpy()
+    h = h.detach().cpu().double().numpy()
+    np.testing.assert_allclose(E, Er, rtol=E_RTOL, atol=0)
+    # h is a sum of |differences|: the FP32 error of each block energy (one
+    # rounding of Y) is bounded relative to E, not to h.
+    np.testing.assert_allclose(h, hr, rtol=E_RTOL, atol=1e-6 * Er.max())
+    assert (h[:, 0] == 0).all()
+    return Er, hr
+
+
+def check_gradient(g, gr):
+    g = g.detach().cpu().double().numpy()
+    np.testing.assert_allclose(g, gr, rtol=GRAD_RTOL, atol=GRAD_ATOL * np.abs(gr).max())
+
+
+CASES = [
+    # (n_seq, seq_len, height, width, w, K, bit depth)
+    (2, 3, 136, 200, 32, 0, 8),     # partial tiles, ragged border rows and columns
+    (1, 4, 104, 176, 16, 8, 8),
+    (2, 2, 72, 104, 8, 0, 10),
+    (1, 3, 128, 128, 32, 16, 8),
+    (1, 2, 64, 72, 8, 2, 8),
+    (3, 1, 64, 96, 16, 0, 10),      # single-frame sequences: h = 0, no h gradient
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_forward_and_backward_match_fp64_autograd(vca, case):
+    n_seq, seq_len, H, W, w, k, B = case
+    print_case(test="backward", shape=(n_seq, seq_len, H, W), w=w, K=k, bits=B)
+    x64 = mixed_frames(n_seq, seq_len, H, W, seed=17 + CASES.index(case), bit_depth=B, w=w)
+    rng = np.random.default_rng(7)
+    gE = rng.normal(size=(n_seq, seq_len))
+    gh = rng.normal(size=(n_seq, seq_len))
+    x = torch.tensor(x64, dtype=torch.float32, device="cuda", requires_grad=True)
+    E, h = vca.energy_features(x, block_size=w, lowpass_k=k, bit_depth=B)
+    check_features(E, h, x64, w, k, B)
+    loss = (E * torch.tensor(gE, dtype=torch.float32, device="cuda")).sum() + \
+           (h * torch.tensor(gh, dtype=torch.float32, device="cuda")).sum()
+    loss.backward()
+    _, _, gr = surrogate.reference_gradient(x64, gE, gh, w=w, k=k or None, bit_depth=B)
+    check_gradient(x.grad, gr)
+    # outside the block grid the gradient is exactly zero
+    g = x.grad.cpu().numpy()
+    assert (g[..., (H // w) * w:, :] == 0).all() and (g[..., :, (W // w) * w:] == 0).all()
+
+
+def test_unaligned_width_and_strided_input(vca):
+    """A row length that is not a multiple of 4 floats goes through a padded
+    copy; gradients come back in the caller's shape."""
+    print_case(test="backward_unaligned")
+    x64 = mixed_frames(1, 2, 64, 70, seed=5, w=16)
+    x = torch.tensor(x64, dtype=torch.float32, device="cuda", requires_grad=True)
+    E, h = vca.energy_features(x, block_size=16)
+    (E.sum() + 2 * h.sum()).backward()
+    _, _, gr = surrogate.reference_gradient(x64, np.ones((1, 2)), 2 * np.ones((1, 2)), w=16)
+    assert x.grad.shape == x.shape
+    check_gradient(x.grad, gr)
+
+
+def local_loss(xblk_f, H_prev, H_next, gE_f, gh_f, gh_n, norm, w):
+    """The part of sum(gE E + gh h) that depends on one block of frame f."""
+    Hf = float(surrogate.block_energies(torch.tensor(xblk_f), w).reshape(()))
+    out = gE_f * Hf
+    if H_prev is not None:
+        out += gh_f * abs(Hf - H_prev)
+    if H_next is not None:
+        out += gh_n * abs(H_next - Hf)
+    return out * norm
+
+
+def test_frame_pairs_1080p(vca):
+    """16 pairs of 1920x1080 8-bit-valued frames, w = 32: features and the
+    whole gradient against FP64 autograd, and the gradient at 64 random
+    pixels against central differences (step 1e-2) of the FP64 surrogate."""
+    n_seq, seq_len, H, W, w = 16, 2, 1080, 1920, 32
+    print_case(test="backward_1080p_pairs", shape=(n_seq, seq_len, H, W))
+    dv = generated_scene_video(W, H, n_seq * seq_len, seed=4, scene_len=seq_len)
+    x = dv.y.float().reshape(n_seq, seq_len, H, W).contiguous().requires_grad_(True)
+    x64 = x.detach().cpu().double().numpy()
+    rng = np.random.default_rng(11)
+    gE = rng.normal(size=(n_seq, seq_len))
+    gh = rng.normal(size=(n_seq, seq_len))
+    E, h = vca.energy_features(x, block_size=w)
+    check_features(E, h, x64, w, 0, 8)
+    ((E * torch.tensor(gE, dtype=torch.float32, device="cuda")).sum() +
+     (h * torch.tensor(gh, dtype=torch.float32, device="cuda")).sum()).backward()
+    g = x.grad.detach().cpu().double().numpy()
+    _, _, gr = surrogate.reference_gradient(x64, gE, gh, w=w)
+    check_gradient(x.grad, gr)
+
+    Hb = surrogate.block_energies(torch.tensor(x64), w).numpy()   # [n_seq, seq_len, nby, nbx]
+    norm = 1.0 / (Hb.shape[-1] * Hb.shape[-2] * w * w)
+    d = 1e-2
+    checked = tried = 0
+    while checked < 64:
+        tried += 1
+        assert tried < 2000, f"only {checked} kink-free pixels in {tried}"
+        s, t = int(rng.integers(n_seq)), int(rng.integers(seq_len))
+        r, c = int(rng.integers((H // w) * w)), int(rng.integers(W))
+        by, bx = r // w, c // w
+        blk = x64[s, t, by * w:(by + 1) * w, bx * w:(bx + 1) * w].copy()
+        H_prev = Hb[s, t - 1, by, bx] if t > 0 else None
+        H_next = Hb[s, t + 1, by, bx] if t + 1 < seq_len else None
+        gh_n = gh[s, t + 1] if t + 1 < seq_len else 0.0
+
+        def L(delta):
+            b = blk.copy()
+            b[r % w, c % w] += delta
+            return local_loss(b, H_prev, H_next, gE[s, t], gh[s, t], gh_n, norm, w)
+
+        fd = (L(d) - L(-d)) / (2 * d)
+        fd_half = (L(d / 2) - L(-d / 2)) / d
+        # piecewise linear in one pixel: skip a kink strictly inside the step
+        if abs(fd - fd_half) > 1e-7 * abs(fd) + 1e-24:
+            continue
+        assert g[s, t, r, c] == pytest.approx(fd, rel=GRAD_RTOL, abs=GRAD_ATOL * np.abs(gr).max())
+        checked += 1
