@@ -145,7 +145,8 @@ vca_status vca_get_timing(vca_ctx* ctx, vca_timing* out, int32_t reset);
 
 /* Autotuner of the launch shape: times the forward kernel on the given
  * frames (at most max_batch of them) for every candidate -- tiles in flight
- * per wavefront 1..3 times workgroups per compute unit 1..(as many as fit) --
+ * per wavefront 1, 2 or 4 times workgroups per compute unit 1..(as many as
+ * fit) --
  * with `reps` timed launches each, and keeps the fastest for this context.
  * The choice is also cached for the process (and in the text file named by
  * the environment variable VCA_TUNE_CACHE, if set) under the key (device,

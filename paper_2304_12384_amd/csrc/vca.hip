@@ -36,6 +36,20 @@ namespace {
 constexpr int kWavesPerGroup = 4;   // wavefronts per workgroup
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
 constexpr int kDefaultDepth = 2;    // tiles in flight per wavefront when untuned
+constexpr int kStrip = 8;           // tiles per strip (work unit of the strip kernel)
+
+// One plane as the strip kernel sees it (read with scalar loads, once per
+// strip, from the kernel argument block).
+struct StripPlane {
+  const uint8_t* plane;
+  int64_t fstride;
+  int32_t pitch;
+  int32_t nbx, nby, ntx;
+  int32_t spr;             // strips per tile row
+  int32_t scnt;            // strips per plane
+  int32_t boff;            // index of the plane's first block within a frame
+  FastDiv div_spr;         // / spr
+};
 
 struct FwdParams {
   const uint8_t* plane[3];
@@ -50,6 +64,10 @@ struct FwdParams {
   FastDiv div_tpf;         // / tiles_per_frame
   FastDiv div_ntx[3];      // / ntx[P]
   int32_t n_frames;
+  // strips: runs of up to kStrip consecutive tiles of one tile row
+  StripPlane sp[3];
+  int32_t strips_per_frame;
+  FastDiv div_spf;         // / strips_per_frame
   const v4i* tab_b1;
   const v4i* tab_a2;
   const double* tab_w;
@@ -119,6 +137,178 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
   }
 }
 
+// ------------------------------------------------------------ strip kernel
+// Work unit: a strip of up to kStrip consecutive tiles of one tile row of one
+// plane of one frame, so that tile ids are decoded once per strip and the
+// tiles of a strip sit side by side in memory (and, for w = 32, in the
+// output).  Strips are dealt to wavefronts round-robin.
+
+struct StripWork {
+  const uint8_t* base;  // first sample of the strip's first tile
+  int32_t pitch;
+  int32_t n;            // tiles in the strip, 1..kStrip
+  int32_t out0;         // output index of block (0, 0) of the first tile
+  int32_t out_row;      // output index step between block rows
+  int32_t vr;           // block rows of the strip inside the grid
+  int32_t vc_last;      // block columns of the last tile inside the grid
+};
+
+template <int kBits, int kW>
+__device__ inline StripWork decode_strip(const FwdParams& p, int id) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kBpt = kTile / kW;
+  const int f = (int)fastdiv((uint32_t)id, p.div_spf);
+  int r = id - f * p.strips_per_frame;
+  int P = 0;
+  if (r >= p.sp[0].scnt) {
+    r -= p.sp[0].scnt;
+    P = 1;
+    if (r >= p.sp[1].scnt) {
+      r -= p.sp[1].scnt;
+      P = 2;
+    }
+  }
+  const StripPlane& pl = p.sp[P];
+  const int ty = (int)fastdiv((uint32_t)r, pl.div_spr);
+  const int tx0 = (r - ty * pl.spr) * kStrip;
+  StripWork w;
+  w.pitch = pl.pitch;
+  w.n = min(kStrip, pl.ntx - tx0);
+  const int by0 = ty * kBpt, bx0 = tx0 * kBpt;
+  w.base = pl.plane + f * pl.fstride + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
+  w.vr = min(kBpt, pl.nby - by0);
+  w.vc_last = min(kBpt, pl.nbx - (tx0 + w.n - 1) * kBpt);
+  w.out0 = f * p.per_frame + pl.boff + by0 * pl.nbx + bx0;
+  w.out_row = pl.nbx;
+  return w;
+}
+
+// Byte offsets of a lane's samples inside the tiles of a strip (scalar tile
+// base + 32-bit lane offset keeps every load in the saddr form): `a` (and,
+// for 10-bit, `b`) for full tiles, and the same for the strip's last tile,
+// whose columns outside the block grid are redirected like load_tile does.
+struct LaneOffsets {
+  uint32_t a, b, last_a, last_b;
+};
+
+template <int kBits, int kW>
+__device__ inline LaneOffsets lane_offsets(const StripWork& s, int lane) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  const int r = lane & 31, g = lane >> 5;
+  const int rows = s.vr * kW;
+  const uint32_t roff = __umul24((uint32_t)(kW == 32 || r < rows ? r : 0), (uint32_t)s.pitch);
+  LaneOffsets o;
+  o.a = roff + 16 * g * kBps;
+  o.b = o.a + 16;
+  if (kW == 32) {            // a w = 32 tile is one complete block
+    o.last_a = o.a;
+    o.last_b = o.b;
+  } else {
+    const int cols = s.vc_last * kW;
+    const int c0 = 16 * g < cols ? 16 * g : 0;
+    const int c1 = 16 * g + 8 < cols ? 16 * g + 8 : c0;
+    o.last_a = roff + c0 * kBps;
+    o.last_b = roff + c1 * kBps;
+  }
+  return o;
+}
+
+template <int kBits, int kW>
+__device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, int t) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  const uint8_t* base = s.base + t * kTile * kBps;
+  const bool last = kW != 32 && t == s.n - 1;
+  TileData d;
+  d.a = *reinterpret_cast<const v4i*>(base + (last ? o.last_a : o.a));
+  if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(base + (last ? o.last_b : o.b));
+  return d;
+}
+
+template <int kBits, int kW>
+__device__ inline TileWork strip_tile(const StripWork& s, int t) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kBpt = kTile / kW;
+  TileWork w;
+  w.base = s.base + t * kTile * kBps;
+  w.pitch = s.pitch;
+  w.vr = s.vr;
+  w.vc = t == s.n - 1 ? s.vc_last : kBpt;
+  w.out0 = s.out0 + t * kBpt;
+  w.out_row = s.out_row;
+  return w;
+}
+
+// Persistent forward kernel over strips.  Each wavefront keeps kDepth tiles
+// in flight: while it transforms tile t of its strip it has issued the loads
+// of tile t + kDepth, which may be the next strip's (kStrip % kDepth == 0, so
+// ring slots line up across strips).  For w = 32 the eight tiles' FP64
+// energy shares are reduced together at the end of the strip and stored by
+// eight lanes; w = 16 and 8 reduce each tile over the lanes of its block
+// columns.
+template <int kBits, int kW, int kK, int kDepth>
+__global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
+  static_assert(kStrip % kDepth == 0, "ring slots must line up across strips");
+  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  TileConsts<kW, kK> tc;
+  tc.load(p.tab_b1, p.tab_a2, p.tab_w, lane);
+
+  const int total = p.n_frames * p.strips_per_frame;
+  const int stride = gridDim.x * kWavesPerGroup;
+  int id = blockIdx.x * kWavesPerGroup + wave;
+  if (id >= total) return;
+  StripWork S = decode_strip<kBits, kW>(p, id);
+  LaneOffsets O = lane_offsets<kBits, kW>(S, lane);
+  TileData ring[kDepth];
+#pragma unroll
+  for (int t = 0; t < kDepth; t++)
+    if (t < S.n) ring[t] = strip_load<kBits, kW>(S, O, t);
+
+  while (true) {
+    const int id2 = id + stride;
+    const bool more = id2 < total;
+    StripWork S2{};
+    LaneOffsets O2{};
+    if (more) {
+      S2 = decode_strip<kBits, kW>(p, id2);
+      O2 = lane_offsets<kBits, kW>(S2, lane);
+    }
+    double hs[kStrip];
+#pragma unroll
+    for (int t = 0; t < kStrip; t++) {
+      TileData d;
+      if (t < S.n) d = ring[t % kDepth];
+      const int u = t + kDepth;   // the tile whose loads go out now
+      if (u < kStrip) {
+        if (u < S.n) ring[t % kDepth] = strip_load<kBits, kW>(S, O, u);
+      } else if (more && u - kStrip < S2.n) {
+        ring[t % kDepth] = strip_load<kBits, kW>(S2, O2, u - kStrip);
+      }
+      if (kW == 32) {
+        if (t < S.n) {
+          int dc = 0;
+          hs[t] = tile_energy32<kBits, kK>(p.out, tc, d, dc);
+          if (lane == 0) p.out.blk_dc[S.out0 + t] = dc + kDcAdd;
+        } else {
+          hs[t] = 0.0;
+        }
+      } else if (t < S.n) {
+        fwd_tile<kBits, kW, kK, false>(p.out, tc, d, strip_tile<kBits, kW>(S, t), lane);
+      }
+    }
+    if (kW == 32) {
+      const double h = reduce_scatter8(hs, lane);
+      const int t = lane >> 3;
+      if ((lane & 7) == 0 && t < S.n) p.out.blk_h[S.out0 + t] = h;
+    }
+    if (!more) break;
+    id = id2;
+    S = S2;
+    O = O2;
+  }
+}
+
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) {
   reduce_frame(p, blockIdx.x);
 }
@@ -130,9 +320,9 @@ using FwdKernel = void (*)(FwdParams);
 template <int B, int W, int K>
 FwdKernel pick_depth(bool keep, int depth) {
   if (keep) return fwd_kernel<B, W, K, true, 1>;
-  if (depth == 1) return fwd_kernel<B, W, K, false, 1>;
-  if (depth == 3) return fwd_kernel<B, W, K, false, 3>;
-  return fwd_kernel<B, W, K, false, 2>;
+  if (depth == 1) return strip_kernel<B, W, K, 1>;
+  if (depth == 4) return strip_kernel<B, W, K, 4>;
+  return strip_kernel<B, W, K, 2>;
 }
 
 template <int B, int W>
@@ -233,7 +423,20 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
     fp.tcnt[P] = g.tcnt[P];
     fp.boff[P] = g.boff[P];
     fp.div_ntx[P] = make_fastdiv((uint32_t)g.ntx[P]);
+    StripPlane& sp = fp.sp[P];
+    sp.plane = fp.plane[P];
+    sp.fstride = fs[P];
+    sp.pitch = (int32_t)pt[P];
+    sp.nbx = g.nbx[P];
+    sp.nby = g.nby[P];
+    sp.ntx = g.ntx[P];
+    sp.spr = (g.ntx[P] + kStrip - 1) / kStrip;
+    sp.scnt = sp.spr * (g.tcnt[P] / g.ntx[P]);
+    sp.boff = g.boff[P];
+    sp.div_spr = make_fastdiv((uint32_t)sp.spr);
   }
+  fp.strips_per_frame = fp.sp[0].scnt + fp.sp[1].scnt + fp.sp[2].scnt;
+  fp.div_spf = make_fastdiv((uint32_t)fp.strips_per_frame);
   fp.tiles_per_frame = g.tiles_per_frame;
   fp.per_frame = g.per_frame;
   fp.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
@@ -260,7 +463,8 @@ vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_p
   HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0));
   resident = std::max(1, resident);
   if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
-  const int64_t waves = (int64_t)fp.n_frames * fp.tiles_per_frame;
+  const int64_t waves = keep ? (int64_t)fp.n_frames * fp.tiles_per_frame
+                             : (int64_t)fp.n_frames * fp.strips_per_frame;
   const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);
@@ -472,7 +676,7 @@ vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_
   LaunchChoice best;
   best.ms = 1e30;
   vca_status st = VCA_OK;
-  for (int depth = 1; depth <= 3 && st == VCA_OK; depth++) {
+  for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
     int resident = 0;
     FwdKernel kern = select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, depth);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0) != hipSuccess)

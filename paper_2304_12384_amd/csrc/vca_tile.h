@@ -192,23 +192,20 @@ struct TileOut {
   int32_t validate;
 };
 
-// Transform, energies and DC of one tile.  Exact split of the
-// horizontal-pass result T (-2^14 <= T < 2^15 for every w and B):
+// Both passes of one tile.  Exact split of the horizontal-pass result T
+// (-2^14 <= T < 2^15 for every w and B):
 //   T = 256 T_hi + u,  T_hi = T >> 8 in [-64, 127],  u = T & 255,
 // C T = 256 C T_hi + C (u - 128) + 128 C 1, the last term being 128 * 64 w
 // on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
 // scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
 // accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
-// Consts: TileConsts<kW, kK>, or TileConsts<8, 8> (all registers loaded)
-// when one wavefront serves tiles of several block sizes.
-template <int kBits, int kW, int kK, bool kKeep, class Consts>
-__device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, const TileData& d,
-                                         const TileWork& t, int lane) {
+// Returns the hi and lo accumulators: Y = (256 dh + dl) >> s2 (+128 on each
+// block's row 0).
+template <int kBits, int kW, class Consts>
+__device__ __forceinline__ void tile_transform(const TileOut& o, const Consts& tc, const TileData& d,
+                                               v16i& dh, v16i& dl) {
   constexpr int kS1 = ilog2c(kW) + kBits - 9;
   constexpr int kS2 = ilog2c(kW) + 6;
-  constexpr int kBpt = kTile / kW;
-  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;   // 8-bit samples are offset by -128
-  const int g = lane >> 5, r = lane & 31;
   v16i c1, c2;
 #pragma unroll
   for (int j = 0; j < 16; j++) {
@@ -265,8 +262,22 @@ __device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, con
     tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
     thi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
   }
-  const v16i dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, thi, c2, 0, 0, 0);
-  const v16i dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, tlo, zero, 0, 0, 0);
+  dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, thi, c2, 0, 0, 0);
+  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, tlo, zero, 0, 0, 0);
+}
+
+// Transform, energies and DC of one tile, reduced and stored per block.
+// Consts: TileConsts<kW, kK>, or TileConsts<8, 8> (all registers loaded)
+// when one wavefront serves tiles of several block sizes.
+template <int kBits, int kW, int kK, bool kKeep, class Consts>
+__device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, const TileData& d,
+                                         const TileWork& t, int lane) {
+  constexpr int kS2 = ilog2c(kW) + 6;
+  constexpr int kBpt = kTile / kW;
+  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;   // 8-bit samples are offset by -128
+  const int g = lane >> 5, r = lane & 31;
+  v16i dh, dl;
+  tile_transform<kBits, kW>(o, tc, d, dh, dl);
 
   // FP64 energy per block row (two partial sums when the tile is one block).
   constexpr int kAcc = kBpt == 1 ? 2 : kBpt;
@@ -326,6 +337,90 @@ __device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, con
       }
     }
   }
+}
+
+// ------------------------------------------------------- w = 32 strips
+// A 32 x 32 tile is one block: its energy is a sum over all 64 lanes.  The
+// functions below leave each lane's FP64 share, and reduce the shares of
+// eight tiles at once.
+
+// Lane share of the block energy of one w = 32 tile; the block's DC (without
+// the 8-bit offset) is returned in dc of lane 0.
+template <int kBits, int kK, class Consts>
+__device__ __forceinline__ double tile_energy32(const TileOut& o, const Consts& tc,
+                                                const TileData& d, int& dc) {
+  constexpr int kS2 = ilog2c(32) + 6;
+  v16i dh, dl;
+  tile_transform<kBits, 32>(o, tc, d, dh, dl);
+  double h0 = 0.0, h1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    if (!reg_used(j, 32, kK)) continue;
+    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
+    if (j == 0) {
+      yv += tc.row0_fix;   // row 0 lives in register 0 of lanes g = 0
+      dc = yv;
+    }
+    if (j & 1)
+      h1 = fma(tc.wt[j], fabs((double)yv), h1);
+    else
+      h0 = fma(tc.wt[j], fabs((double)yv), h0);
+  }
+  return h0 + h1;
+}
+
+__device__ inline uint32_t lo32(double v) { return (uint32_t)__double_as_longlong(v); }
+__device__ inline uint32_t hi32(double v) { return (uint32_t)(__double_as_longlong(v) >> 32); }
+__device__ inline double mk64(uint32_t hi, uint32_t lo) {
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// a + b after exchanging the upper 32 lanes of a with the lower 32 lanes of
+// b: lanes 0..31 get the two-half sum of a, lanes 32..63 that of b.
+__device__ inline double fold32(double a, double b) {
+  const auto l = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+  return mk64(h[0], l[0]) + mk64(h[1], l[1]);
+}
+
+// The same over 16-lane rows: odd rows of a swap with even rows of b; lanes
+// with bit 4 clear get the row-pair sum of a, the others that of b.
+__device__ inline double fold16(double a, double b) {
+  const auto l = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+  return mk64(h[0], l[0]) + mk64(h[1], l[1]);
+}
+
+// v read from another lane of the same 16-lane row through DPP.
+template <int kCtrl>
+__device__ inline double dpp64(double v) {
+  const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo32(v), kCtrl, 0xf, 0xf, false);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi32(v), kCtrl, 0xf, 0xf, false);
+  return mk64(h, l);
+}
+
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within each 8 lanes
+constexpr int kDppRor8 = 0x128;        // lane i <- lane (i + 8) mod 16 in its row
+
+// Sums v[t] over all 64 lanes for t = 0..7; lane l receives the total of
+// tile l >> 3 (every lane of each group of eight holds it).
+__device__ inline double reduce_scatter8(const double (&v)[8], int lane) {
+  // halves: lanes < 32 keep tiles 0..3, the others 4..7
+  const double a0 = fold32(v[0], v[4]), a1 = fold32(v[1], v[5]);
+  const double a2 = fold32(v[2], v[6]), a3 = fold32(v[3], v[7]);
+  // rows: bit 4 of the lane picks tile pair (0, 1) or (2, 3) of the half
+  const double b0 = fold16(a0, a2), b1 = fold16(a1, a3);
+  // bit 3 picks the tile; its partner 8 lanes away sends the other one
+  const bool odd = (lane & 8) != 0;
+  const double keep = odd ? b1 : b0, send = odd ? b0 : b1;
+  double c = keep + dpp64<kDppRor8>(send);
+  // all eight lanes of the group
+  c += dpp64<kDppXor1>(c);
+  c += dpp64<kDppXor2>(c);
+  c += dpp64<kDppHalfMirror>(c);
+  return c;
 }
 
 }  // namespace vca

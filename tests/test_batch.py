@@ -133,7 +133,7 @@ def test_plain_tune(vca, frames):
     d = STREAMS[5]
     an = vca.Analyzer(d["width"], d["height"], block_size=d["block_size"])
     choice = an.tune(*frames[5], reps=1)
-    assert 1 <= choice["depth"] <= 3 and choice["groups_per_cu"] >= 1
+    assert choice["depth"] in (1, 2, 4) and choice["groups_per_cu"] >= 1
     an.submit(*frames[5])
     f = an.features(0, d["n"])
     an.close()
