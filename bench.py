@@ -42,12 +42,15 @@ def algorithmic_bytes_per_frame(width: int, height: int, w: int) -> int:
     return yb + 2 * cb
 
 
-def mfma_ops_per_frame(width: int, height: int, w: int) -> int:
-    """int8 ops the forward kernel issues on MFMA per frame: three 32x32x32
-    products (stage 1, stage 2 hi and lo) per 32 x 32 tile."""
+def mfma_ops_per_frame(width: int, height: int, w: int, k: int = 0) -> int:
+    """int8 ops the forward kernel issues on MFMA per frame.  A unit of
+    w / K sample tiles of 32 x 32 (one tile for the full transform) takes one
+    32x32x32 horizontal-pass product per sample tile and two vertical-pass
+    products (hi and lo) shared by the unit."""
+    pack = w // (k or w)
     tiles = (width // w) * (height // w) + 2 * ((width // 2) // w) * ((height // 2) // w)
-    tiles = tiles * (w * w) // (32 * 32)
-    return tiles * 3 * 2 * 32 * 32 * 32
+    tiles = tiles * (w * w) / (32 * 32)
+    return int(tiles * (pack + 2) / pack * 2 * 32 * 32 * 32)
 
 
 def cpu_baseline(sv, frames: int, lowpass_k: int = 0) -> dict:
@@ -89,7 +92,7 @@ def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool) -> d
     frames_per_launch = tm["frames"] / max(1, tm["forward_launches"])
     alg_bytes = algorithmic_bytes_per_frame(WIDTH, HEIGHT, BLOCK) * frames_per_launch
     gbs = alg_bytes / (fwd_ms * 1e-3) / 1e9
-    tops = mfma_ops_per_frame(WIDTH, HEIGHT, BLOCK) * frames_per_launch / (fwd_ms * 1e-3) / 1e12
+    tops = mfma_ops_per_frame(WIDTH, HEIGHT, BLOCK, lowpass_k) * frames_per_launch / (fwd_ms * 1e-3) / 1e12
     return {
         "fps": steps * FRAMES / dt,
         "ms_per_step": dt * 1e3 / steps,

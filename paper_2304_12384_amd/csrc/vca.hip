@@ -71,6 +71,8 @@ struct FwdParams {
   const v4i* tab_b1;
   const v4i* tab_a2;
   const double* tab_w;
+  const v4i* tab_b1p;      // packed layout (K < w): w / K stage-1 operands per lane
+  const double* tab_wp;    // packed layout weights
   TileOut out;
 };
 
@@ -238,21 +240,41 @@ __device__ inline TileWork strip_tile(const StripWork& s, int t) {
   return w;
 }
 
-// Persistent forward kernel over strips.  Each wavefront keeps kDepth tiles
-// in flight: while it transforms tile t of its strip it has issued the loads
-// of tile t + kDepth, which may be the next strip's (kStrip % kDepth == 0, so
-// ring slots line up across strips).  For w = 32 the eight tiles' FP64
-// energy shares are reduced together at the end of the strip and stored by
-// eight lanes; w = 16 and 8 reduce each tile over the lanes of its block
-// columns.
+// Persistent forward kernel over strips.  A strip is processed in units of
+// kPack = w / K tiles that share one MFMA tile (packed layout, one tile when
+// K = w).  Each wavefront keeps kDepth units in flight: while it transforms
+// unit u it has issued the loads of unit u + kDepth, which may belong to the
+// next strip (units per strip % kDepth == 0, so ring slots line up across
+// strips).  Every unit issues the same loads whatever the strip length (tile
+// indices are clamped into the strip, and the last strip prefetches itself
+// again), so the compiler can wait for exactly the oldest unit's loads; the
+// missing tiles of a short strip are transformed but never stored.  For
+// w = 32 the FP64 energy shares of the strip's eight tiles are reduced
+// together and stored, with the DCs, at the end of the strip; for w = 16 and
+// 8 each unit reduces over the lanes of its blocks and stores them.
 template <int kBits, int kW, int kK, int kDepth>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
-  static_assert(kStrip % kDepth == 0, "ring slots must line up across strips");
+  constexpr int kPack = kW / kK;
+  constexpr int kUnits = kStrip / kPack;
+  constexpr int kBpt = kTile / kW;
+  static_assert(kUnits % kDepth == 0, "ring slots must line up across strips");
   constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
+  struct Unit {
+    TileData t[kPack];
+  };
   const int lane = threadIdx.x & 63;
+  const int c = lane & 31, g = lane >> 5;
+  const int cc = c % kW, q = cc / kK, bc = c / kW;   // lane's tile in its unit, block column
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  TileConsts<kW, kK> tc;
-  tc.load(p.tab_b1, p.tab_a2, p.tab_w, lane);
+  PackConsts<kW, kK> pc;
+  pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
+
+  auto load_unit = [&](const StripWork& S, const LaneOffsets& O, int u) {
+    Unit d;
+#pragma unroll
+    for (int i = 0; i < kPack; i++) d.t[i] = strip_load<kBits, kW>(S, O, min(u * kPack + i, S.n - 1));
+    return d;
+  };
 
   const int total = p.n_frames * p.strips_per_frame;
   const int stride = gridDim.x * kWavesPerGroup;
@@ -260,47 +282,76 @@ __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   if (id >= total) return;
   StripWork S = decode_strip<kBits, kW>(p, id);
   LaneOffsets O = lane_offsets<kBits, kW>(S, lane);
-  TileData ring[kDepth];
+  Unit ring[kDepth];
 #pragma unroll
-  for (int t = 0; t < kDepth; t++)
-    if (t < S.n) ring[t] = strip_load<kBits, kW>(S, O, t);
+  for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
 
   while (true) {
     const int id2 = id + stride;
     const bool more = id2 < total;
-    StripWork S2{};
-    LaneOffsets O2{};
+    StripWork S2 = S;
+    LaneOffsets O2 = O;
     if (more) {
       S2 = decode_strip<kBits, kW>(p, id2);
       O2 = lane_offsets<kBits, kW>(S2, lane);
     }
-    double hs[kStrip];
+    double hs[kUnits];
+    int dcs[kUnits];
 #pragma unroll
-    for (int t = 0; t < kStrip; t++) {
-      TileData d;
-      if (t < S.n) d = ring[t % kDepth];
-      const int u = t + kDepth;   // the tile whose loads go out now
-      if (u < kStrip) {
-        if (u < S.n) ring[t % kDepth] = strip_load<kBits, kW>(S, O, u);
-      } else if (more && u - kStrip < S2.n) {
-        ring[t % kDepth] = strip_load<kBits, kW>(S2, O2, u - kStrip);
-      }
+    for (int u = 0; u < kUnits; u++) {
+      const Unit d = ring[u % kDepth];
+      const int v = u + kDepth;   // the unit whose loads go out now
+      ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
+      double h[kBpt];
+      int dc[kBpt];
+      unit_energy<kBits, kW, kK>(p.out, pc, d.t, h, dc);
       if (kW == 32) {
-        if (t < S.n) {
-          int dc = 0;
-          hs[t] = tile_energy32<kBits, kK>(p.out, tc, d, dc);
-          if (lane == 0) p.out.blk_dc[S.out0 + t] = dc + kDcAdd;
-        } else {
-          hs[t] = 0.0;
+        hs[u] = h[0];
+        dcs[u] = dc[0];
+      } else {
+        // butterfly over the K lanes of the tile's block column, then halves
+#pragma unroll
+        for (int off = 1; off < kK; off <<= 1)
+#pragma unroll
+          for (int b = 0; b < kBpt; b++) h[b] += __shfl_xor(h[b], off);
+#pragma unroll
+        for (int b = 0; b < kBpt; b++) h[b] += __shfl_xor(h[b], 32);
+        const int t = u * kPack + q;   // this lane's tile within the strip
+        if (g == 0 && cc % kK == 0 && t < S.n) {
+          const int vc = t == S.n - 1 ? S.vc_last : kBpt;
+          if (bc < vc) {
+#pragma unroll
+            for (int b = 0; b < kBpt; b++) {
+              if (b < S.vr) {
+                const int idx = S.out0 + t * kBpt + b * S.out_row + bc;
+                p.out.blk_h[idx] = h[b];
+                p.out.blk_dc[idx] = dc[b] + kDcAdd;
+              }
+            }
+          }
         }
-      } else if (t < S.n) {
-        fwd_tile<kBits, kW, kK, false>(p.out, tc, d, strip_tile<kBits, kW>(S, t), lane);
       }
     }
     if (kW == 32) {
-      const double h = reduce_scatter8(hs, lane);
-      const int t = lane >> 3;
+      double h;
+      int t;
+      if constexpr (kPack == 1) {
+        h = reduce_scatter8(hs, lane);
+        t = lane >> 3;
+      } else if constexpr (kPack == 2) {
+        h = reduce_scatter4x2(hs, lane);
+        t = 4 * (lane >> 5) + 2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
+      } else {
+        h = reduce_scatter2x4(hs);
+        t = lane >> 3;
+      }
       if ((lane & 7) == 0 && t < S.n) p.out.blk_h[S.out0 + t] = h;
+      // DC of tile u * kPack + q sits in lane q * K (g = 0), register dcs[u]
+      if (g == 0 && cc % kK == 0) {
+#pragma unroll
+        for (int u = 0; u < kUnits; u++)
+          if (u * kPack + q < S.n) p.out.blk_dc[S.out0 + u * kPack + q] = dcs[u] + kDcAdd;
+      }
     }
     if (!more) break;
     id = id2;
@@ -319,9 +370,11 @@ using FwdKernel = void (*)(FwdParams);
 
 template <int B, int W, int K>
 FwdKernel pick_depth(bool keep, int depth) {
+  constexpr int kUnits = kStrip / (W / K);   // units per strip bound the ring
   if (keep) return fwd_kernel<B, W, K, true, 1>;
   if (depth == 1) return strip_kernel<B, W, K, 1>;
-  if (depth == 4) return strip_kernel<B, W, K, 4>;
+  if constexpr (kUnits >= 4)
+    if (depth >= 4) return strip_kernel<B, W, K, 4>;
   return strip_kernel<B, W, K, 2>;
 }
 
@@ -362,6 +415,8 @@ struct vca_ctx {
   v4i* tab_b1 = nullptr;
   v4i* tab_a2 = nullptr;
   double* tab_w = nullptr;
+  v4i* tab_b1p = nullptr;
+  double* tab_wp = nullptr;
   double* blk_h = nullptr;
   int32_t* blk_dc = nullptr;
   int16_t* coeffs = nullptr;
@@ -444,6 +499,8 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
   fp.tab_b1 = ctx->tab_b1;
   fp.tab_a2 = ctx->tab_a2;
   fp.tab_w = ctx->tab_w;
+  fp.tab_b1p = ctx->tab_b1p;
+  fp.tab_wp = ctx->tab_wp;
   fp.out.blk_h = ctx->blk_h;
   fp.out.blk_dc = ctx->blk_dc;
   fp.out.coeffs = ctx->coeffs;
@@ -515,8 +572,9 @@ void vca_close(vca_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void* bufs[] = {ctx->tab_b1, ctx->tab_a2,   ctx->tab_w,    ctx->blk_h,    ctx->blk_dc,
-                    ctx->coeffs, ctx->err_flag, ctx->state[0], ctx->state[1], ctx->ring};
+    void* bufs[] = {ctx->tab_b1,   ctx->tab_a2,   ctx->tab_w,    ctx->tab_b1p,
+                    ctx->tab_wp,   ctx->blk_h,    ctx->blk_dc,   ctx->coeffs,
+                    ctx->err_flag, ctx->state[0], ctx->state[1], ctx->ring};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
@@ -568,6 +626,8 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   if ((s = dev_alloc(c, &c->tab_b1, 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_a2, 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_w, 16 * 64)) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->tab_b1p, (size_t)(cfg->block_size / K) * 64)) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->tab_wp, 16 * 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->blk_h, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->blk_dc, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->state[0], c->geo.cnt[0])) != VCA_OK) return bail(s);
@@ -581,9 +641,15 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   std::vector<int8_t> b1, a2;
   std::vector<double> wt;
   build_tile_tables(cfg->block_size, K, b1, a2, wt);
+  std::vector<int8_t> b1p;
+  std::vector<double> wtp;
+  build_packed_tables(cfg->block_size, K, b1p, wtp);
   if (hipMemcpy(c->tab_b1, b1.data(), b1.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_a2, a2.data(), a2.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_w, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->tab_b1p, b1p.data(), b1p.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->tab_wp, wtp.data(), wtp.size() * sizeof(double), hipMemcpyHostToDevice) !=
           hipSuccess)
     return bail(VCA_ERR_DEVICE);
   TuneCache::get().find(tune_key(c), &c->tuned);

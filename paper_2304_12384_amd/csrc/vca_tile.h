@@ -99,6 +99,28 @@ inline void build_tile_tables(int w, int K, std::vector<int8_t>& b1, std::vector
   }
 }
 
+// Tables of the packed layout used when K < w: one 32 x 32 MFMA tile holds
+// kPack = w / K sample tiles, sample tile p owning lanes whose column c has
+// (c % w) / K == p.  b1p[(p * 64 + lane) * 16 + j] = stage-1 B operand of
+// sample tile p (Cd row bc*w + kk, zero in other tiles' columns), wt as in
+// build_tile_tables for the coefficient (row % w, c % w % K) of the lane's
+// tile.  With K == w this is build_tile_tables' b1 and wt.
+inline void build_packed_tables(int w, int K, std::vector<int8_t>& b1p, std::vector<double>& wt) {
+  const int pack = w / K;
+  b1p.assign((size_t)pack * 64 * 16, 0);
+  wt.assign(16 * 64, 0.0);
+  for (int lane = 0; lane < 64; lane++) {
+    const int c = lane & 31, g = lane >> 5;
+    const int bc = c / w, cc = c % w, p = cc / K, kk = cc % K;
+    for (int j = 0; j < 16; j++) {
+      const int n = 16 * g + j;   // the sample column this lane's byte j multiplies
+      b1p[((size_t)p * 64 + lane) * 16 + j] = (int8_t)(n / w == bc ? matw(w, kk, n % w) : 0);
+      const int ii = reg_row(j, g) % w;
+      wt[j * 64 + lane] = (ii < K && !(ii == 0 && kk == 0)) ? weight(w, ii, kk) : 0.0;
+    }
+  }
+}
+
 // Division by an invariant d (Granlund-Montgomery, round-up multiplier):
 // n / d = (umulhi(n, m) + n) >> l for 0 <= n < 2^31, with l = ceil(log2 d)
 // and m = floor(2^32 (2^l - d) / d) + 1.  Keeps tile-id decoding scalar.
@@ -201,55 +223,85 @@ struct TileOut {
 // accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
 // Returns the hi and lo accumulators: Y = (256 dh + dl) >> s2 (+128 on each
 // block's row 0).
-template <int kBits, int kW, class Consts>
-__device__ __forceinline__ void tile_transform(const TileOut& o, const Consts& tc, const TileData& d,
-                                               v16i& dh, v16i& dl) {
+template <int kS1>
+__device__ __forceinline__ v16i stage1_bias() {
+  v16i c1;
+#pragma unroll
+  for (int j = 0; j < 16; j++) c1[j] = 1 << (kS1 - 1);   // rounding of the horizontal pass
+  return c1;
+}
+
+// 10-bit samples need no offset: x = 256 t + lo with lo the sign-extended low
+// byte and t = (x + 128) >> 8 in [0, 4], both int8.  The raw horizontal-pass
+// result stays within [-2^14, 2^15) (its first column is at most 32 * 1023),
+// so the T >> 8 byte of the split still fits int8, and DC needs no
+// correction.  A pair of samples x0 | x1 << 16 gives t0 and t1 in bytes 0 and
+// 2 of ((pair + 0x00800080) >> 8).
+__device__ __forceinline__ void operands10(const TileOut& o, const TileData& d, v4i& hi, v4i& lo) {
+  uint32_t tv[8];
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    tv[q] = ((uint32_t)d.a[q] + 0x00800080u) >> 8;
+    tv[4 + q] = ((uint32_t)d.b[q] + 0x00800080u) >> 8;
+  }
+  lo[0] = (int)perm_b32((uint32_t)d.a[1], (uint32_t)d.a[0], 0x06040200u);
+  lo[1] = (int)perm_b32((uint32_t)d.a[3], (uint32_t)d.a[2], 0x06040200u);
+  lo[2] = (int)perm_b32((uint32_t)d.b[1], (uint32_t)d.b[0], 0x06040200u);
+  lo[3] = (int)perm_b32((uint32_t)d.b[3], (uint32_t)d.b[2], 0x06040200u);
+#pragma unroll
+  for (int q = 0; q < 4; q++) hi[q] = (int)perm_b32(tv[2 * q + 1], tv[2 * q], 0x06040200u);
+  if (o.validate) {
+    uint32_t any = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) any |= (uint32_t)d.a[q] | (uint32_t)d.b[q];
+    if (any & 0xFC00FC00u) *o.err_flag = 1;
+  }
+}
+
+// Horizontal pass of kPack sample tiles into one accumulator: tile p's
+// B operand b1[p] puts its coefficients in its own lanes (kPack = 1: the
+// plain tile).
+template <int kBits, int kW, int kPack>
+__device__ __forceinline__ v16i stage1(const TileOut& o, const v4i (&b1)[kPack],
+                                       const TileData (&d)[kPack]) {
+  constexpr int kS1 = ilog2c(kW) + kBits - 9;
+  v16i d1 = stage1_bias<kS1>();
+  if (kBits == 8) {
+#pragma unroll
+    for (int p = 0; p < kPack; p++)
+      d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(d[p].a ^ (int)0x80808080, b1[p], d1, 0, 0, 0);   // x - 128
+  } else {
+    v16i dh1 = {};
+#pragma unroll
+    for (int p = 0; p < kPack; p++) {
+      v4i hi, lo;
+      operands10(o, d[p], hi, lo);
+      dh1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], dh1, 0, 0, 0);
+      d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], d1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 16; j++) d1[j] = (int)((uint32_t)dh1[j] * 256u + (uint32_t)d1[j]);
+  }
+  return d1;
+}
+
+// Split of the horizontal-pass result and the vertical pass.  Exact split of
+// T (-2^14 <= T < 2^15 for every w and B):
+//   T = 256 T_hi + u,  T_hi = T >> 8 in [-64, 127],  u = T & 255,
+// C T = 256 C T_hi + C (u - 128) + 128 C 1, the last term being 128 * 64 w
+// on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
+// scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
+// accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
+// Returns the hi and lo accumulators: Y = (256 dh + dl) >> s2 (+128 on each
+// block's row 0).
+template <int kBits, int kW>
+__device__ __forceinline__ void stage2(const v4i& a2, const v16i& d1, v16i& dh, v16i& dl) {
   constexpr int kS1 = ilog2c(kW) + kBits - 9;
   constexpr int kS2 = ilog2c(kW) + 6;
-  v16i c1, c2;
+  v16i c2;
 #pragma unroll
-  for (int j = 0; j < 16; j++) {
-    c1[j] = 1 << (kS1 - 1);            // rounding of the horizontal pass
-    c2[j] = 1 << (kS2 - 9);            // 256 * 2^(s2-9) = 2^(s2-1)
-  }
+  for (int j = 0; j < 16; j++) c2[j] = 1 << (kS2 - 9);   // 256 * 2^(s2-9) = 2^(s2-1)
   const v16i zero = {};
-
-  v16i d1;
-  if (kBits == 8) {
-    const v4i x = d.a ^ (int)0x80808080;   // x - 128 as int8
-    d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(x, tc.b1, c1, 0, 0, 0);
-  } else {
-    // 10-bit samples need no offset: x = 256 t + lo with lo the sign-extended
-    // low byte and t = (x + 128) >> 8 in [0, 4], both int8.  The raw
-    // horizontal-pass result stays within [-2^14, 2^15) (its first column
-    // is at most 32 * 1023), so the T >> 8 byte below still fits int8, and
-    // DC needs no correction.  A pair of samples x0 | x1 << 16 gives t0 and
-    // t1 in bytes 0 and 2 of ((pair + 0x00800080) >> 8).
-    v4i lo, hi;
-    uint32_t tv[8];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      tv[q] = ((uint32_t)d.a[q] + 0x00800080u) >> 8;
-      tv[4 + q] = ((uint32_t)d.b[q] + 0x00800080u) >> 8;
-    }
-    lo[0] = (int)perm_b32((uint32_t)d.a[1], (uint32_t)d.a[0], 0x06040200u);
-    lo[1] = (int)perm_b32((uint32_t)d.a[3], (uint32_t)d.a[2], 0x06040200u);
-    lo[2] = (int)perm_b32((uint32_t)d.b[1], (uint32_t)d.b[0], 0x06040200u);
-    lo[3] = (int)perm_b32((uint32_t)d.b[3], (uint32_t)d.b[2], 0x06040200u);
-#pragma unroll
-    for (int q = 0; q < 4; q++) hi[q] = (int)perm_b32(tv[2 * q + 1], tv[2 * q], 0x06040200u);
-    if (o.validate) {
-      uint32_t any = 0;
-#pragma unroll
-      for (int q = 0; q < 4; q++) any |= (uint32_t)d.a[q] | (uint32_t)d.b[q];
-      if (any & 0xFC00FC00u) *o.err_flag = 1;
-    }
-    const v16i dh1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, tc.b1, zero, 0, 0, 0);
-    const v16i dl1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, tc.b1, c1, 0, 0, 0);
-#pragma unroll
-    for (int j = 0; j < 16; j++) d1[j] = (int)((uint32_t)dh1[j] * 256u + (uint32_t)dl1[j]);
-  }
-
   v4i tlo, thi;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
@@ -262,8 +314,17 @@ __device__ __forceinline__ void tile_transform(const TileOut& o, const Consts& t
     tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
     thi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
   }
-  dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, thi, c2, 0, 0, 0);
-  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(tc.a2, tlo, zero, 0, 0, 0);
+  dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, thi, c2, 0, 0, 0);
+  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, tlo, zero, 0, 0, 0);
+}
+
+// Both passes of one tile.
+template <int kBits, int kW, class Consts>
+__device__ __forceinline__ void tile_transform(const TileOut& o, const Consts& tc, const TileData& d,
+                                               v16i& dh, v16i& dl) {
+  const v4i b1[1] = {tc.b1};
+  const TileData dd[1] = {d};
+  stage2<kBits, kW>(tc.a2, stage1<kBits, kW, 1>(o, b1, dd), dh, dl);
 }
 
 // Transform, energies and DC of one tile, reduced and stored per block.
@@ -421,6 +482,88 @@ __device__ inline double reduce_scatter8(const double (&v)[8], int lane) {
   c += dpp64<kDppXor2>(c);
   c += dpp64<kDppHalfMirror>(c);
   return c;
+}
+
+// Sums over all 64 lanes for 4 units of two w = 32, K = 16 tiles (unit u
+// holds tile 2u in lanes with bit 4 clear, 2u + 1 in the others); lane l
+// receives the total of tile 4 b5 + 2 b3 + b4 (b_i = bit i of l).
+__device__ inline double reduce_scatter4x2(const double (&v)[4], int lane) {
+  const double e0 = fold32(v[0], v[2]), e1 = fold32(v[1], v[3]);   // units 0|2, 1|3
+  const bool odd = (lane & 8) != 0;
+  const double keep = odd ? e1 : e0, send = odd ? e0 : e1;
+  double c = keep + dpp64<kDppRor8>(send);
+  c += dpp64<kDppXor1>(c);
+  c += dpp64<kDppXor2>(c);
+  c += dpp64<kDppHalfMirror>(c);
+  return c;
+}
+
+// The same for 2 units of four w = 32, K = 8 tiles (unit u holds tile
+// 4u + q in lanes with (l >> 3) & 3 == q): lane l receives tile l >> 3.
+__device__ inline double reduce_scatter2x4(const double (&v)[2]) {
+  double c = fold32(v[0], v[1]);
+  c += dpp64<kDppXor1>(c);
+  c += dpp64<kDppXor2>(c);
+  c += dpp64<kDppHalfMirror>(c);
+  return c;
+}
+
+// Per-wavefront constants of the packed layout (kPack = w / K sample tiles
+// per MFMA tile; kPack = 1 is the plain tile).
+template <int kW, int kK>
+struct PackConsts {
+  static constexpr int kPack = kW / kK;
+  v4i b1[kPack];      // stage-1 B operand of each sample tile
+  v4i a2;             // stage-2 A operand
+  double wt[16];      // weights (only registers in use are loaded)
+  int row0_fix;       // +128 on each block's first coefficient row (lanes g = 0)
+
+  __device__ void load(const v4i* tab_b1p, const v4i* tab_a2, const double* tab_w, int lane) {
+#pragma unroll
+    for (int p = 0; p < kPack; p++) b1[p] = tab_b1p[p * 64 + lane];
+    a2 = tab_a2[lane];
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (reg_used(j, kW, kK)) wt[j] = tab_w[j * 64 + lane];
+    row0_fix = lane < 32 ? 128 : 0;
+  }
+};
+
+// Energies of one packed unit: h[b] = this lane's FP64 share of the energy of
+// block row b of its sample tile, dc[b] = the coefficient in register row
+// (b, 0) (the block's DC where the lane is a DC lane: c % K == 0, g = 0).
+template <int kBits, int kW, int kK, class PC>
+__device__ __forceinline__ void unit_energy(const TileOut& o, const PC& pc,
+                                            const TileData (&d)[kW / kK],
+                                            double (&h)[kTile / kW], int (&dc)[kTile / kW]) {
+  constexpr int kS2 = ilog2c(kW) + 6;
+  constexpr int kBpt = kTile / kW;
+  constexpr int kAcc = kBpt == 1 ? 2 : kBpt;   // two chains when one block row
+  v16i dh, dl;
+  stage2<kBits, kW>(pc.a2, stage1<kBits, kW, kW / kK>(o, pc.b1, d), dh, dl);
+  double acc[kAcc];
+#pragma unroll
+  for (int a = 0; a < kAcc; a++) acc[a] = 0.0;
+#pragma unroll
+  for (int b = 0; b < kBpt; b++) dc[b] = 0;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    if (!reg_used(j, kW, kK)) continue;
+    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
+    const int br = (8 * (j / 4)) / kW;
+    if (reg_block_row0(j, kW)) {
+      yv += pc.row0_fix;
+      dc[br] = yv;
+    }
+    const int a = kBpt == 1 ? (j & 1) : br;
+    acc[a] = fma(pc.wt[j], fabs((double)yv), acc[a]);
+  }
+  if (kBpt == 1) {
+    h[0] = acc[0] + acc[1];
+  } else {
+#pragma unroll
+    for (int b = 0; b < kBpt; b++) h[b] = acc[b];
+  }
 }
 
 }  // namespace vca
