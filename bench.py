@@ -276,6 +276,60 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
     }
 
 
+KERNEL_SOURCES = ("vca.hip", "vca_tile.h", "vca_host.h", "vca_reduce.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fwd32_2160p.md")
+
+
+def kernel_sources_sha() -> str:
+    """SHA-256 over the plain path's kernel sources, to tell whether byte
+    counters taken earlier still describe the kernel being timed."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2304_12384_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per forward launch from the committed counter summary (the
+    JSON block of the traffic profile), or None when that summary is missing
+    or was taken on different kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    start = text.find("```json")
+    if start < 0:
+        return None
+    end = text.find("```", start + 7)
+    try:
+        data = json.loads(text[start + 7:end])
+    except ValueError:
+        return None
+    if data.get("kernel_sources_sha256") != kernel_sources_sha():
+        return None
+    return {mode: data[mode]["hbm_bytes_per_launch"] for mode in ("full", "lowpass") if mode in data}
+
+
+def calibration_copy(mib: int) -> dict:
+    """One plain device copy of `mib` MiB whose source was written before a
+    1 GiB flush buffer, so that it is read from HBM: the reference that scales
+    FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+    n = mib << 20
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(7)
+    dst = torch.empty_like(src)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda").fill_(1)
+    torch.cuda.synchronize()
+    del flush
+    t0 = time.perf_counter()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"bytes": n, "ms": dt * 1e3}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +340,9 @@ def main() -> int:
     ap.add_argument("--modes", default="full,lowpass,batch,backward",
                     help="comma list of full, lowpass, batch, backward")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB from a cold source (the "
+                         "known-size reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the analysis has no multi-GPU path); "
@@ -337,8 +394,11 @@ def main() -> int:
         log(f"timing the CPU oracle on {args.cpu_frames} frames")
         cpu = cpu_baseline(sv, args.cpu_frames)
 
+    copy = calibration_copy(args.calibrate_copy) if args.calibrate_copy > 0 else None
+
     if not results:
-        print(json.dumps({"metric": METRIC, "batched": batch, "backward": backward}), flush=True)
+        print(json.dumps({"metric": METRIC, "batched": batch, "backward": backward,
+                          "calibration_copy": copy}), flush=True)
         return 0
     head = results.get("full") or next(iter(results.values()))
     line = {
@@ -371,6 +431,13 @@ def main() -> int:
                                "ms_per_step": lp["ms_per_step"], "roofline": lp["roofline"],
                                "mfma": lp["mfma"], "forward_kernel_ms": lp["forward_kernel_ms"],
                                "launch": lp["launch"]}
+    traffic = measured_traffic()
+    if traffic is not None:
+        for mode, entry in (("full", line), ("lowpass", line.get("lowpass_k16"))):
+            if entry is not None and mode in traffic and mode in results:
+                entry["roofline"]["traffic"] = traffic[mode]
+    if copy is not None:
+        line["calibration_copy"] = copy
     if batch is not None:
         line["batched"] = batch
     if backward is not None:

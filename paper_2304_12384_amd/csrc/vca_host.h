@@ -100,7 +100,7 @@ inline const char* check_frames(const vca_config& cfg, const vca_frames* fr, int
 
 // Launch parameters chosen by the autotuner (depth 0 = not tuned).
 struct LaunchChoice {
-  int depth = 0;          // tiles in flight per wavefront (1..3)
+  int depth = 0;          // work units in flight per wavefront (1..4)
   int groups_per_cu = 0;  // 0: as many as fit
   double ms = 0.0;
 };
@@ -146,7 +146,7 @@ class TuneCache {
     char key[256];
     LaunchChoice c;
     while (std::fscanf(f, "%255s %d %d %lf", key, &c.depth, &c.groups_per_cu, &c.ms) == 4)
-      if (c.depth >= 1 && c.depth <= 3 && c.groups_per_cu >= 0) map_[key] = c;
+      if (c.depth >= 1 && c.depth <= 4 && c.groups_per_cu >= 0) map_[key] = c;
     std::fclose(f);
   }
   std::mutex mu_;
