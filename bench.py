@@ -335,7 +335,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-frames", type=int, default=64,
+    ap.add_argument("--cpu-frames", type=int, default=512,
                     help="frames of the oracle's bounded CPU sample (0 skips it)")
     ap.add_argument("--modes", default="full,lowpass,batch,backward",
                     help="comma list of full, lowpass, batch, backward")

@@ -27,6 +27,7 @@
 #include "../../include/vca.h"
 #include "vca_host.h"
 #include "vca_reduce.h"
+#include "vca_strip.h"
 #include "vca_tile.h"
 
 using namespace vca;
@@ -36,20 +37,6 @@ namespace {
 constexpr int kWavesPerGroup = 4;   // wavefronts per workgroup
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
 constexpr int kDefaultDepth = 2;    // tiles in flight per wavefront when untuned
-constexpr int kStrip = 8;           // tiles per strip (work unit of the strip kernel)
-
-// One plane as the strip kernel sees it (read with scalar loads, once per
-// strip, from the kernel argument block).
-struct StripPlane {
-  const uint8_t* plane;
-  int64_t fstride;
-  int32_t pitch;
-  int32_t nbx, nby, ntx;
-  int32_t spr;             // strips per tile row
-  int32_t scnt;            // strips per plane
-  int32_t boff;            // index of the plane's first block within a frame
-  FastDiv div_spr;         // / spr
-};
 
 struct FwdParams {
   const uint8_t* plane[3];
@@ -64,10 +51,7 @@ struct FwdParams {
   FastDiv div_tpf;         // / tiles_per_frame
   FastDiv div_ntx[3];      // / ntx[P]
   int32_t n_frames;
-  // strips: runs of up to kStrip consecutive tiles of one tile row
-  StripPlane sp[3];
-  int32_t strips_per_frame;
-  FastDiv div_spf;         // / strips_per_frame
+  StripGeom geom;          // the same frames as strips (strip kernel)
   const v4i* tab_b1;
   const v4i* tab_a2;
   const double* tab_w;
@@ -139,225 +123,17 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
   }
 }
 
-// ------------------------------------------------------------ strip kernel
-// Work unit: a strip of up to kStrip consecutive tiles of one tile row of one
-// plane of one frame, so that tile ids are decoded once per strip and the
-// tiles of a strip sit side by side in memory (and, for w = 32, in the
-// output).  Strips are dealt to wavefronts round-robin.
-
-struct StripWork {
-  const uint8_t* base;  // first sample of the strip's first tile
-  int32_t pitch;
-  int32_t n;            // tiles in the strip, 1..kStrip
-  int32_t out0;         // output index of block (0, 0) of the first tile
-  int32_t out_row;      // output index step between block rows
-  int32_t vr;           // block rows of the strip inside the grid
-  int32_t vc_last;      // block columns of the last tile inside the grid
-};
-
-template <int kBits, int kW>
-__device__ inline StripWork decode_strip(const FwdParams& p, int id) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  constexpr int kBpt = kTile / kW;
-  const int f = (int)fastdiv((uint32_t)id, p.div_spf);
-  int r = id - f * p.strips_per_frame;
-  int P = 0;
-  if (r >= p.sp[0].scnt) {
-    r -= p.sp[0].scnt;
-    P = 1;
-    if (r >= p.sp[1].scnt) {
-      r -= p.sp[1].scnt;
-      P = 2;
-    }
-  }
-  const StripPlane& pl = p.sp[P];
-  const int ty = (int)fastdiv((uint32_t)r, pl.div_spr);
-  const int tx0 = (r - ty * pl.spr) * kStrip;
-  StripWork w;
-  w.pitch = pl.pitch;
-  w.n = min(kStrip, pl.ntx - tx0);
-  const int by0 = ty * kBpt, bx0 = tx0 * kBpt;
-  w.base = pl.plane + f * pl.fstride + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
-  w.vr = min(kBpt, pl.nby - by0);
-  w.vc_last = min(kBpt, pl.nbx - (tx0 + w.n - 1) * kBpt);
-  w.out0 = f * p.per_frame + pl.boff + by0 * pl.nbx + bx0;
-  w.out_row = pl.nbx;
-  return w;
-}
-
-// Byte offsets of a lane's samples inside the tiles of a strip (scalar tile
-// base + 32-bit lane offset keeps every load in the saddr form): `a` (and,
-// for 10-bit, `b`) for full tiles, and the same for the strip's last tile,
-// whose columns outside the block grid are redirected like load_tile does.
-struct LaneOffsets {
-  uint32_t a, b, last_a, last_b;
-};
-
-template <int kBits, int kW>
-__device__ inline LaneOffsets lane_offsets(const StripWork& s, int lane) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  const int r = lane & 31, g = lane >> 5;
-  const int rows = s.vr * kW;
-  const uint32_t roff = __umul24((uint32_t)(kW == 32 || r < rows ? r : 0), (uint32_t)s.pitch);
-  LaneOffsets o;
-  o.a = roff + 16 * g * kBps;
-  o.b = o.a + 16;
-  if (kW == 32) {            // a w = 32 tile is one complete block
-    o.last_a = o.a;
-    o.last_b = o.b;
-  } else {
-    const int cols = s.vc_last * kW;
-    const int c0 = 16 * g < cols ? 16 * g : 0;
-    const int c1 = 16 * g + 8 < cols ? 16 * g + 8 : c0;
-    o.last_a = roff + c0 * kBps;
-    o.last_b = roff + c1 * kBps;
-  }
-  return o;
-}
-
-template <int kBits, int kW>
-__device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, int t) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  const uint8_t* base = s.base + t * kTile * kBps;
-  const bool last = kW != 32 && t == s.n - 1;
-  TileData d;
-  d.a = *reinterpret_cast<const v4i*>(base + (last ? o.last_a : o.a));
-  if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(base + (last ? o.last_b : o.b));
-  return d;
-}
-
-template <int kBits, int kW>
-__device__ inline TileWork strip_tile(const StripWork& s, int t) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  constexpr int kBpt = kTile / kW;
-  TileWork w;
-  w.base = s.base + t * kTile * kBps;
-  w.pitch = s.pitch;
-  w.vr = s.vr;
-  w.vc = t == s.n - 1 ? s.vc_last : kBpt;
-  w.out0 = s.out0 + t * kBpt;
-  w.out_row = s.out_row;
-  return w;
-}
-
-// Persistent forward kernel over strips.  A strip is processed in units of
-// kPack = w / K tiles that share one MFMA tile (packed layout, one tile when
-// K = w).  Each wavefront keeps kDepth units in flight: while it transforms
-// unit u it has issued the loads of unit u + kDepth, which may belong to the
-// next strip (units per strip % kDepth == 0, so ring slots line up across
-// strips).  Every unit issues the same loads whatever the strip length (tile
-// indices are clamped into the strip, and the last strip prefetches itself
-// again), so the compiler can wait for exactly the oldest unit's loads; the
-// missing tiles of a short strip are transformed but never stored.  For
-// w = 32 the FP64 energy shares of the strip's eight tiles are reduced
-// together and stored, with the DCs, at the end of the strip; for w = 16 and
-// 8 each unit reduces over the lanes of its blocks and stores them.
+// Persistent forward kernel over strips (vca_strip.h): wavefront i of S
+// takes strips i, i + S, ...
 template <int kBits, int kW, int kK, int kDepth>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
-  constexpr int kPack = kW / kK;
-  constexpr int kUnits = kStrip / kPack;
-  constexpr int kBpt = kTile / kW;
-  static_assert(kUnits % kDepth == 0, "ring slots must line up across strips");
-  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
-  struct Unit {
-    TileData t[kPack];
-  };
   const int lane = threadIdx.x & 63;
-  const int c = lane & 31, g = lane >> 5;
-  const int cc = c % kW, q = cc / kK, bc = c / kW;   // lane's tile in its unit, block column
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   PackConsts<kW, kK> pc;
   pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
-
-  auto load_unit = [&](const StripWork& S, const LaneOffsets& O, int u) {
-    Unit d;
-#pragma unroll
-    for (int i = 0; i < kPack; i++) d.t[i] = strip_load<kBits, kW>(S, O, min(u * kPack + i, S.n - 1));
-    return d;
-  };
-
-  const int total = p.n_frames * p.strips_per_frame;
-  const int stride = gridDim.x * kWavesPerGroup;
-  int id = blockIdx.x * kWavesPerGroup + wave;
-  if (id >= total) return;
-  StripWork S = decode_strip<kBits, kW>(p, id);
-  LaneOffsets O = lane_offsets<kBits, kW>(S, lane);
-  Unit ring[kDepth];
-#pragma unroll
-  for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
-
-  while (true) {
-    const int id2 = id + stride;
-    const bool more = id2 < total;
-    StripWork S2 = S;
-    LaneOffsets O2 = O;
-    if (more) {
-      S2 = decode_strip<kBits, kW>(p, id2);
-      O2 = lane_offsets<kBits, kW>(S2, lane);
-    }
-    double hs[kUnits];
-    int dcs[kUnits];
-#pragma unroll
-    for (int u = 0; u < kUnits; u++) {
-      const Unit d = ring[u % kDepth];
-      const int v = u + kDepth;   // the unit whose loads go out now
-      ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
-      double h[kBpt];
-      int dc[kBpt];
-      unit_energy<kBits, kW, kK>(p.out, pc, d.t, h, dc);
-      if (kW == 32) {
-        hs[u] = h[0];
-        dcs[u] = dc[0];
-      } else {
-        // butterfly over the K lanes of the tile's block column, then halves
-#pragma unroll
-        for (int off = 1; off < kK; off <<= 1)
-#pragma unroll
-          for (int b = 0; b < kBpt; b++) h[b] += __shfl_xor(h[b], off);
-#pragma unroll
-        for (int b = 0; b < kBpt; b++) h[b] += __shfl_xor(h[b], 32);
-        const int t = u * kPack + q;   // this lane's tile within the strip
-        if (g == 0 && cc % kK == 0 && t < S.n) {
-          const int vc = t == S.n - 1 ? S.vc_last : kBpt;
-          if (bc < vc) {
-#pragma unroll
-            for (int b = 0; b < kBpt; b++) {
-              if (b < S.vr) {
-                const int idx = S.out0 + t * kBpt + b * S.out_row + bc;
-                p.out.blk_h[idx] = h[b];
-                p.out.blk_dc[idx] = dc[b] + kDcAdd;
-              }
-            }
-          }
-        }
-      }
-    }
-    if (kW == 32) {
-      double h;
-      int t;
-      if constexpr (kPack == 1) {
-        h = reduce_scatter8(hs, lane);
-        t = lane >> 3;
-      } else if constexpr (kPack == 2) {
-        h = reduce_scatter4x2(hs, lane);
-        t = 4 * (lane >> 5) + 2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
-      } else {
-        h = reduce_scatter2x4(hs);
-        t = lane >> 3;
-      }
-      if ((lane & 7) == 0 && t < S.n) p.out.blk_h[S.out0 + t] = h;
-      // DC of tile u * kPack + q sits in lane q * K (g = 0), register dcs[u]
-      if (g == 0 && cc % kK == 0) {
-#pragma unroll
-        for (int u = 0; u < kUnits; u++)
-          if (u * kPack + q < S.n) p.out.blk_dc[S.out0 + u * kPack + q] = dcs[u] + kDcAdd;
-      }
-    }
-    if (!more) break;
-    id = id2;
-    S = S2;
-    O = O2;
-  }
+  run_strips<kBits, kW, kK, kDepth>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
+                                    gridDim.x * kWavesPerGroup, p.n_frames * p.geom.strips_per_frame,
+                                    lane);
 }
 
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) {
@@ -370,11 +146,9 @@ using FwdKernel = void (*)(FwdParams);
 
 template <int B, int W, int K>
 FwdKernel pick_depth(bool keep, int depth) {
-  constexpr int kUnits = kStrip / (W / K);   // units per strip bound the ring
   if (keep) return fwd_kernel<B, W, K, true, 1>;
   if (depth == 1) return strip_kernel<B, W, K, 1>;
-  if constexpr (kUnits >= 4)
-    if (depth >= 4) return strip_kernel<B, W, K, 4>;
+  if (depth >= 4) return strip_kernel<B, W, K, 4>;   // capped at the units per strip
   return strip_kernel<B, W, K, 2>;
 }
 
@@ -478,20 +252,8 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
     fp.tcnt[P] = g.tcnt[P];
     fp.boff[P] = g.boff[P];
     fp.div_ntx[P] = make_fastdiv((uint32_t)g.ntx[P]);
-    StripPlane& sp = fp.sp[P];
-    sp.plane = fp.plane[P];
-    sp.fstride = fs[P];
-    sp.pitch = (int32_t)pt[P];
-    sp.nbx = g.nbx[P];
-    sp.nby = g.nby[P];
-    sp.ntx = g.ntx[P];
-    sp.spr = (g.ntx[P] + kStrip - 1) / kStrip;
-    sp.scnt = sp.spr * (g.tcnt[P] / g.ntx[P]);
-    sp.boff = g.boff[P];
-    sp.div_spr = make_fastdiv((uint32_t)sp.spr);
   }
-  fp.strips_per_frame = fp.sp[0].scnt + fp.sp[1].scnt + fp.sp[2].scnt;
-  fp.div_spf = make_fastdiv((uint32_t)fp.strips_per_frame);
+  fp.geom = make_strip_geom(g, fp.plane, fs, pt, 0);
   fp.tiles_per_frame = g.tiles_per_frame;
   fp.per_frame = g.per_frame;
   fp.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
@@ -521,7 +283,7 @@ vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_p
   resident = std::max(1, resident);
   if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
   const int64_t waves = keep ? (int64_t)fp.n_frames * fp.tiles_per_frame
-                             : (int64_t)fp.n_frames * fp.strips_per_frame;
+                             : (int64_t)fp.n_frames * fp.geom.strips_per_frame;
   const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);

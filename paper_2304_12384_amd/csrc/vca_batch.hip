@@ -2,14 +2,15 @@
 //
 // Many independent video streams of different resolution, block size, bit
 // depth and frame count are analysed by ONE persistent launch: every
-// wavefront walks a flat list of chunks (runs of kChunk consecutive 32 x 32
-// tiles of one stream; a stream's chunks are contiguous), copies the chunk's
-// stream descriptor into registers, and runs the tile loop specialised for
-// the stream's (bit depth, w, K) class (vca_tile.h).  A second launch reduces every
-// (stream, frame) pair to its seven features (vca_reduce.h).  Both launches
-// are captured once into a hipGraph per frame-count signature and replayed;
-// per call only the descriptor tables (frame pointers, state buffers) are
-// uploaded.  The ring depth and workgroups per CU come from vca_tune_batch.
+// wavefront walks a flat list of chunks (runs of kChunkStrips consecutive
+// strips of one stream, vca_strip.h; a stream's chunks are contiguous),
+// copies the chunk's stream descriptor into registers, and runs the strip
+// loop specialised for the stream's (bit depth, w, K) class.  A second launch
+// reduces every (stream, frame) pair to its seven features (vca_reduce.h).
+// Both launches are captured once into a hipGraph per frame-count signature
+// and replayed; per call only the descriptor tables (frame pointers, state
+// buffers) are uploaded.  The ring depth and workgroups per CU come from
+// vca_tune_batch.
 
 #include <hip/hip_runtime.h>
 
@@ -24,6 +25,7 @@
 #include "../../include/vca.h"
 #include "vca_host.h"
 #include "vca_reduce.h"
+#include "vca_strip.h"
 #include "vca_tile.h"
 
 using namespace vca;
@@ -42,29 +44,31 @@ inline int kind_of(int bits, int w, int K) {
 
 // Device-side description of one stream for one launch.
 struct StreamDesc {
-  const uint8_t* plane[3];
-  int64_t fstride[3];
-  int32_t pitch[3];
-  int32_t nbx[3], nby[3], ntx[3], tcnt[3], boff[3];
-  int32_t tiles_per_frame, per_frame;
-  FastDiv div_tpf, div_ntx[3];
+  StripGeom geom;                  // the stream's frames of this launch as strips
   int32_t kind;
-  int32_t tiles;                 // tiles of the stream in this launch
+  int32_t strips;                  // strips of the stream in this launch
   int32_t chunk_begin, chunk_end;  // the stream's chunks in the launch's flat list
-  int32_t blk_base;              // block index of the stream's frame 0
   int32_t validate;
 };
 
-// Consecutive tiles of one stream handed to a wavefront at a time.
-constexpr int kChunk = 256;
+// Consecutive strips of one stream handed to a wavefront at a time.
+constexpr int kChunkStrips = 32;
+constexpr int kMaxPack = 4;        // w / K at most
+
+// Descriptors and chunks of one class, ranges in the launch's flat lists
+// (ordered by class, then stream).
+struct KindRange {
+  int32_t desc_begin, desc_end;
+  int32_t chunk_begin, chunk_end;
+};
 
 struct BatchParams {
-  const StreamDesc* streams;
-  int32_t n_streams;
+  const StreamDesc* streams;   // in flat order (by class, then stream)
+  KindRange kinds[kKinds];
   int32_t total_chunks;
-  const v4i* tab_b1;     // [kKinds][64]
+  const v4i* tab_b1p;    // [kKinds][kMaxPack][64] packed stage-1 operands
   const v4i* tab_a2;     // [kKinds][64]
-  const double* tab_w;   // [kKinds][16][64]
+  const double* tab_wp;  // [kKinds][16][64] packed-layout weights
   double* blk_h;
   int32_t* blk_dc;
   int32_t* err_flag;
@@ -75,127 +79,70 @@ struct BatchReduceParams {
   int32_t n_streams;
 };
 
-template <int kBits, int kW>
-__device__ inline TileWork decode_stream_tile(const StreamDesc& sd, int t) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  constexpr int kBpt = kTile / kW;
-  const int f = (int)fastdiv((uint32_t)t, sd.div_tpf);
-  t -= f * sd.tiles_per_frame;
-  int P = 0;
-  if (t >= sd.tcnt[0]) {
-    t -= sd.tcnt[0];
-    P = 1;
-    if (t >= sd.tcnt[1]) {
-      t -= sd.tcnt[1];
-      P = 2;
-    }
-  }
-  const int ty = (int)fastdiv((uint32_t)t, sd.div_ntx[P]);
-  const int tx = t - ty * sd.ntx[P];
-  const int by0 = ty * kBpt, bx0 = tx * kBpt;
-  TileWork w;
-  w.pitch = sd.pitch[P];
-  w.base = sd.plane[P] + f * sd.fstride[P] + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
-  w.vr = min(kBpt, sd.nby[P] - by0);
-  w.vc = min(kBpt, sd.nbx[P] - bx0);
-  w.out0 = sd.blk_base + f * sd.per_frame + sd.boff[P] + by0 * sd.nbx[P] + bx0;
-  w.out_row = sd.nbx[P];
-  return w;
-}
-
-// Tiles [t0, t1) of one stream, with the plain kernel's register ring.
+// All chunks of one class: wavefront gw of W takes chunks gw, gw + W, ... of
+// the class's range (its descriptors are contiguous, so the stream search
+// only moves forward), with the class's operand tables loaded once.
 template <int kBits, int kW, int kK, int kDepth>
-__device__ __forceinline__ void run_chunk(const StreamDesc& sd, const TileOut& o,
-                                          const TileConsts<8, 8>& tc, int t0, int t1, int lane) {
-  TileData ring[kDepth];
-#pragma unroll
-  for (int q = 0; q < kDepth; q++)
-    if (t0 + q < t1) ring[q] = load_tile<kBits, kW>(decode_stream_tile<kBits, kW>(sd, t0 + q), lane);
-  int t = t0;
-  while (t < t1) {
-#pragma unroll
-    for (int q = 0; q < kDepth; q++) {
-      if (t < t1) {
-        const TileData d = ring[q];
-        if (t + kDepth < t1)
-          ring[q] = load_tile<kBits, kW>(decode_stream_tile<kBits, kW>(sd, t + kDepth), lane);
-        fwd_tile<kBits, kW, kK, false>(o, tc, d, decode_stream_tile<kBits, kW>(sd, t), lane);
-        t++;
-      }
-    }
+__device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw, int W,
+                                         const TileOut& o0, int lane) {
+  const KindRange kr = p.kinds[kind];
+  PackConsts<kW, kK> pc;
+  pc.load(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
+  TileOut o = o0;
+  int d = kr.desc_begin;
+  for (int c = kr.chunk_begin + gw; c < kr.chunk_end; c += W) {
+    while (d < kr.desc_end - 1 && c >= p.streams[d].chunk_end) d++;
+    const StreamDesc& sd = p.streams[d];
+    o.validate = sd.validate;
+    const int s0 = (c - sd.chunk_begin) * kChunkStrips;
+    const int s1 = min(s0 + kChunkStrips, sd.strips);
+    run_strips<kBits, kW, kK, kDepth>(sd.geom, o, pc, s0, 1, s1, lane);
   }
 }
 
-// kOnly8: every stream of the launch is 8-bit (the 10-bit tile loops are
-// left out, which lowers the kernel's register allocation).
-template <int kDepth, bool kOnly8>
-__device__ inline void dispatch_chunk(const StreamDesc& sd, const TileOut& o,
-                                      const TileConsts<8, 8>& tc, int t0, int t1, int lane) {
-  if (kOnly8) {
-    switch (sd.kind) {
-      case 0: run_chunk<8, 32, 32, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 1: run_chunk<8, 32, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 2: run_chunk<8, 32, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 3: run_chunk<8, 16, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 4: run_chunk<8, 16, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 5: run_chunk<8, 16, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 6: run_chunk<8, 8, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-      case 7: run_chunk<8, 8, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
-      default: run_chunk<8, 8, 2, kDepth>(sd, o, tc, t0, t1, lane); break;
-    }
-    return;
-  }
-  switch (sd.kind) {
-    case 0: run_chunk<8, 32, 32, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 1: run_chunk<8, 32, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 2: run_chunk<8, 32, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 3: run_chunk<8, 16, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 4: run_chunk<8, 16, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 5: run_chunk<8, 16, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 6: run_chunk<8, 8, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 7: run_chunk<8, 8, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 8: run_chunk<8, 8, 2, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 9: run_chunk<10, 32, 32, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 10: run_chunk<10, 32, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 11: run_chunk<10, 32, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 12: run_chunk<10, 16, 16, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 13: run_chunk<10, 16, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 14: run_chunk<10, 16, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 15: run_chunk<10, 8, 8, kDepth>(sd, o, tc, t0, t1, lane); break;
-    case 16: run_chunk<10, 8, 4, kDepth>(sd, o, tc, t0, t1, lane); break;
-    default: run_chunk<10, 8, 2, kDepth>(sd, o, tc, t0, t1, lane); break;
-  }
+// The classes one after the other, each its own loop (a switch inside one
+// loop made the compiler allocate registers for several classes at once).
+template <int kDepth, int kBits, int kW, int kK>
+__device__ __forceinline__ void run_kind_if(const BatchParams& p, int kind, int gw, int W,
+                                            const TileOut& o, int lane) {
+  if (p.kinds[kind].chunk_begin < p.kinds[kind].chunk_end)
+    run_kind<kBits, kW, kK, kDepth>(p, kind, gw, W, o, lane);
 }
 
-// Persistent batched kernel: each wavefront walks chunks c, c + S, ... of
-// the flat chunk list (chunks of a stream are contiguous, so the stream
-// search only moves forward).  Per chunk the stream's descriptor is copied
-// into registers once and one specialised tile loop runs.
+// Persistent batched kernel: every wavefront walks the classes present in
+// the launch in order and, within each, its share of the class's chunks.
+// kOnly8: every stream of the launch is 8-bit (the 10-bit classes are left
+// out, which lowers the kernel's register allocation).
 template <int kDepth, bool kOnly8>
 __global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int stride = gridDim.x * kWaves;
+  const int gw = blockIdx.x * kWaves + wave, W = gridDim.x * kWaves;
   TileOut o;
   o.blk_h = p.blk_h;
   o.blk_dc = p.blk_dc;
   o.coeffs = nullptr;
   o.err_flag = p.err_flag;
-  int cur_kind = -1;
-  TileConsts<8, 8> tc;
-  int s = 0;
-  for (int c = blockIdx.x * kWaves + wave; c < p.total_chunks; c += stride) {
-    while (s < p.n_streams - 1 && c >= p.streams[s].chunk_end) s++;
-    const StreamDesc sd = p.streams[s];
-    const int kind = __builtin_amdgcn_readfirstlane(sd.kind);
-    if (kind != cur_kind) {
-      tc.load(p.tab_b1 + kind * 64, p.tab_a2 + kind * 64, p.tab_w + kind * 16 * 64, lane);
-      cur_kind = kind;
-    }
-    o.validate = sd.validate;
-    const int t0 = (c - sd.chunk_begin) * kChunk;
-    const int t1 = min(t0 + kChunk, sd.tiles);
-    dispatch_chunk<kDepth, kOnly8>(sd, o, tc, t0, t1, lane);
+  o.validate = 0;
+  run_kind_if<kDepth, 8, 32, 32>(p, 0, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 32, 16>(p, 1, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 32, 8>(p, 2, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 16, 16>(p, 3, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 16, 8>(p, 4, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 16, 4>(p, 5, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 8, 8>(p, 6, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 8, 4>(p, 7, gw, W, o, lane);
+  run_kind_if<kDepth, 8, 8, 2>(p, 8, gw, W, o, lane);
+  if constexpr (!kOnly8) {
+    run_kind_if<kDepth, 10, 32, 32>(p, 9, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 32, 16>(p, 10, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 32, 8>(p, 11, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 16, 16>(p, 12, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 16, 8>(p, 13, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 16, 4>(p, 14, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 8, 8>(p, 15, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 8, 4>(p, 16, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 8, 2>(p, 17, gw, W, o, lane);
   }
 }
 
@@ -216,11 +163,11 @@ using BatchKernel = void (*)(BatchParams);
 BatchKernel batch_kernel_for(int depth, bool only8) {
   if (only8) {
     if (depth == 1) return batch_fwd_kernel<1, true>;
-    if (depth == 3) return batch_fwd_kernel<3, true>;
+    if (depth >= 4) return batch_fwd_kernel<4, true>;
     return batch_fwd_kernel<2, true>;
   }
   if (depth == 1) return batch_fwd_kernel<1, false>;
-  if (depth == 3) return batch_fwd_kernel<3, false>;
+  if (depth >= 4) return batch_fwd_kernel<4, false>;
   return batch_fwd_kernel<2, false>;
 }
 
@@ -236,9 +183,9 @@ struct vca_batch {
   bool own_stream = false;
   hipStream_t capture = nullptr;   // private stream the graph is captured on
   // tables for every kind
-  v4i* tab_b1 = nullptr;
+  v4i* tab_b1p = nullptr;
   v4i* tab_a2 = nullptr;
-  double* tab_w = nullptr;
+  double* tab_wp = nullptr;
   // per-stream device state
   double* blk_h = nullptr;
   int32_t* blk_dc = nullptr;
@@ -264,6 +211,7 @@ struct vca_batch {
   std::vector<int32_t> graph_sig;
   bool use_graph = true;
   bool only8 = true;               // no 10-bit stream: the 8-bit-only kernel serves
+  KindRange kinds[kKinds] = {};    // flat-list ranges of the current round
   LaunchChoice tuned;
   // timing
   bool timing = false;
@@ -308,38 +256,37 @@ void drop_graph(vca_batch* b) {
 // frames of the round.
 void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, const int32_t* cnt,
                       int32_t* total_chunks, int32_t* total_frames) {
-  int32_t chunks = 0, frames = 0;
+  int32_t chunks = 0, frames = 0, i = 0;
+  for (int k = 0; k < kKinds; k++) {
+    KindRange& kr = b->kinds[k];
+    kr.desc_begin = i;
+    kr.chunk_begin = chunks;
+    for (int s = 0; s < b->n; s++) {
+      const Geometry& g = b->geos[s];
+      const vca_config& c = b->cfgs[s];
+      if (kind_of(c.bit_depth, c.block_size, g.K) != k) continue;
+      StreamDesc& sd = b->h_streams[i++];
+      std::memset(&sd, 0, sizeof(sd));
+      const uint8_t* base[3] = {static_cast<const uint8_t*>(fr[s].y), static_cast<const uint8_t*>(fr[s].u),
+                                static_cast<const uint8_t*>(fr[s].v)};
+      const int64_t fs[3] = {fr[s].fstride_y, fr[s].fstride_uv, fr[s].fstride_uv};
+      const int64_t pt[3] = {fr[s].pitch_y, fr[s].pitch_uv, fr[s].pitch_uv};
+      const uint8_t* first[3];
+      for (int P = 0; P < 3; P++) first[P] = cnt[s] > 0 ? base[P] + fs[P] * off[s] : nullptr;
+      sd.geom = make_strip_geom(g, first, fs, pt, (int32_t)b->blk_base[s]);
+      sd.kind = k;
+      sd.strips = cnt[s] * sd.geom.strips_per_frame;
+      sd.chunk_begin = chunks;
+      chunks += (sd.strips + kChunkStrips - 1) / kChunkStrips;
+      sd.chunk_end = chunks;
+      sd.validate = (c.flags & VCA_F_VALIDATE) && c.bit_depth == 10 ? 1 : 0;
+    }
+    kr.desc_end = i;
+    kr.chunk_end = chunks;
+  }
   for (int s = 0; s < b->n; s++) {
     const Geometry& g = b->geos[s];
     const vca_config& c = b->cfgs[s];
-    StreamDesc& sd = b->h_streams[s];
-    std::memset(&sd, 0, sizeof(sd));
-    const uint8_t* base[3] = {static_cast<const uint8_t*>(fr[s].y), static_cast<const uint8_t*>(fr[s].u),
-                              static_cast<const uint8_t*>(fr[s].v)};
-    const int64_t fs[3] = {fr[s].fstride_y, fr[s].fstride_uv, fr[s].fstride_uv};
-    const int64_t pt[3] = {fr[s].pitch_y, fr[s].pitch_uv, fr[s].pitch_uv};
-    for (int P = 0; P < 3; P++) {
-      sd.plane[P] = cnt[s] > 0 ? base[P] + fs[P] * off[s] : nullptr;
-      sd.fstride[P] = fs[P];
-      sd.pitch[P] = (int32_t)pt[P];
-      sd.nbx[P] = g.nbx[P];
-      sd.nby[P] = g.nby[P];
-      sd.ntx[P] = g.ntx[P];
-      sd.tcnt[P] = g.tcnt[P];
-      sd.boff[P] = g.boff[P];
-      sd.div_ntx[P] = make_fastdiv((uint32_t)g.ntx[P]);
-    }
-    sd.tiles_per_frame = g.tiles_per_frame;
-    sd.per_frame = g.per_frame;
-    sd.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
-    sd.kind = kind_of(c.bit_depth, c.block_size, g.K);
-    sd.tiles = cnt[s] * g.tiles_per_frame;
-    sd.chunk_begin = chunks;
-    chunks += (sd.tiles + kChunk - 1) / kChunk;
-    sd.chunk_end = chunks;
-    sd.blk_base = (int32_t)b->blk_base[s];
-    sd.validate = (c.flags & VCA_F_VALIDATE) && c.bit_depth == 10 ? 1 : 0;
-
     ReduceParams& rp = b->h_red[s];
     std::memset(&rp, 0, sizeof(rp));
     const double ww = (double)c.block_size * c.block_size;
@@ -375,11 +322,11 @@ vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_chunks, 
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)b->num_cus * resident));
   BatchParams bp{};
   bp.streams = b->d_streams;
-  bp.n_streams = b->n;
+  for (int k = 0; k < kKinds; k++) bp.kinds[k] = b->kinds[k];
   bp.total_chunks = total_chunks;
-  bp.tab_b1 = b->tab_b1;
+  bp.tab_b1p = b->tab_b1p;
   bp.tab_a2 = b->tab_a2;
-  bp.tab_w = b->tab_w;
+  bp.tab_wp = b->tab_wp;
   bp.blk_h = b->blk_h;
   bp.blk_dc = b->blk_dc;
   bp.err_flag = b->err_flag;
@@ -450,7 +397,7 @@ void vca_close_batch(vca_batch* b) {
     DeviceGuard g(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    void* bufs[] = {b->tab_b1, b->tab_a2, b->tab_w,   b->blk_h,     b->blk_dc,
+    void* bufs[] = {b->tab_b1p, b->tab_a2, b->tab_wp,   b->blk_h,     b->blk_dc,
                     b->state,  b->rings,  b->err_flag, b->d_streams, b->d_red};
     for (void* p : bufs)
       if (p) (void)hipFree(p);
@@ -527,9 +474,9 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess)
     return bail(VCA_ERR_DEVICE);
   vca_status s;
-  if ((s = balloc(b, &b->tab_b1, kKinds * 64)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->tab_b1p, kKinds * kMaxPack * 64)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->tab_a2, kKinds * 64)) != VCA_OK) return bail(s);
-  if ((s = balloc(b, &b->tab_w, kKinds * 16 * 64)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->tab_wp, kKinds * 16 * 64)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->blk_h, (size_t)blk)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->blk_dc, (size_t)blk)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->state, (size_t)st_total)) != VCA_OK) return bail(s);
@@ -541,23 +488,24 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
       hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(ReduceParams) * n_streams, 0) != hipSuccess)
     return bail(VCA_ERR_OOM);
   if (hipMemset(b->err_flag, 0, sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
-  // operand and weight tables of every kind
-  std::vector<int8_t> b1all(kKinds * 64 * 16), a2all(kKinds * 64 * 16);
+  // operand and weight tables of every kind (packed layout)
+  std::vector<int8_t> b1all((size_t)kKinds * kMaxPack * 64 * 16, 0), a2all(kKinds * 64 * 16);
   std::vector<double> wall(kKinds * 16 * 64);
   for (int bits : {8, 10})
     for (int w : {32, 16, 8})
       for (int kd : {1, 2, 4}) {
         const int kind = kind_of(bits, w, w / kd);
-        std::vector<int8_t> b1, a2;
-        std::vector<double> wt;
+        std::vector<int8_t> b1, a2, b1p;
+        std::vector<double> wt, wtp;
         build_tile_tables(w, w / kd, b1, a2, wt);
-        std::copy(b1.begin(), b1.end(), b1all.begin() + kind * 64 * 16);
+        build_packed_tables(w, w / kd, b1p, wtp);
+        std::copy(b1p.begin(), b1p.end(), b1all.begin() + (size_t)kind * kMaxPack * 64 * 16);
         std::copy(a2.begin(), a2.end(), a2all.begin() + kind * 64 * 16);
-        std::copy(wt.begin(), wt.end(), wall.begin() + kind * 16 * 64);
+        std::copy(wtp.begin(), wtp.end(), wall.begin() + kind * 16 * 64);
       }
-  if (hipMemcpy(b->tab_b1, b1all.data(), b1all.size(), hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(b->tab_b1p, b1all.data(), b1all.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->tab_a2, a2all.data(), a2all.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->tab_w, wall.data(), wall.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(b->tab_wp, wall.data(), wall.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return bail(VCA_ERR_DEVICE);
   if (const char* e = std::getenv("VCA_BATCH_NO_GRAPH")) b->use_graph = !(e[0] == '1');
   TuneCache::get().find(batch_tune_key(b), &b->tuned);
@@ -652,7 +600,7 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
   }
   LaunchChoice best;
   best.ms = 1e30;
-  for (int depth = 1; depth <= 3 && st == VCA_OK; depth++) {
+  for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
     int resident = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batch_kernel_for(depth, b->only8), kThreads, 0) != hipSuccess)
       resident = 1;

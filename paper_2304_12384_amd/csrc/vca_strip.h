@@ -1,0 +1,260 @@
+// vca_strip.h -- strips of 32 x 32 tiles, the work unit of the plain and the
+// batched forward kernels.
+//
+// A strip is a run of up to kStrip consecutive tiles of one tile row of one
+// plane of one frame.  A wavefront decodes a strip once (scalar loads of one
+// plane record), addresses every tile as scalar base + a 32-bit lane offset
+// computed once per strip, and transforms the strip in units of
+// kPack = w / K tiles that share one MFMA tile (vca_tile.h, packed layout).
+// For w = 32 the FP64 energy shares of the strip's tiles are reduced together
+// at the end of the strip.
+#pragma once
+
+#include "vca_host.h"
+#include "vca_tile.h"
+
+namespace vca {
+
+constexpr int kStrip = 8;   // tiles per strip
+
+// One plane as the strip decoder sees it.
+struct StripPlane {
+  const uint8_t* plane;    // first sample of frame 0
+  int64_t fstride;         // bytes between frames
+  int32_t pitch;           // bytes between rows
+  int32_t nbx, nby, ntx;   // blocks per row / column, tiles per row
+  int32_t spr;             // strips per tile row
+  int32_t scnt;            // strips per plane
+  int32_t boff;            // index of the plane's first block within a frame
+  FastDiv div_spr;         // / spr
+};
+
+// The strips of a run of frames of one video.
+struct StripGeom {
+  StripPlane sp[3];
+  int32_t strips_per_frame;
+  FastDiv div_spf;         // / strips_per_frame
+  int32_t per_frame;       // blocks per frame
+  int32_t blk_base;        // output index of block 0 of the run's frame 0
+};
+
+// Host: strips of frames starting at base[P] (Y, U, V) with the given frame
+// strides and pitches, outputs from block blk_base on.
+inline StripGeom make_strip_geom(const Geometry& g, const uint8_t* const base[3],
+                                 const int64_t fstride[3], const int64_t pitch[3],
+                                 int32_t blk_base) {
+  StripGeom G{};
+  for (int P = 0; P < 3; P++) {
+    StripPlane& sp = G.sp[P];
+    sp.plane = base[P];
+    sp.fstride = fstride[P];
+    sp.pitch = (int32_t)pitch[P];
+    sp.nbx = g.nbx[P];
+    sp.nby = g.nby[P];
+    sp.ntx = g.ntx[P];
+    sp.spr = (g.ntx[P] + kStrip - 1) / kStrip;
+    sp.scnt = sp.spr * (g.tcnt[P] / g.ntx[P]);
+    sp.boff = g.boff[P];
+    sp.div_spr = make_fastdiv((uint32_t)sp.spr);
+  }
+  G.strips_per_frame = G.sp[0].scnt + G.sp[1].scnt + G.sp[2].scnt;
+  G.div_spf = make_fastdiv((uint32_t)G.strips_per_frame);
+  G.per_frame = g.per_frame;
+  G.blk_base = blk_base;
+  return G;
+}
+
+struct StripWork {
+  const uint8_t* base;  // first sample of the strip's first tile
+  int32_t pitch;
+  int32_t n;            // tiles in the strip, 1..kStrip
+  int32_t out0;         // output index of block (0, 0) of the first tile
+  int32_t out_row;      // output index step between block rows
+  int32_t vr;           // block rows of the strip inside the grid
+  int32_t vc_last;      // block columns of the last tile inside the grid
+};
+
+// Strip `id` (frame-major, then Y, U, V, then tile rows, then strips along a
+// row).
+template <int kBits, int kW>
+__device__ inline StripWork decode_strip(const StripGeom& G, int id) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kBpt = kTile / kW;
+  const int f = (int)fastdiv((uint32_t)id, G.div_spf);
+  int r = id - f * G.strips_per_frame;
+  int P = 0;
+  if (r >= G.sp[0].scnt) {
+    r -= G.sp[0].scnt;
+    P = 1;
+    if (r >= G.sp[1].scnt) {
+      r -= G.sp[1].scnt;
+      P = 2;
+    }
+  }
+  const StripPlane& pl = G.sp[P];
+  const int ty = (int)fastdiv((uint32_t)r, pl.div_spr);
+  const int tx0 = (r - ty * pl.spr) * kStrip;
+  StripWork w;
+  w.pitch = pl.pitch;
+  w.n = min(kStrip, pl.ntx - tx0);
+  const int by0 = ty * kBpt, bx0 = tx0 * kBpt;
+  w.base = pl.plane + f * pl.fstride + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
+  w.vr = min(kBpt, pl.nby - by0);
+  w.vc_last = min(kBpt, pl.nbx - (tx0 + w.n - 1) * kBpt);
+  w.out0 = G.blk_base + f * G.per_frame + pl.boff + by0 * pl.nbx + bx0;
+  w.out_row = pl.nbx;
+  return w;
+}
+
+// Byte offsets of a lane's samples inside the tiles of a strip (scalar tile
+// base + 32-bit lane offset keeps every load in the saddr form): `a` (and,
+// for 10-bit, `b`) for full tiles, and the same for the strip's last tile.
+// Rows past the block grid (bottom tile row) and 16-byte pieces past it (last
+// tile of a row) are redirected to the strip's first valid row / the lane's
+// first valid piece: a piece that starts inside the block grid lies inside
+// the row's pitch (a multiple of 16 bytes), so every access stays in bounds;
+// the redirected data only feeds blocks that are discarded.
+struct LaneOffsets {
+  uint32_t a, b, last_a, last_b;
+};
+
+template <int kBits, int kW>
+__device__ inline LaneOffsets lane_offsets(const StripWork& s, int lane) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  const int r = lane & 31, g = lane >> 5;
+  const int rows = s.vr * kW;
+  const uint32_t roff = __umul24((uint32_t)(kW == 32 || r < rows ? r : 0), (uint32_t)s.pitch);
+  LaneOffsets o;
+  o.a = roff + 16 * g * kBps;
+  o.b = o.a + 16;
+  if (kW == 32) {            // a w = 32 tile is one complete block
+    o.last_a = o.a;
+    o.last_b = o.b;
+  } else {
+    const int cols = s.vc_last * kW;
+    const int c0 = 16 * g < cols ? 16 * g : 0;
+    const int c1 = 16 * g + 8 < cols ? 16 * g + 8 : c0;
+    o.last_a = roff + c0 * kBps;
+    o.last_b = roff + c1 * kBps;
+  }
+  return o;
+}
+
+template <int kBits, int kW>
+__device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, int t) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  const uint8_t* base = s.base + t * kTile * kBps;
+  const bool last = kW != 32 && t == s.n - 1;
+  TileData d;
+  d.a = *reinterpret_cast<const v4i*>(base + (last ? o.last_a : o.a));
+  if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(base + (last ? o.last_b : o.b));
+  return d;
+}
+
+// Strips id, id + stride, ... (< end) of G.  Each wavefront keeps kDepth
+// units in flight: while it transforms unit u it has issued the loads of
+// unit u + kDepth, which may belong to its next strip (units per strip %
+// kDepth == 0, so ring slots line up across strips).  Every unit issues the
+// same loads whatever the strip length (tile indices are clamped into the
+// strip, and the last strip prefetches itself again), so the compiler waits
+// for exactly the oldest unit's loads; the missing tiles of a short strip are
+// transformed but never stored.  w = 32 stores H and DC once per strip; w =
+// 16 and 8 reduce each unit over the lanes of its blocks and store them.
+template <int kBits, int kW, int kK, int kDepthMax>
+__device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
+                                           const PackConsts<kW, kK>& pc, int id, int stride,
+                                           int end, int lane) {
+  constexpr int kPack = kW / kK;
+  constexpr int kUnits = kStrip / kPack;
+  constexpr int kDepth = kDepthMax < kUnits ? kDepthMax : kUnits;
+  constexpr int kBpt = kTile / kW;
+  static_assert(kUnits % kDepth == 0, "ring slots must line up across strips");
+  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
+  struct Unit {
+    TileData t[kPack];
+  };
+  const int c = lane & 31, g = lane >> 5;
+  const int cc = c % kW, q = cc / kK, bc = c / kW;   // lane's tile in its unit, block column
+
+  auto load_unit = [&](const StripWork& S, const LaneOffsets& O, int u) {
+    Unit d;
+#pragma unroll
+    for (int i = 0; i < kPack; i++) d.t[i] = strip_load<kBits, kW>(S, O, min(u * kPack + i, S.n - 1));
+    return d;
+  };
+
+  if (id >= end) return;
+  StripWork S = decode_strip<kBits, kW>(G, id);
+  LaneOffsets O = lane_offsets<kBits, kW>(S, lane);
+  Unit ring[kDepth];
+#pragma unroll
+  for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
+
+  while (true) {
+    const int id2 = id + stride;
+    const bool more = id2 < end;
+    StripWork S2 = S;
+    LaneOffsets O2 = O;
+    if (more) {
+      S2 = decode_strip<kBits, kW>(G, id2);
+      O2 = lane_offsets<kBits, kW>(S2, lane);
+    }
+    double hs[kUnits];
+    int dcs[kUnits];
+#pragma unroll
+    for (int u = 0; u < kUnits; u++) {
+      const Unit d = ring[u % kDepth];
+      const int v = u + kDepth;   // the unit whose loads go out now
+      ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
+      double h[kBpt];
+      int dc[kBpt];
+      unit_energy<kBits, kW, kK>(out, pc, d.t, h, dc);
+      if constexpr (kW == 32) {
+        hs[u] = h[0];
+        dcs[u] = dc[0];
+      } else {
+        // every row's shares summed over the block's lanes; lane keeps one row
+        const double hr = rows_reduce<kW, kK>(h, lane);
+        const int r = rows_lane_row<kW, kK>(lane);
+        const int t = u * kPack + q;   // this lane's tile within the strip
+        const int vc = t == S.n - 1 ? S.vc_last : kBpt;
+        const bool mine = t < S.n && bc < vc;
+        // one writer per (block, tile): the group's lanes holding a row
+        constexpr int kFree = kBpt == 2 ? kK - 1 : kK / 2 - 1;   // in-group bits summed over
+        if ((cc & kFree) == 0 && mine && r < S.vr) out.blk_h[S.out0 + t * kBpt + r * S.out_row + bc] = hr;
+        if (g == 0 && cc % kK == 0 && mine) {
+#pragma unroll
+          for (int b = 0; b < kBpt; b++)
+            if (b < S.vr) out.blk_dc[S.out0 + t * kBpt + b * S.out_row + bc] = dc[b] + kDcAdd;
+        }
+      }
+    }
+    if (kW == 32) {
+      double h;
+      int t;
+      if constexpr (kPack == 1) {
+        h = reduce_scatter8(hs, lane);
+        t = lane >> 3;
+      } else if constexpr (kPack == 2) {
+        h = reduce_scatter4x2(hs, lane);
+        t = 4 * (lane >> 5) + 2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
+      } else {
+        h = reduce_scatter2x4(hs);
+        t = lane >> 3;
+      }
+      if ((lane & 7) == 0 && t < S.n) out.blk_h[S.out0 + t] = h;
+      // DC of tile u * kPack + q sits in lane q * K (g = 0), register dcs[u]
+      if (g == 0 && cc % kK == 0) {
+#pragma unroll
+        for (int u = 0; u < kUnits; u++)
+          if (u * kPack + q < S.n) out.blk_dc[S.out0 + u * kPack + q] = dcs[u] + kDcAdd;
+      }
+    }
+    if (!more) break;
+    id = id2;
+    S = S2;
+    O = O2;
+  }
+}
+
+}  // namespace vca

@@ -566,4 +566,56 @@ __device__ __forceinline__ void unit_energy(const TileOut& o, const PC& pc,
   }
 }
 
+// ----------------------------------------------------- w = 16, 8 blocks
+// In the packed layout a block's energy is spread over the 2 kK lanes of its
+// (block column, sample tile) group -- kK consecutive lanes in each half --
+// one share per block row held in h[0 .. kBpt - 1].  rows_reduce sums every
+// row's shares over its group and leaves row rows_lane_row(lane) in each
+// lane: the halves split the rows first (lanes < 32 keep the first half of
+// the rows), then, with four rows, the top in-group lane bit picks one of
+// the remaining two, and the other in-group bits are summed over.
+
+// 8-lane pairing across bit 2 (lane i with 7 - i), 4-lane pairing across
+// bit 1, 2-lane pairing across bit 0.
+template <int kLanes>
+__device__ inline double dpp_top(double v) {
+  if constexpr (kLanes == 16) return dpp64<kDppRor8>(v);
+  else if constexpr (kLanes == 8) return dpp64<kDppHalfMirror>(v);
+  else if constexpr (kLanes == 4) return dpp64<kDppXor2>(v);
+  else return dpp64<kDppXor1>(v);
+}
+
+// Sum over the low log2(kLanes) lane bits (DPP inside 16-lane rows).
+template <int kLanes>
+__device__ inline double dpp_allreduce(double v) {
+  if constexpr (kLanes >= 2) v += dpp64<kDppXor1>(v);
+  if constexpr (kLanes >= 4) v += dpp64<kDppXor2>(v);
+  if constexpr (kLanes >= 8) v += dpp64<kDppHalfMirror>(v);
+  if constexpr (kLanes >= 16) v += dpp64<kDppRor8>(v);
+  return v;
+}
+
+template <int kW, int kK>
+__device__ inline int rows_lane_row(int lane) {
+  constexpr int kBpt = kTile / kW;
+  const int half = lane >> 5;
+  if constexpr (kBpt == 2) return half;
+  else return 2 * half + ((lane & (kK / 2)) ? 1 : 0);
+}
+
+template <int kW, int kK>
+__device__ inline double rows_reduce(const double (&h)[kTile / kW], int lane) {
+  constexpr int kBpt = kTile / kW;
+  static_assert(kBpt == 2 || kBpt == 4, "w = 16 or 8");
+  if constexpr (kBpt == 2) {
+    return dpp_allreduce<kK>(fold32(h[0], h[1]));
+  } else {
+    const double r01 = fold32(h[0], h[2]);   // halves: rows 0 | 2
+    const double r23 = fold32(h[1], h[3]);   //         rows 1 | 3
+    const bool top = (lane & (kK / 2)) != 0;
+    const double keep = top ? r23 : r01, send = top ? r01 : r23;
+    return dpp_allreduce<kK / 2>(keep + dpp_top<kK>(send));
+  }
+}
+
 }  // namespace vca

@@ -115,7 +115,7 @@ def test_batch_tune_and_no_graph_path(vca, frames, monkeypatch):
     sub = list(frames[:6])
     b = vca.Batch(STREAMS[:6])
     choice = b.tune(sub, reps=1)
-    assert 1 <= choice["depth"] <= 3 and choice["groups_per_cu"] >= 1 and choice["ms"] > 0
+    assert choice["depth"] in (1, 2, 4) and choice["groups_per_cu"] >= 1 and choice["ms"] > 0
     b.submit(sub)
     tuned = [b.features(s, 0, d["n"]) for s, d in enumerate(STREAMS[:6])]
     b.close()
