@@ -236,8 +236,9 @@ void vca_close_batch(vca_batch* b);
  *   E_t = sum_blocks H_t / (C_Y w^2),
  *   h_t = sum_blocks |H_t - H_{t-1}| / (C_Y w^2), h = 0 at a sequence start,
  * and dH/dX = 2^-(2 log2 w + B - 3) C_w^T (W o sign(Y)) C_w, sign(0) = 0.
- * The transforms run in FP32 (MFMA), block energies and the per-frame sums
- * in FP64.  Input: n_seq sequences of seq_len consecutive float32 frames. */
+ * The transforms run on fp16 matrix cores with FP32 accumulation over exact
+ * fp16 splits of the FP32 operands; block energies and the per-frame sums
+ * are FP64.  Input: n_seq sequences of seq_len consecutive float32 frames. */
 typedef struct {
   uint32_t struct_size; /* = sizeof(vca_grad_config)                                   */
   int32_t width;        /* luma width; >= block_size                                   */
@@ -252,25 +253,27 @@ typedef struct {
   int64_t fstride;      /* floats between consecutive frames (multiple of 4)           */
 } vca_grad_config;
 
-/* Doubles of device workspace the two calls below need (the FP64 block
- * energies of every frame), or -1 for an invalid configuration.  Host only. */
+/* Bytes of device workspace the two calls below need (the FP64 block
+ * energies of every frame and the signs of every tile's coefficients, 256
+ * bytes per 32 x 32 tile), or -1 for an invalid configuration.  Host only. */
 int64_t vca_grad_workspace(const vca_grad_config* cfg);
 
 /* Forward: reads x (device, 16-byte aligned, cfg's layout), writes E[f] and
  * h[f] (device, n_seq * seq_len floats each, frame f = s * seq_len + t) and
- * the block energies into workspace (device, vca_grad_workspace doubles;
- * keep it for vca_energy_backward).  Enqueued on hip_stream (NULL: the
- * default stream); returns without waiting. */
+ * the workspace (device, vca_grad_workspace bytes, 256-byte aligned; keep it
+ * unchanged for vca_energy_backward).  For integer-valued samples below 2^11
+ * the signs of all coefficients, zeros included, are exact.  Enqueued on
+ * hip_stream (NULL: the default stream); returns without waiting. */
 vca_status vca_energy_forward(const vca_grad_config* cfg, const float* x, float* E, float* h,
-                              double* workspace, void* hip_stream);
+                              void* workspace, void* hip_stream);
 
 /* Backward: given dL/dE and dL/dh per frame (device, n_seq * seq_len floats)
- * and the workspace of the forward call on the same x, writes dL/dx to
- * grad_x (device, 16-byte aligned, the same layout as x); every sample within
+ * and the workspace of the forward call, writes dL/dx to grad_x (device,
+ * 16-byte aligned, the layout of the forward's x); every sample within
  * width x height of every frame is written (0 outside the block grid), the
- * pitch padding is not touched.  Enqueued on hip_stream; returns without
- * waiting. */
-vca_status vca_energy_backward(const vca_grad_config* cfg, const float* x, const double* workspace,
+ * pitch padding is not touched.  The samples themselves are not read again.
+ * Enqueued on hip_stream; returns without waiting. */
+vca_status vca_energy_backward(const vca_grad_config* cfg, const void* workspace,
                                const float* grad_E, const float* grad_h, float* grad_x,
                                void* hip_stream);
 

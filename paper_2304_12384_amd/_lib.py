@@ -115,7 +115,7 @@ def lib() -> ctypes.CDLL:
             "vca_close": (None, [P]),
             "vca_grad_workspace": (ctypes.c_int64, [ctypes.POINTER(VcaGradConfig)]),
             "vca_energy_forward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P]),
-            "vca_energy_backward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P, P]),
+            "vca_energy_backward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P]),
             "vca_status_str": (ctypes.c_char_p, [ctypes.c_int]),
             "vca_last_error": (ctypes.c_char_p, [P]),
         }

@@ -7,20 +7,29 @@
 //   E = sum_blocks H / (C_Y w^2),  h_t = sum_blocks |H_t - H_{t-1}| / (C_Y w^2).
 // d/dX of H is 2^-(s1+s2) C^T (W o sign(Y)) C, with sign(0) = 0.
 //
-// Layout (one wavefront per 32 x 32 tile, block-diagonal Cd for w < 32):
-//   forward  T = X Cd^T, Y = Cd T: 16 + 2 x 16 v_mfma_f32_32x32x2f32, the
-//            first accumulator feeding the second pass (split in hi and lo
-//            parts) as its B operand;
-//   backward S' = c o W o sign(Y) per block (c from dL/dE, dL/dh and the
-//            signs of the neighbouring frames' block-energy differences),
-//            V = Cd^T S' (chained), V through a per-wavefront LDS tile into
-//            the A layout, G = V Cd, stored to dL/dX.
+// One wavefront per 32 x 32 tile (block-diagonal Cd for w < 32), on fp16
+// matrix cores (v_mfma_f32_32x32x16_f16, FP32 accumulation) with exact
+// splits of the FP32 operands:
+//   forward  T = X Cd^T with X = x0 + x1 + x2 (three fp16 parts: every FP32
+//            sample exactly), Y = Cd T with T = 4096 hi + lo, lo = lo0 + lo1.
+//            For integer samples below 2^11 every product and partial sum
+//            is exact and Y = 4096 Yh + Yl rounds once: sign(Y), and Y = 0,
+//            are exact.  Block energies in FP64; per tile the signs of the
+//            coefficients go to the workspace as two 16-bit masks per lane.
+//   backward S = W o sign(Y) from the masks (W = w0 + w1, two fp16 parts),
+//            U = S^T Cd, G^T = Cd^T U (U in three fp16 parts), both chained
+//            in registers, then each block of G times its upstream factor
+//            c = (dL/dE_t + dL/dh_t sgn(H_t - H_{t-1})
+//                 - dL/dh_{t+1} sgn(H_{t+1} - H_t)) 2^-(s1+s2) / (C_Y w^2).
+//            The backward reads 256 bytes of masks per tile instead of the
+//            4 KiB tile of samples, and does not repeat the forward passes.
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
@@ -35,26 +44,37 @@ using namespace vca;
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __fp16 h2 __attribute__((ext_vector_type(2)));
 
 namespace {
 
 constexpr int kGWaves = 4;
 constexpr int kGThreads = 64 * kGWaves;
 
-// Per-lane FP32 operand tables (16 values per lane) and FP64 weights.
+// Eight fp16 operand values of one lane (one MFMA slot each), packed.
+struct H8 {
+  uint32_t w[4];
+};
+
+// Per-lane operand tables and weights.  Slot s of MFMA h of lane (c + 32 g):
+//   b1: Cd[c][16 g + 8 h + s]        (stage 1 B; the lane's samples 16 g..)
+//   a2: Cd[c][m_{8h+s}(g)]           (stage 2 A; T rows held in registers)
+//   ct: Cd[m_{8h+s}(g)][c]           (backward: B of S^T Cd and A of Cd^T U)
 struct alignas(16) GradTables {
-  float b1[64][16];   // stage 1 B: lane (k + 32g): Cd[k][16g + t]
-  float a2[64][16];   // stage 2 A: lane (i + 32g): Cd[i][m_t(g)]
-  float v1[64][16];   // backward V = Cd^T S: lane (m + 32g): Cd[m_t(g)][m]
-  float g2[64][16];   // backward G = V Cd:  lane (n + 32g): Cd[16g + t][n]
-  float wf[16][64];   // weight (FP32) of coefficient register j of each lane
-  double wd[16][64];  // weight * 2^-(s1+s2) (FP64) for the energy sums
+  H8 b1[2][64];
+  H8 a2[2][64];
+  H8 ct[2][64];
+  double wd[16][64];   // weight * 2^-(s1+s2) of coefficient register j (energy)
+  float w0[16][64];    // weight = w0 + w1, both fp16 values (backward)
+  float w1[16][64];
 };
 
 struct GradParams {
   const float* x;
   float* gx;
   double* blk_h;        // [frames][C_Y]
+  uint32_t* masks;      // [tiles][64]: bit j positive, bit 16 + j negative
   const float* gE;      // [frames]
   const float* gh;      // [frames]
   const GradTables* tab;
@@ -68,8 +88,7 @@ struct GradParams {
 
 template <int kW>
 struct FTile {
-  const float* base;    // tile origin in x
-  int64_t origin;       // float offset of the tile origin (for gx)
+  int64_t origin;       // float offset of the tile origin
   int32_t f, vr, vc, out0;
 };
 
@@ -83,7 +102,6 @@ __device__ inline FTile<kW> decode_ftile(const GradParams& p, int id) {
   const int tx = r - ty * p.ntx;
   const int by0 = ty * kBpt, bx0 = tx * kBpt;
   t.origin = t.f * p.fstride + (int64_t)by0 * kW * p.pitch + bx0 * kW;
-  t.base = p.x + t.origin;
   t.vr = min(kBpt, p.nby - by0);
   t.vc = min(kBpt, p.nbx - bx0);
   t.out0 = t.f * p.per_frame + by0 * p.nbx + bx0;
@@ -97,7 +115,7 @@ template <int kW>
 __device__ inline void load_ftile(const GradParams& p, const FTile<kW>& t, int lane, float x[16]) {
   const int r = lane & 31, g = lane >> 5;
   const int rows = t.vr * kW, cols = t.vc * kW;
-  const float* row = t.base + (int64_t)(r < rows ? r : 0) * p.pitch;
+  const float* row = p.x + t.origin + (int64_t)(r < rows ? r : 0) * p.pitch;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const int c = 16 * g + 4 * q;
@@ -109,38 +127,76 @@ __device__ inline void load_ftile(const GradParams& p, const FTile<kW>& t, int l
   }
 }
 
-// Y of a tile in the accumulator layout (lane = column, register j = row m_j),
-// without the 2^-(s1+s2) scale.  For integer samples below 2^12 the first
-// pass is exact in FP32; the second splits T = 4096 hi + lo (|lo| <= 2048,
-// both exact) so that C hi and C lo are exact sums, and only their final
-// combination rounds: sign(Y), and Y = 0, are exact.
-__device__ inline v16f tile_y(const float b1[16], const float a2[16], const float x[16]) {
-  v16f d = {};
+__device__ inline uint32_t pk(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(a, b));   // toward zero
+}
+__device__ inline float lo_of(uint32_t p) { return (float)__builtin_bit_cast(h2, p).x; }
+__device__ inline float hi_of(uint32_t p) { return (float)__builtin_bit_cast(h2, p).y; }
+
+// v = p0 + p1 + p2 exactly in fp16 parts (each part keeps the leading 11
+// significant bits of what is left; three parts hold an FP32 significand,
+// down to fp16's smallest subnormal).
+__device__ inline void split3(const float* v, H8& p0, H8& p1, H8& p2) {
 #pragma unroll
-  for (int t = 0; t < 16; t++) d = __builtin_amdgcn_mfma_f32_32x32x2f32(x[t], b1[t], d, 0, 0, 0);
+  for (int q = 0; q < 4; q++) {
+    const float a = v[2 * q], b = v[2 * q + 1];
+    const uint32_t u0 = pk(a, b);
+    const float ra = a - lo_of(u0), rb = b - hi_of(u0);
+    const uint32_t u1 = pk(ra, rb);
+    p0.w[q] = u0;
+    p1.w[q] = u1;
+    p2.w[q] = pk(ra - lo_of(u1), rb - hi_of(u1));
+  }
+}
+
+__device__ inline v16f mma(const H8& a, const H8& b, v16f c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b),
+                                                c, 0, 0, 0);
+}
+
+__device__ inline H8 ld8(const H8 (&t)[64], int lane) {
+  const v4i v = *reinterpret_cast<const v4i*>(&t[lane]);
+  H8 h;
+  h.w[0] = (uint32_t)v[0];
+  h.w[1] = (uint32_t)v[1];
+  h.w[2] = (uint32_t)v[2];
+  h.w[3] = (uint32_t)v[3];
+  return h;
+}
+
+// Y of a tile in the accumulator layout (lane = column, register j = row
+// m_j), without the 2^-(s1+s2) scale.
+__device__ inline v16f tile_y(const H8 (&b1)[2], const H8 (&a2)[2], const float x[16]) {
+  v16f t = {};
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    H8 x0, x1, x2;
+    split3(x + 8 * h, x0, x1, x2);
+    t = mma(x0, b1[h], t);
+    t = mma(x1, b1[h], t);
+    t = mma(x2, b1[h], t);
+  }
   v16f yh = {}, yl = {};
 #pragma unroll
-  for (int t = 0; t < 16; t++) {
-    const float hi = rintf(d[t] * (1.f / 4096.f));
-    const float lo = fmaf(-4096.f, hi, d[t]);
-    yh = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[t], hi, yh, 0, 0, 0);
-    yl = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[t], lo, yl, 0, 0, 0);
+  for (int h = 0; h < 2; h++) {
+    H8 hi, l0, l1;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int j = 8 * h + 2 * q;
+      const float ha = rintf(t[j] * (1.f / 4096.f)), hb = rintf(t[j + 1] * (1.f / 4096.f));
+      const float la = fmaf(-4096.f, ha, t[j]), lb = fmaf(-4096.f, hb, t[j + 1]);
+      hi.w[q] = pk(ha, hb);
+      l0.w[q] = pk(la, lb);
+      l1.w[q] = pk(la - lo_of(l0.w[q]), lb - hi_of(l0.w[q]));
+    }
+    yh = mma(a2[h], hi, yh);
+    yl = mma(a2[h], l0, yl);
+    yl = mma(a2[h], l1, yl);
   }
   v16f y;
 #pragma unroll
   for (int j = 0; j < 16; j++) y[j] = fmaf(4096.f, yh[j], yl[j]);
   return y;
-}
-
-__device__ inline void load_row16(const float (*tab)[16], int lane, float out[16]) {
-#pragma unroll
-  for (int q = 0; q < 16; q += 4) {
-    const v4f v = *reinterpret_cast<const v4f*>(&tab[lane][q]);
-    out[q] = v[0];
-    out[q + 1] = v[1];
-    out[q + 2] = v[2];
-    out[q + 3] = v[3];
-  }
 }
 
 template <int kW, int kK>
@@ -152,9 +208,12 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
   double wd[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) wd[j] = reg_used(j, kW, kK) ? p.tab->wd[j][lane] : 0.0;
-  float b1[16], a2[16];
-  load_row16(p.tab->b1, lane, b1);
-  load_row16(p.tab->a2, lane, a2);
+  H8 b1[2], a2[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    b1[h] = ld8(p.tab->b1[h], lane);
+    a2[h] = ld8(p.tab->a2[h], lane);
+  }
   const int total = p.n_frames * p.tiles_per_frame;
   for (int id = blockIdx.x * kGWaves + wave; id < total; id += gridDim.x * kGWaves) {
     const FTile<kW> t = decode_ftile<kW>(p, id);
@@ -164,9 +223,14 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
     double h[kBpt];
 #pragma unroll
     for (int b = 0; b < kBpt; b++) h[b] = 0.0;
+    uint32_t mask = 0;
 #pragma unroll
-    for (int j = 0; j < 16; j++)
-      if (reg_used(j, kW, kK)) h[(8 * (j / 4)) / kW] = fma(wd[j], (double)fabsf(y[j]), h[(8 * (j / 4)) / kW]);
+    for (int j = 0; j < 16; j++) {
+      if (!reg_used(j, kW, kK)) continue;
+      h[(8 * (j / 4)) / kW] = fma(wd[j], (double)fabsf(y[j]), h[(8 * (j / 4)) / kW]);
+      mask |= (y[j] > 0.f ? 1u << j : 0u) | (y[j] < 0.f ? 1u << (16 + j) : 0u);
+    }
+    p.masks[(int64_t)id * 64 + lane] = mask;
 #pragma unroll
     for (int off = 1; off < kW; off <<= 1)
 #pragma unroll
@@ -215,73 +279,89 @@ __device__ inline float sgn(double v) { return v > 0.0 ? 1.f : (v < 0.0 ? -1.f :
 template <int kW, int kK>
 __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
   constexpr int kBpt = kTile / kW;
-  __shared__ float vt[kGWaves][32][33];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int r = lane & 31, g = lane >> 5;
-  float wf[16];
+  float w0[16], w1[16];
 #pragma unroll
-  for (int j = 0; j < 16; j++) wf[j] = reg_used(j, kW, kK) ? p.tab->wf[j][lane] : 0.f;
-  float b1[16], a2[16], v1[16], g2[16];
-  load_row16(p.tab->b1, lane, b1);
-  load_row16(p.tab->a2, lane, a2);
-  load_row16(p.tab->v1, lane, v1);
-  load_row16(p.tab->g2, lane, g2);
+  for (int j = 0; j < 16; j++) {
+    w0[j] = reg_used(j, kW, kK) ? p.tab->w0[j][lane] : 0.f;
+    w1[j] = reg_used(j, kW, kK) ? p.tab->w1[j][lane] : 0.f;
+  }
+  H8 ct[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) ct[h] = ld8(p.tab->ct[h], lane);
   const int total = p.n_frames * p.tiles_per_frame;
   for (int id = blockIdx.x * kGWaves + wave; id < total; id += gridDim.x * kGWaves) {
     const FTile<kW> t = decode_ftile<kW>(p, id);
-    float x[16];
-    load_ftile<kW>(p, t, lane, x);
-    const v16f y = tile_y(b1, a2, x);
-    // upstream coefficient of each block of this lane's block column
+    const uint32_t mask = p.masks[(int64_t)id * 64 + lane];
+    // S = W o sign(Y): lane (c + 32 g) register j is coefficient (m_j, c);
+    // as S^T's A operand, slot s of MFMA h is register 8 h + s
+    v16f u = {};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      H8 s0, s1;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        float a[2][2];
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+          const int j = 8 * h + 2 * q + e;
+          const float sg = (mask >> j) & 1u ? 1.f : ((mask >> (16 + j)) & 1u ? -1.f : 0.f);
+          a[0][e] = sg * w0[j];
+          a[1][e] = sg * w1[j];
+        }
+        s0.w[q] = pk(a[0][0], a[0][1]);
+        s1.w[q] = pk(a[1][0], a[1][1]);
+      }
+      u = mma(s0, ct[h], u);
+      u = mma(s1, ct[h], u);
+    }
+    // G^T = Cd^T U: U's register 8 h + s is the B operand's slot s
+    v16f gt = {};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      float uv[8];
+#pragma unroll
+      for (int s = 0; s < 8; s++) uv[s] = u[8 * h + s];
+      H8 u0, u1, u2;
+      split3(uv, u0, u1, u2);
+      gt = mma(ct[h], u0, gt);
+      gt = mma(ct[h], u1, gt);
+      gt = mma(ct[h], u2, gt);
+    }
+    // upstream factor of each block: lane's pixel row r is in block row
+    // r / w; register j's pixel column m_j in block column m_j / w
     const int f = t.f;
     const int pos = f % p.seq_len;
     const bool has_prev = pos > 0, has_next = pos + 1 < p.seq_len;
     const float gE = p.gE[f];
     const float ghf = has_prev ? p.gh[f] : 0.f;
     const float ghn = has_next ? p.gh[f + 1] : 0.f;
-    const int bc = min(r / kW, t.vc - 1);
+    const int br = min(r / kW, t.vr - 1);
     float cb[kBpt];
 #pragma unroll
     for (int b = 0; b < kBpt; b++) {
-      const int idx = t.out0 + min(b, t.vr - 1) * p.nbx + bc;
+      const int idx = t.out0 + br * p.nbx + min(b, t.vc - 1);
       const double hc = p.blk_h[idx];
       float c = gE;
       if (has_prev) c += ghf * sgn(hc - p.blk_h[idx - p.per_frame]);
       if (has_next) c -= ghn * sgn(p.blk_h[idx + p.per_frame] - hc);
       cb[b] = c * p.grad_scale;
     }
-    v16f s;
-#pragma unroll
-    for (int j = 0; j < 16; j++) {
-      const float sy = y[j] > 0.f ? 1.f : (y[j] < 0.f ? -1.f : 0.f);
-      s[j] = cb[(8 * (j / 4)) / kW] * wf[j] * sy;
-    }
-    v16f v = {};
-#pragma unroll
-    for (int q = 0; q < 16; q++) v = __builtin_amdgcn_mfma_f32_32x32x2f32(v1[q], s[q], v, 0, 0, 0);
-    // V[m_j][k] -> LDS row-major, then rows back in the A-operand layout
-#pragma unroll
-    for (int j = 0; j < 16; j++) vt[wave][reg_row(j, g)][r] = v[j];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float a[16];
-#pragma unroll
-    for (int q = 0; q < 16; q++) a[q] = vt[wave][r][16 * g + q];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    v16f gm = {};
-#pragma unroll
-    for (int q = 0; q < 16; q++) gm = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], g2[q], gm, 0, 0, 0);
-    // G[m_j][n]: lane n = r, row m_j; only pixels of valid blocks are written
-    float* out = p.gx + t.origin;
+    // pixel (r, m_j): registers 4q..4q+3 are columns 8q + 4g + 0..3
+    float* out = p.gx + t.origin + (int64_t)r * p.pitch;
     const int rows = t.vr * kW, cols = t.vc * kW;
+    if (r < rows) {
 #pragma unroll
-    for (int j = 0; j < 16; j++) {
-      const int m = reg_row(j, g);
-      if (m < rows && r < cols) out[(int64_t)m * p.pitch + r] = gm[j];
+      for (int q = 0; q < 4; q++) {
+        const int col = 8 * q + 4 * g;
+        if (col < cols) {
+          const float c = cb[col / kW];
+          const v4f v = {gt[4 * q] * c, gt[4 * q + 1] * c, gt[4 * q + 2] * c, gt[4 * q + 3] * c};
+          *reinterpret_cast<v4f*>(out + col) = v;
+        }
+      }
     }
   }
 }
@@ -309,6 +389,17 @@ __global__ __launch_bounds__(256) void zero_border_kernel(float* gx, int64_t pit
   }
 }
 
+uint16_t half_bits(float v) {
+  const _Float16 h = (_Float16)v;
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+
+void put8(H8& dst, const float (&v)[8]) {
+  for (int q = 0; q < 4; q++) dst.w[q] = half_bits(v[2 * q]) | ((uint32_t)half_bits(v[2 * q + 1]) << 16);
+}
+
 void build_grad_tables(int w, int K, int bit_depth, GradTables& t) {
   std::vector<int8_t> b1, a2;
   std::vector<double> wt;
@@ -316,16 +407,25 @@ void build_grad_tables(int w, int K, int bit_depth, GradTables& t) {
   const double sc = std::ldexp(1.0, -(2 * ilog2c(w) + bit_depth - 3));
   for (int lane = 0; lane < 64; lane++) {
     const int c = lane & 31, g = lane >> 5;
-    for (int q = 0; q < 16; q++) {
-      const int mt = reg_row(q, g);
-      t.b1[lane][q] = (float)matd(w, c, 16 * g + q);
-      t.a2[lane][q] = (float)matd(w, c, mt);
-      t.v1[lane][q] = (float)matd(w, mt, c);
-      t.g2[lane][q] = (float)matd(w, 16 * g + q, c);
+    for (int h = 0; h < 2; h++) {
+      float vb1[8], va2[8], vct[8];
+      for (int s = 0; s < 8; s++) {
+        const int m = reg_row(8 * h + s, g);
+        vb1[s] = (float)matd(w, c, 16 * g + 8 * h + s);
+        va2[s] = (float)matd(w, c, m);
+        vct[s] = (float)matd(w, m, c);
+      }
+      put8(t.b1[h][lane], vb1);
+      put8(t.a2[h][lane], va2);
+      put8(t.ct[h][lane], vct);
     }
     for (int j = 0; j < 16; j++) {
-      t.wf[j][lane] = (float)wt[j * 64 + lane];
-      t.wd[j][lane] = wt[j * 64 + lane] * sc;
+      const double wv = wt[j * 64 + lane];
+      t.wd[j][lane] = wv * sc;
+      const float hi = (float)(_Float16)(float)wv;      // nearest fp16
+      const float lo = (float)(_Float16)(float)(wv - (double)hi);
+      t.w0[j][lane] = hi;
+      t.w1[j][lane] = lo;
     }
   }
 }
@@ -364,12 +464,26 @@ vca_status check_grad_config(const vca_grad_config* c) {
   return VCA_OK;
 }
 
-struct GradLaunch {
-  GradParams p{};
-  int n_frames = 0;
+// Workspace layout: FP64 block energies of every frame, then the sign masks
+// (64 words per tile), 256-byte aligned.
+struct WorkspaceLayout {
+  int64_t h_bytes, mask_off, bytes;
 };
 
-// Tables live in device memory per (w, K, bit depth); built once per process.
+WorkspaceLayout workspace_layout(const vca_grad_config* c) {
+  const int w = c->block_size, bpt = kTile / w;
+  const int64_t nbx = c->width / w, nby = c->height / w;
+  const int64_t tiles = ((nbx + bpt - 1) / bpt) * ((nby + bpt - 1) / bpt);
+  const int64_t frames = (int64_t)c->n_seq * c->seq_len;
+  WorkspaceLayout L;
+  L.h_bytes = nbx * nby * frames * (int64_t)sizeof(double);
+  L.mask_off = (L.h_bytes + 255) / 256 * 256;
+  L.bytes = L.mask_off + tiles * frames * 64 * (int64_t)sizeof(uint32_t);
+  return L;
+}
+
+// Tables live in device memory per (device, w, K, bit depth); built once per
+// process and kept until it ends.
 struct GradTableCache {
   std::mutex mu;
   std::map<std::tuple<int, int, int, int>, GradTables*> map;
@@ -403,19 +517,14 @@ vca_status get_tables(const vca_grad_config* c, int K, const GradTables** out) {
     (void)hipFree(d);
     return VCA_ERR_DEVICE;
   }
-  tc.map[key] = d;   // kept until the process ends
+  tc.map[key] = d;
   *out = d;
   return VCA_OK;
 }
 
-vca_status prepare(const vca_grad_config* c, const float* x, GradLaunch& L) {
-  vca_status s = check_grad_config(c);
-  if (s != VCA_OK) return s;
-  if (!x || ((uintptr_t)x & 15)) return VCA_ERR_INVALID_ARG;
+vca_status prepare(const vca_grad_config* c, void* workspace, GradParams& p) {
   const int w = c->block_size, K = c->lowpass_k == 0 ? w : c->lowpass_k;
   const int bpt = kTile / w;
-  GradParams& p = L.p;
-  p.x = x;
   p.pitch = c->pitch;
   p.fstride = c->fstride;
   p.nbx = c->width / w;
@@ -429,7 +538,9 @@ vca_status prepare(const vca_grad_config* c, const float* x, GradLaunch& L) {
   p.seq_len = c->seq_len;
   p.grad_scale = (float)(std::ldexp(1.0, -(2 * ilog2c(w) + c->bit_depth - 3)) /
                          ((double)p.per_frame * w * w));
-  L.n_frames = p.n_frames;
+  const WorkspaceLayout L = workspace_layout(c);
+  p.blk_h = static_cast<double*>(workspace);
+  p.masks = reinterpret_cast<uint32_t*>(static_cast<char*>(workspace) + L.mask_off);
   return get_tables(c, K, &p.tab);
 }
 
@@ -454,49 +565,48 @@ extern "C" {
 
 int64_t vca_grad_workspace(const vca_grad_config* c) {
   if (check_grad_config(c) != VCA_OK) return -1;
-  return (int64_t)(c->width / c->block_size) * (c->height / c->block_size) * c->n_seq * c->seq_len;
+  return workspace_layout(c).bytes;
 }
 
 vca_status vca_energy_forward(const vca_grad_config* c, const float* x, float* E, float* h,
-                              double* workspace, void* hip_stream) {
-  if (!x || ((uintptr_t)x & 15) || !E || !h || !workspace) return VCA_ERR_INVALID_ARG;
-  GradLaunch L;
+                              void* workspace, void* hip_stream) {
+  if (!x || ((uintptr_t)x & 15) || !E || !h || !workspace || ((uintptr_t)workspace & 255))
+    return VCA_ERR_INVALID_ARG;
   vca_status s = check_grad_config(c);
   if (s != VCA_OK) return s;
   DeviceGuard guard(c->device);
-  if ((s = prepare(c, x, L)) != VCA_OK) return s;
-  L.p.blk_h = workspace;
+  GradParams p{};
+  if ((s = prepare(c, workspace, p)) != VCA_OK) return s;
+  p.x = x;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  if ((s = launch_grad(c, L.p, false, st)) != VCA_OK) return s;
-  const double norm = 1.0 / ((double)L.p.per_frame * c->block_size * c->block_size);
-  hipLaunchKernelGGL(energy_reduce_kernel, dim3(L.n_frames), dim3(256), 0, st, workspace,
-                     L.p.per_frame, L.p.seq_len, norm, E, h);
+  if ((s = launch_grad(c, p, false, st)) != VCA_OK) return s;
+  const double norm = 1.0 / ((double)p.per_frame * c->block_size * c->block_size);
+  hipLaunchKernelGGL(energy_reduce_kernel, dim3(p.n_frames), dim3(256), 0, st, p.blk_h, p.per_frame,
+                     p.seq_len, norm, E, h);
   return hipGetLastError() == hipSuccess ? VCA_OK : VCA_ERR_DEVICE;
 }
 
-vca_status vca_energy_backward(const vca_grad_config* c, const float* x, const double* workspace,
-                               const float* grad_E, const float* grad_h, float* grad_x,
-                               void* hip_stream) {
-  if (!x || ((uintptr_t)x & 15) || !workspace || !grad_E || !grad_h || !grad_x ||
+vca_status vca_energy_backward(const vca_grad_config* c, const void* workspace, const float* grad_E,
+                               const float* grad_h, float* grad_x, void* hip_stream) {
+  if (!workspace || ((uintptr_t)workspace & 255) || !grad_E || !grad_h || !grad_x ||
       ((uintptr_t)grad_x & 15))
     return VCA_ERR_INVALID_ARG;
-  GradLaunch L;
   vca_status s = check_grad_config(c);
   if (s != VCA_OK) return s;
   DeviceGuard guard(c->device);
-  if ((s = prepare(c, x, L)) != VCA_OK) return s;
-  L.p.blk_h = const_cast<double*>(workspace);
-  L.p.gE = grad_E;
-  L.p.gh = grad_h;
-  L.p.gx = grad_x;
+  GradParams p{};
+  if ((s = prepare(c, const_cast<void*>(workspace), p)) != VCA_OK) return s;
+  p.gE = grad_E;
+  p.gh = grad_h;
+  p.gx = grad_x;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-  if ((s = launch_grad(c, L.p, true, st)) != VCA_OK) return s;
+  if ((s = launch_grad(c, p, true, st)) != VCA_OK) return s;
   const int w = c->block_size;
-  const int grid_w = L.p.nbx * w, grid_h = L.p.nby * w;
+  const int grid_w = p.nbx * w, grid_h = p.nby * w;
   const int64_t border = (int64_t)(c->height - grid_h) * c->width + (int64_t)grid_h * (c->width - grid_w);
   if (border > 0) {
     const int gx_blocks = (int)std::min<int64_t>((border + 255) / 256, 1024);
-    hipLaunchKernelGGL(zero_border_kernel, dim3(gx_blocks, L.n_frames), dim3(256), 0, st, grad_x,
+    hipLaunchKernelGGL(zero_border_kernel, dim3(gx_blocks, p.n_frames), dim3(256), 0, st, grad_x,
                        c->pitch, c->fstride, c->width, c->height, grid_w, grid_h);
     if (hipGetLastError() != hipSuccess) return VCA_ERR_DEVICE;
   }

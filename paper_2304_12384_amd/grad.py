@@ -6,7 +6,8 @@ Forward and backward run in the HIP library (``vca_energy_forward`` and
 this module only marshals tensors.  The features are those of the block
 transform with its two roundings dropped (scale 2^-(2 log2 w + B - 3)), so
 they are piecewise linear in the samples and the backward is
-C^T (W o sign(Y)) C per block, with sign(0) = 0.
+C^T (W o sign(Y)) C per block, with sign(0) = 0.  The forward keeps the
+coefficient signs in its workspace; the backward reads those, not x.
 """
 from __future__ import annotations
 
@@ -51,14 +52,16 @@ class VCAEnergyFn(torch.autograd.Function):
         xp = _prepare(x.detach())
         cfg = _config(xp, block_size, lowpass_k, bit_depth)
         L = _lib.lib()
-        n_ws = L.vca_grad_workspace(ctypes.byref(cfg))
+        n_ws = L.vca_grad_workspace(ctypes.byref(cfg))   # bytes
         if n_ws < 0:
             raise ValueError(f"unsupported configuration {tuple(x.shape)}, w={block_size}, "
                              f"K={lowpass_k}, B={bit_depth}")
         B, T = x.shape[:2]
         E = torch.empty(B, T, device=x.device, dtype=torch.float32)
         h = torch.empty(B, T, device=x.device, dtype=torch.float32)
-        ws = torch.empty(max(n_ws, 1), device=x.device, dtype=torch.float64)
+        ws = torch.empty(n_ws, device=x.device, dtype=torch.uint8)
+        if ws.data_ptr() % 256:
+            raise RuntimeError("workspace allocation is not 256-byte aligned")
         stream = torch.cuda.current_stream(x.device).cuda_stream
         check(L.vca_energy_forward(ctypes.byref(cfg), xp.data_ptr(), E.data_ptr(), h.data_ptr(),
                                    ws.data_ptr(), stream), "vca_energy_forward")
@@ -76,8 +79,8 @@ class VCAEnergyFn(torch.autograd.Function):
         cfg = _config(xp, block_size, lowpass_k, bit_depth)
         gx = torch.empty(xp.shape[:3] + (xp.stride(2),), device=xp.device, dtype=torch.float32)
         stream = torch.cuda.current_stream(xp.device).cuda_stream
-        check(_lib.lib().vca_energy_backward(ctypes.byref(cfg), xp.data_ptr(), ws.data_ptr(),
-                                             gE.data_ptr(), gh.data_ptr(), gx.data_ptr(), stream),
+        check(_lib.lib().vca_energy_backward(ctypes.byref(cfg), ws.data_ptr(), gE.data_ptr(),
+                                             gh.data_ptr(), gx.data_ptr(), stream),
               "vca_energy_backward")
         return gx[..., :xp.shape[3]], None, None, None
 

@@ -106,9 +106,11 @@ def grad_cfg(**kw):
 def test_grad_config_layout_and_workspace():
     assert ctypes.sizeof(_lib.VcaGradConfig) == 56
     L = _lib.lib()
-    assert L.vca_grad_workspace(ctypes.byref(grad_cfg())) == 60 * 33 * 32
-    assert L.vca_grad_workspace(ctypes.byref(grad_cfg(block_size=8, lowpass_k=2, n_seq=1,
-                                                      seq_len=3))) == 240 * 135 * 3
+    def ws(blocks, tiles):   # FP64 block energies, 256-byte aligned, then 256 B of masks per tile
+        return (blocks * 8 + 255) // 256 * 256 + tiles * 256
+    assert L.vca_grad_workspace(ctypes.byref(grad_cfg())) == ws(60 * 33 * 32, 60 * 33 * 32)
+    assert L.vca_grad_workspace(ctypes.byref(grad_cfg(block_size=8, lowpass_k=2, n_seq=1, seq_len=3))) \
+        == ws(240 * 135 * 3, 60 * 34 * 3)
 
 
 @pytest.mark.parametrize("bad", [
@@ -122,7 +124,7 @@ def test_bad_grad_config_rejected_before_device(bad):
     assert L.vca_grad_workspace(ctypes.byref(c)) == -1
     p = ctypes.c_void_p(1 << 20)   # never dereferenced: the configuration fails first
     assert L.vca_energy_forward(ctypes.byref(c), p, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
-    assert L.vca_energy_backward(ctypes.byref(c), p, p, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), p, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
 
 
 def test_grad_null_and_misaligned_arguments():
@@ -134,5 +136,7 @@ def test_grad_null_and_misaligned_arguments():
     assert L.vca_energy_forward(ctypes.byref(c), None, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_energy_forward(ctypes.byref(c), odd, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_energy_forward(ctypes.byref(c), p, p, p, None, None) == _lib.VCA_ERR_INVALID_ARG
-    assert L.vca_energy_backward(ctypes.byref(c), p, p, p, p, odd, None) == _lib.VCA_ERR_INVALID_ARG
-    assert L.vca_energy_backward(ctypes.byref(c), p, None, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_forward(ctypes.byref(c), p, p, p, odd, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), p, p, p, odd, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), odd, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_energy_backward(ctypes.byref(c), None, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
