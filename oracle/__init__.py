@@ -151,3 +151,31 @@ def analyze(cfg: Config, y: np.ndarray, u: np.ndarray, v: np.ndarray, *,
         n, threads, _ptr(hp), _ptr(feats), _ptr(bh), _ptr(bdc), _ptr(co))
     _check(rc, "analyze")
     return Result(feats, bh, bdc, co)
+
+
+# --------------------------------------------------------------- downsampling
+# The paper's own low-pass option (Section 2, optimisation (3)) evaluates the
+# features on the video spatially downsampled by two.  The filter is not
+# stated; the reading taken here: each output sample is the mean of a 2 x 2
+# input block, rounded half up, in integer arithmetic, on every plane.  Frame
+# dimensions must be multiples of 4 so that the result is 4:2:0 video of
+# half the width and height.
+
+def downsample(plane: np.ndarray) -> np.ndarray:
+    """[..., H, W] uint8/uint16 -> [..., H/2, W/2] of (a + b + c + d + 2) >> 2,
+    a..d the 2 x 2 block (H, W even)."""
+    p = np.asarray(plane)
+    assert p.shape[-1] % 2 == 0 and p.shape[-2] % 2 == 0, p.shape
+    q = p.astype(np.int64)
+    s = q[..., 0::2, 0::2] + q[..., 0::2, 1::2] + q[..., 1::2, 0::2] + q[..., 1::2, 1::2]
+    return ((s + 2) >> 2).astype(p.dtype)
+
+
+def analyze_downsampled(cfg: Config, y: np.ndarray, u: np.ndarray, v: np.ndarray,
+                        **kw) -> Result:
+    """The features of video (cfg.width x cfg.height) after 2x downsampling
+    of every plane: analyze() on the (width/2 x height/2) 4:2:0 video."""
+    if cfg.width % 4 or cfg.height % 4:
+        raise OracleError("downsampling needs width and height divisible by 4")
+    half = Config(cfg.width // 2, cfg.height // 2, cfg.bit_depth, cfg.block_size, cfg.lowpass_k)
+    return analyze(half, downsample(y), downsample(u), downsample(v), **kw)
