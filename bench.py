@@ -68,10 +68,17 @@ def cpu_baseline(sv, frames: int, lowpass_k: int = 0) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
-def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool) -> dict:
+def downsampled_bytes_per_frame(width: int, height: int, w: int) -> int:
+    """Input samples under the complete w x w blocks of the half-size planes
+    (each analysed sample is the mean of a 2 x 2 input block)."""
+    return 4 * algorithmic_bytes_per_frame(width // 2, height // 2, w)
+
+
+def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool,
+             downsample: bool = False) -> dict:
     import torch
     an = vca.Analyzer(WIDTH, HEIGHT, block_size=BLOCK, lowpass_k=lowpass_k, timing=True,
-                      max_batch=MAX_BATCH)
+                      max_batch=MAX_BATCH, downsample=downsample)
     planes = dev.planes()
     launch = an.tune(*planes, reps=2) if tune else an.tuned_launch()
     for _ in range(warmup):
@@ -90,9 +97,13 @@ def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool) -> d
     fwd_ms = tm["forward_ms"] / max(1, tm["forward_launches"])
     red_ms = tm["reduce_ms"] / max(1, tm["reduce_launches"])
     frames_per_launch = tm["frames"] / max(1, tm["forward_launches"])
-    alg_bytes = algorithmic_bytes_per_frame(WIDTH, HEIGHT, BLOCK) * frames_per_launch
+    per_frame = (downsampled_bytes_per_frame if downsample else algorithmic_bytes_per_frame)(
+        WIDTH, HEIGHT, BLOCK)
+    alg_bytes = per_frame * frames_per_launch
     gbs = alg_bytes / (fwd_ms * 1e-3) / 1e9
-    tops = mfma_ops_per_frame(WIDTH, HEIGHT, BLOCK, lowpass_k) * frames_per_launch / (fwd_ms * 1e-3) / 1e12
+    mfma_frame = (mfma_ops_per_frame(WIDTH // 2, HEIGHT // 2, BLOCK) if downsample
+                  else mfma_ops_per_frame(WIDTH, HEIGHT, BLOCK, lowpass_k))
+    tops = mfma_frame * frames_per_launch / (fwd_ms * 1e-3) / 1e12
     return {
         "fps": steps * FRAMES / dt,
         "ms_per_step": dt * 1e3 / steps,
@@ -339,8 +350,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-frames", type=int, default=512,
                     help="frames of the oracle's bounded CPU sample (0 skips it)")
-    ap.add_argument("--modes", default="full,lowpass,batch,backward",
-                    help="comma list of full, lowpass, batch, backward")
+    ap.add_argument("--modes", default="full,lowpass,downsample,batch,backward",
+                    help="comma list of full, lowpass (K = 16 crop), downsample (the paper's 2x "
+                         "downsampled low-pass), batch, backward")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB from a cold source (the "
@@ -362,16 +374,17 @@ def main() -> int:
     results = {}
     modes = args.modes.split(",")
     sv = dev = None
-    if "full" in modes or "lowpass" in modes or args.cpu_frames > 0:
+    if any(m in modes for m in ("full", "lowpass", "downsample")) or args.cpu_frames > 0:
         log("generating the 600-frame 2160p synthetic workload")
         sv = synth.scene_video(WIDTH, HEIGHT, FRAMES)
         dev = scene_to_device(sv)
         torch.cuda.synchronize()
         log(f"frames resident on the device: {dev.nbytes / 1e9:.2f} GB")
-    for mode in (m for m in modes if m in ("full", "lowpass")):
-        k = 0 if mode == "full" else 16
+    for mode in (m for m in modes if m in ("full", "lowpass", "downsample")):
+        k = 16 if mode == "lowpass" else 0
         log(f"timing mode={mode} steps={args.steps} warmup={args.warmup}")
-        results[mode] = run_mode(vca, dev, k, args.steps, args.warmup, not args.no_tune)
+        results[mode] = run_mode(vca, dev, k, args.steps, args.warmup, not args.no_tune,
+                                 downsample=mode == "downsample")
         log(f"mode={mode}: {results[mode]['fps']:.0f} frames/s, forward kernel "
             f"{results[mode]['forward_kernel_ms']:.3f} ms/launch, launch {results[mode]['launch']}")
     batch = None
@@ -427,6 +440,13 @@ def main() -> int:
         "launch": head["launch"],
         "cpu_baseline": cpu,
     }
+    if "downsample" in results and "full" in results:
+        ds = results["downsample"]
+        line["lowpass_downsample"] = {"value": ds["fps"], "unit": "frames/s",
+                                      "ms_per_step": ds["ms_per_step"], "roofline": ds["roofline"],
+                                      "mfma": ds["mfma"], "forward_kernel_ms": ds["forward_kernel_ms"],
+                                      "launch": ds["launch"],
+                                      "what": "planes downsampled 2x (2x2 mean), full 32x32 DCT"}
     if "lowpass" in results and "full" in results:
         lp = results["lowpass"]
         line["lowpass_k16"] = {"value": lp["fps"], "unit": "frames/s",

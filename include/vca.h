@@ -58,6 +58,15 @@ typedef enum {
 #define VCA_F_KEEP_COEFFS 0x1u /* keep the K x K int16 coefficients of the last call (tests) */
 #define VCA_F_VALIDATE 0x2u    /* 10-bit: count samples above 1023; vca_features then fails  */
 #define VCA_F_TIMING 0x4u      /* record HIP events around every kernel launch (vca_timing)  */
+#define VCA_F_DOWNSAMPLE 0x8u  /* the paper's own low-pass option (Section 2, (3)): every     \
+                                  plane is downsampled by two -- each sample the mean of a    \
+                                  2 x 2 block, rounded half up -- and the features are those  \
+                                  of the half-size video with the full w x w transform.       \
+                                  Needs width and height divisible by 4, width/4 and          \
+                                  height/4 >= block_size, lowpass_k 0 or w; not with          \
+                                  VCA_F_KEEP_COEFFS or the batched form (VCA_ERR_UNSUPPORTED). \
+                                  Frames are passed at full size; vca_block_counts and the    \
+                                  per-block exports refer to the half-size planes.            */
 
 typedef struct {
   uint32_t struct_size;  /* = sizeof(vca_config); guards ABI evolution                    */

@@ -21,6 +21,7 @@ VCA_ERR_STATE = 5
 VCA_F_KEEP_COEFFS = 0x1
 VCA_F_VALIDATE = 0x2
 VCA_F_TIMING = 0x4
+VCA_F_DOWNSAMPLE = 0x8
 
 # Every symbol include/vca.h declares.
 EXPORTS = (

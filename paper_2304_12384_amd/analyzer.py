@@ -18,8 +18,9 @@ FEATURE_NAMES = ("E_Y", "h", "L_Y", "E_U", "E_V", "L_U", "L_V")
 
 
 def block_counts(width: int, height: int, block_size: int = 32, bit_depth: int = 8,
-                 lowpass_k: int = 0) -> tuple[int, int, int]:
-    cfg = _config(width, height, bit_depth, block_size, lowpass_k, 0, 0, 0, 0)
+                 lowpass_k: int = 0, downsample: bool = False) -> tuple[int, int, int]:
+    cfg = _config(width, height, bit_depth, block_size, lowpass_k, 0,
+                  _lib.VCA_F_DOWNSAMPLE if downsample else 0, 0, 0)
     out = (ctypes.c_int32 * 3)()
     check(_lib.lib().vca_block_counts(ctypes.byref(cfg), out), "vca_block_counts")
     return out[0], out[1], out[2]
@@ -54,12 +55,13 @@ class Analyzer:
     def __init__(self, width: int, height: int, *, bit_depth: int = 8, block_size: int = 32,
                  lowpass_k: int = 0, device: int | None = None, keep_coeffs: bool = False,
                  validate: bool = False, timing: bool = False, max_batch: int = 0,
-                 feature_capacity: int = 0,
+                 feature_capacity: int = 0, downsample: bool = False,
                  stream: torch.cuda.Stream | None = None):
         if device is None:
             device = torch.cuda.current_device()
         flags = ((_lib.VCA_F_KEEP_COEFFS if keep_coeffs else 0) |
-                 (_lib.VCA_F_VALIDATE if validate else 0) | (_lib.VCA_F_TIMING if timing else 0))
+                 (_lib.VCA_F_VALIDATE if validate else 0) | (_lib.VCA_F_TIMING if timing else 0) |
+                 (_lib.VCA_F_DOWNSAMPLE if downsample else 0))
         self.cfg = _config(width, height, bit_depth, block_size, lowpass_k, device, flags,
                            max_batch, feature_capacity)
         self.width, self.height, self.bit_depth = width, height, bit_depth
@@ -70,7 +72,7 @@ class Analyzer:
         self._ctx = ctypes.c_void_p()
         check(_lib.lib().vca_open(ctypes.byref(self.cfg), ctypes.c_void_p(self.stream.cuda_stream),
                                   ctypes.byref(self._ctx)), "vca_open")
-        self.counts = block_counts(width, height, block_size, bit_depth, lowpass_k)
+        self.counts = block_counts(width, height, block_size, bit_depth, lowpass_k, downsample)
         self._keep = []   # frame tensors referenced until their work is known to be done
 
     # ------------------------------------------------------------------ calls

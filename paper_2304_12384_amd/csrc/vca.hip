@@ -125,15 +125,16 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
 
 // Persistent forward kernel over strips (vca_strip.h): wavefront i of S
 // takes strips i, i + S, ...
-template <int kBits, int kW, int kK, int kDepth>
+// kDs: the planes are downsampled by two on the fly (VCA_F_DOWNSAMPLE).
+template <int kBits, int kW, int kK, int kDepth, bool kDs>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   PackConsts<kW, kK> pc;
   pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
-  run_strips<kBits, kW, kK, kDepth>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
-                                    gridDim.x * kWavesPerGroup, p.n_frames * p.geom.strips_per_frame,
-                                    lane);
+  run_strips<kBits, kW, kK, kDepth, kDs>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
+                                         gridDim.x * kWavesPerGroup,
+                                         p.n_frames * p.geom.strips_per_frame, lane);
 }
 
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) {
@@ -144,33 +145,33 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) 
 // export (tests only) always uses depth 1.
 using FwdKernel = void (*)(FwdParams);
 
-template <int B, int W, int K>
-FwdKernel pick_depth(bool keep, int depth) {
-  if (keep) return fwd_kernel<B, W, K, true, 1>;
-  if (depth == 1) return strip_kernel<B, W, K, 1>;
-  if (depth >= 4) return strip_kernel<B, W, K, 4>;   // capped at the units per strip
-  return strip_kernel<B, W, K, 2>;
+template <int B, int W, int K, bool kDs>
+FwdKernel pick_depth(int depth) {
+  if (depth == 1) return strip_kernel<B, W, K, 1, kDs>;
+  if (depth >= 4) return strip_kernel<B, W, K, 4, kDs>;   // capped at the units per strip
+  return strip_kernel<B, W, K, 2, kDs>;
 }
 
 template <int B, int W>
-FwdKernel pick_k(int K, bool keep, int depth) {
-  if (K == W) return pick_depth<B, W, W>(keep, depth);
-  if (K == W / 2) return pick_depth<B, W, W / 2>(keep, depth);
-  if (K == W / 4) return pick_depth<B, W, W / 4>(keep, depth);
+FwdKernel pick_k(int K, bool keep, bool ds, int depth) {
+  if (ds) return K == W ? pick_depth<B, W, W, true>(depth) : nullptr;
+  if (K == W) return keep ? fwd_kernel<B, W, W, true, 1> : pick_depth<B, W, W, false>(depth);
+  if (K == W / 2) return keep ? fwd_kernel<B, W, W / 2, true, 1> : pick_depth<B, W, W / 2, false>(depth);
+  if (K == W / 4) return keep ? fwd_kernel<B, W, W / 4, true, 1> : pick_depth<B, W, W / 4, false>(depth);
   return nullptr;
 }
 
 template <int B>
-FwdKernel pick_w(int w, int K, bool keep, int depth) {
-  if (w == 32) return pick_k<B, 32>(K, keep, depth);
-  if (w == 16) return pick_k<B, 16>(K, keep, depth);
-  if (w == 8) return pick_k<B, 8>(K, keep, depth);
+FwdKernel pick_w(int w, int K, bool keep, bool ds, int depth) {
+  if (w == 32) return pick_k<B, 32>(K, keep, ds, depth);
+  if (w == 16) return pick_k<B, 16>(K, keep, ds, depth);
+  if (w == 8) return pick_k<B, 8>(K, keep, ds, depth);
   return nullptr;
 }
 
-FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, int depth) {
-  return bits == 8 ? pick_w<8>(w, K, keep, depth)
-                   : (bits == 10 ? pick_w<10>(w, K, keep, depth) : nullptr);
+FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, bool ds, int depth) {
+  return bits == 8 ? pick_w<8>(w, K, keep, ds, depth)
+                   : (bits == 10 ? pick_w<10>(w, K, keep, ds, depth) : nullptr);
 }
 
 }  // namespace
@@ -274,7 +275,8 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
 // Enqueues one forward launch with the given ring depth and workgroup cap.
 vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu) {
   const bool keep = ctx->coeffs != nullptr;
-  FwdKernel kern = select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, depth);
+  FwdKernel kern =
+      select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth);
   if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
   // Persistent grid: at most as many workgroups as can be resident at once,
   // so no workgroup waits for another to drain before it starts its loop.
@@ -293,9 +295,9 @@ vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_p
 
 std::string tune_key(const vca_ctx* ctx) {
   char key[160];
-  std::snprintf(key, sizeof(key), "gfx950/cu%d/plain/b%d/w%d/k%d/%dx%d", ctx->num_cus,
-                ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, ctx->cfg.width,
-                ctx->cfg.height);
+  std::snprintf(key, sizeof(key), "gfx950/cu%d/plain/b%d/w%d/k%d%s/%dx%d", ctx->num_cus,
+                ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, ctx->geo.ds ? "/ds" : "",
+                ctx->cfg.width, ctx->cfg.height);
   return key;
 }
 
@@ -506,7 +508,8 @@ vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_
   vca_status st = VCA_OK;
   for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
     int resident = 0;
-    FwdKernel kern = select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, depth);
+    FwdKernel kern =
+        select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, ctx->geo.ds, depth);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0) != hipSuccess)
       resident = 1;
     for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {

@@ -418,6 +418,7 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   if (!cfgs || n_streams <= 0) return VCA_ERR_INVALID_ARG;
   for (int s = 0; s < n_streams; s++) {
     vca_status st = check_config(&cfgs[s]);
+    if (st == VCA_OK && (cfgs[s].flags & VCA_F_DOWNSAMPLE)) st = VCA_ERR_UNSUPPORTED;
     if (st != VCA_OK) return st;
     if (cfgs[s].flags & VCA_F_KEEP_COEFFS) return VCA_ERR_UNSUPPORTED;
     if (cfgs[s].device != cfgs[0].device) return VCA_ERR_INVALID_ARG;

@@ -45,7 +45,14 @@ inline vca_status check_config(const vca_config* cfg) {
   if (k != 0 && k != w && k != w / 2 && k != w / 4) return VCA_ERR_INVALID_ARG;
   if (cfg->max_batch < 0 || cfg->feature_capacity < 0 || cfg->device < 0)
     return VCA_ERR_INVALID_ARG;
-  if (cfg->flags & ~(VCA_F_KEEP_COEFFS | VCA_F_VALIDATE | VCA_F_TIMING)) return VCA_ERR_INVALID_ARG;
+  if (cfg->flags & ~(VCA_F_KEEP_COEFFS | VCA_F_VALIDATE | VCA_F_TIMING | VCA_F_DOWNSAMPLE))
+    return VCA_ERR_INVALID_ARG;
+  if (cfg->flags & VCA_F_DOWNSAMPLE) {
+    if (cfg->width % 4 || cfg->height % 4 || cfg->width / 4 < w || cfg->height / 4 < w)
+      return VCA_ERR_INVALID_ARG;
+    if (k != 0 && k != w) return VCA_ERR_INVALID_ARG;
+    if (cfg->flags & VCA_F_KEEP_COEFFS) return VCA_ERR_UNSUPPORTED;
+  }
   return VCA_OK;
 }
 
@@ -57,15 +64,19 @@ struct Geometry {
   int32_t per_frame = 0;        // blocks per frame
   int32_t tiles_per_frame = 0;  // 32 x 32 tiles per frame
 
+  bool ds = false;               // planes downsampled by two before the analysis
+
   void init(const vca_config& cfg) {
     w = cfg.block_size;
     K = cfg.lowpass_k == 0 ? w : cfg.lowpass_k;
     bits = cfg.bit_depth;
+    ds = (cfg.flags & VCA_F_DOWNSAMPLE) != 0;
+    const int vw = ds ? cfg.width / 2 : cfg.width, vh = ds ? cfg.height / 2 : cfg.height;
     const int bpt = kTile / w;
     per_frame = tiles_per_frame = 0;
     for (int P = 0; P < 3; P++) {
-      const int pw = P == 0 ? cfg.width : cfg.width / 2;
-      const int ph = P == 0 ? cfg.height : cfg.height / 2;
+      const int pw = P == 0 ? vw : vw / 2;
+      const int ph = P == 0 ? vh : vh / 2;
       nbx[P] = pw / w;
       nby[P] = ph / w;
       cnt[P] = nbx[P] * nby[P];

@@ -76,10 +76,11 @@ struct StripWork {
 
 // Strip `id` (frame-major, then Y, U, V, then tile rows, then strips along a
 // row).
-template <int kBits, int kW>
+template <int kBits, int kW, bool kDs = false>
 __device__ inline StripWork decode_strip(const StripGeom& G, int id) {
   constexpr int kBps = kBits == 8 ? 1 : 2;
   constexpr int kBpt = kTile / kW;
+  constexpr int kScale = kDs ? 2 : 1;   // input samples per analysed sample, each way
   const int f = (int)fastdiv((uint32_t)id, G.div_spf);
   int r = id - f * G.strips_per_frame;
   int P = 0;
@@ -98,7 +99,7 @@ __device__ inline StripWork decode_strip(const StripGeom& G, int id) {
   w.pitch = pl.pitch;
   w.n = min(kStrip, pl.ntx - tx0);
   const int by0 = ty * kBpt, bx0 = tx0 * kBpt;
-  w.base = pl.plane + f * pl.fstride + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
+  w.base = pl.plane + f * pl.fstride + (int64_t)by0 * kW * kScale * w.pitch + bx0 * kW * kBps * kScale;
   w.vr = min(kBpt, pl.nby - by0);
   w.vc_last = min(kBpt, pl.nbx - (tx0 + w.n - 1) * kBpt);
   w.out0 = G.blk_base + f * G.per_frame + pl.boff + by0 * pl.nbx + bx0;
@@ -118,15 +119,22 @@ struct LaneOffsets {
   uint32_t a, b, last_a, last_b;
 };
 
-template <int kBits, int kW>
+// Downsampled (kDs): the analysed row r comes from input rows 2r and 2r + 1
+// (the second at + pitch), output columns c..c+7 from input columns 2c..2c+15;
+// `a` and `b` are the byte offsets of the pieces of output columns 16g..16g+7
+// and 16g+8..16g+15 (whole tiles), last_a / last_b the same for the strip's
+// last tile, redirected like the plain layout's pieces.
+template <int kBits, int kW, bool kDs = false>
 __device__ inline LaneOffsets lane_offsets(const StripWork& s, int lane) {
   constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kScale = kDs ? 2 : 1;
   const int r = lane & 31, g = lane >> 5;
   const int rows = s.vr * kW;
-  const uint32_t roff = __umul24((uint32_t)(kW == 32 || r < rows ? r : 0), (uint32_t)s.pitch);
+  const uint32_t roff =
+      __umul24((uint32_t)(kScale * (kW == 32 || r < rows ? r : 0)), (uint32_t)s.pitch);
   LaneOffsets o;
-  o.a = roff + 16 * g * kBps;
-  o.b = o.a + 16;
+  o.a = roff + 16 * g * kBps * kScale;
+  o.b = o.a + 8 * kBps * kScale;
   if (kW == 32) {            // a w = 32 tile is one complete block
     o.last_a = o.a;
     o.last_b = o.b;
@@ -134,17 +142,87 @@ __device__ inline LaneOffsets lane_offsets(const StripWork& s, int lane) {
     const int cols = s.vc_last * kW;
     const int c0 = 16 * g < cols ? 16 * g : 0;
     const int c1 = 16 * g + 8 < cols ? 16 * g + 8 : c0;
-    o.last_a = roff + c0 * kBps;
-    o.last_b = roff + c1 * kBps;
+    o.last_a = roff + c0 * kBps * kScale;
+    o.last_b = roff + c1 * kBps * kScale;
   }
   return o;
 }
 
-template <int kBits, int kW>
+// 2 x 2 means, rounded half up, of two input rows' dwords: 8-bit, four input
+// samples per dword -> output samples 2q, 2q + 1 of the piece in the 16-bit
+// halves, as (sum + 2) (shift still to come).
+__device__ inline uint32_t sum4_u8(uint32_t r0, uint32_t r1) {
+  const uint32_t e0 = __builtin_amdgcn_perm(r0, r0, 0x0C020C00u);   // bytes 0, 2 -> halves
+  const uint32_t o0 = __builtin_amdgcn_perm(r0, r0, 0x0C030C01u);   // bytes 1, 3
+  const uint32_t e1 = __builtin_amdgcn_perm(r1, r1, 0x0C020C00u);
+  const uint32_t o1 = __builtin_amdgcn_perm(r1, r1, 0x0C030C01u);
+  return e0 + e1 + o0 + o1 + 0x00020002u;   // each half <= 1022 + 2: no carry across
+}
+
+// Four output samples (bytes) from two dwords of 16-bit (sum + 2).
+__device__ inline uint32_t pack4_u8(uint32_t s01, uint32_t s23) {
+  const uint32_t a = (s01 >> 2) & 0x00FF00FFu, b = (s23 >> 2) & 0x00FF00FFu;
+  return __builtin_amdgcn_perm(b, a, 0x06040200u);
+}
+
+// 10-bit: one dword of each row (two input samples each) -> one output sample,
+// with any bit above 1023 of the inputs carried into bits 10..15 (so that a
+// validation of the output samples sees it).
+__device__ inline uint32_t mean4_u16(uint32_t r0, uint32_t r1) {
+  const uint32_t s = r0 + r1;                       // two 16-bit sums <= 2046 each
+  const uint32_t t = (s & 0xFFFFu) + (s >> 16) + 2u;
+  return ((t >> 2) & 0x3FFu) | (((r0 | r1) & 0xFC00FC00u) ? 0xFC00u : 0u);
+}
+
+template <int kBits>
+__device__ inline TileData downsample_tile(const uint8_t* row0, uint32_t oa, uint32_t ob,
+                                           int64_t pitch) {
+  const uint8_t* row1 = row0 + pitch;
+  TileData d;
+  if (kBits == 8) {
+    // pieces: 16 input bytes -> 8 output samples
+    const v4i a0 = *reinterpret_cast<const v4i*>(row0 + oa);
+    const v4i a1 = *reinterpret_cast<const v4i*>(row1 + oa);
+    const v4i b0 = *reinterpret_cast<const v4i*>(row0 + ob);
+    const v4i b1 = *reinterpret_cast<const v4i*>(row1 + ob);
+    d.a[0] = (int)pack4_u8(sum4_u8(a0[0], a1[0]), sum4_u8(a0[1], a1[1]));
+    d.a[1] = (int)pack4_u8(sum4_u8(a0[2], a1[2]), sum4_u8(a0[3], a1[3]));
+    d.a[2] = (int)pack4_u8(sum4_u8(b0[0], b1[0]), sum4_u8(b0[1], b1[1]));
+    d.a[3] = (int)pack4_u8(sum4_u8(b0[2], b1[2]), sum4_u8(b0[3], b1[3]));
+  } else {
+    // pieces: 32 input bytes (16 samples) -> 8 output samples
+    v4i in0[4], in1[4];
+    in0[0] = *reinterpret_cast<const v4i*>(row0 + oa);
+    in0[1] = *reinterpret_cast<const v4i*>(row0 + oa + 16);
+    in0[2] = *reinterpret_cast<const v4i*>(row0 + ob);
+    in0[3] = *reinterpret_cast<const v4i*>(row0 + ob + 16);
+    in1[0] = *reinterpret_cast<const v4i*>(row1 + oa);
+    in1[1] = *reinterpret_cast<const v4i*>(row1 + oa + 16);
+    in1[2] = *reinterpret_cast<const v4i*>(row1 + ob);
+    in1[3] = *reinterpret_cast<const v4i*>(row1 + ob + 16);
+    uint32_t out[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const int piece = k / 2, q = (k % 2) * 2;
+      const uint32_t lo = mean4_u16((uint32_t)in0[piece][q], (uint32_t)in1[piece][q]);
+      const uint32_t hi = mean4_u16((uint32_t)in0[piece][q + 1], (uint32_t)in1[piece][q + 1]);
+      out[k] = lo | (hi << 16);
+    }
+    d.a = v4i{(int)out[0], (int)out[1], (int)out[2], (int)out[3]};
+    d.b = v4i{(int)out[4], (int)out[5], (int)out[6], (int)out[7]};
+  }
+  return d;
+}
+
+template <int kBits, int kW, bool kDs = false>
 __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, int t) {
   constexpr int kBps = kBits == 8 ? 1 : 2;
-  const uint8_t* base = s.base + t * kTile * kBps;
   const bool last = kW != 32 && t == s.n - 1;
+  if constexpr (kDs) {
+    return downsample_tile<kBits>(s.base + t * kTile * kBps * 2, last ? o.last_a : o.a,
+                                  last ? o.last_b : o.b, s.pitch);
+  }
+  const uint8_t* base = s.base + t * kTile * kBps;
   TileData d;
   d.a = *reinterpret_cast<const v4i*>(base + (last ? o.last_a : o.a));
   if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(base + (last ? o.last_b : o.b));
@@ -160,7 +238,7 @@ __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, 
 // for exactly the oldest unit's loads; the missing tiles of a short strip are
 // transformed but never stored.  w = 32 stores H and DC once per strip; w =
 // 16 and 8 reduce each unit over the lanes of its blocks and store them.
-template <int kBits, int kW, int kK, int kDepthMax>
+template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false>
 __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
                                            const PackConsts<kW, kK>& pc, int id, int stride,
                                            int end, int lane) {
@@ -179,13 +257,13 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   auto load_unit = [&](const StripWork& S, const LaneOffsets& O, int u) {
     Unit d;
 #pragma unroll
-    for (int i = 0; i < kPack; i++) d.t[i] = strip_load<kBits, kW>(S, O, min(u * kPack + i, S.n - 1));
+    for (int i = 0; i < kPack; i++) d.t[i] = strip_load<kBits, kW, kDs>(S, O, min(u * kPack + i, S.n - 1));
     return d;
   };
 
   if (id >= end) return;
-  StripWork S = decode_strip<kBits, kW>(G, id);
-  LaneOffsets O = lane_offsets<kBits, kW>(S, lane);
+  StripWork S = decode_strip<kBits, kW, kDs>(G, id);
+  LaneOffsets O = lane_offsets<kBits, kW, kDs>(S, lane);
   Unit ring[kDepth];
 #pragma unroll
   for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
@@ -196,8 +274,8 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     StripWork S2 = S;
     LaneOffsets O2 = O;
     if (more) {
-      S2 = decode_strip<kBits, kW>(G, id2);
-      O2 = lane_offsets<kBits, kW>(S2, lane);
+      S2 = decode_strip<kBits, kW, kDs>(G, id2);
+      O2 = lane_offsets<kBits, kW, kDs>(S2, lane);
     }
     double hs[kUnits];
     int dcs[kUnits];

@@ -140,3 +140,20 @@ def test_grad_null_and_misaligned_arguments():
     assert L.vca_energy_backward(ctypes.byref(c), p, p, p, odd, None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_energy_backward(ctypes.byref(c), odd, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_energy_backward(ctypes.byref(c), None, p, p, p, None) == _lib.VCA_ERR_INVALID_ARG
+
+
+def test_downsample_flag_block_counts_and_rejections():
+    L = _lib.lib()
+    out = (ctypes.c_int32 * 3)()
+    c = cfg(flags=_lib.VCA_F_DOWNSAMPLE)
+    assert L.vca_block_counts(ctypes.byref(c), out) == 0
+    assert tuple(out) == (60 * 33, 30 * 16, 30 * 16)   # the 1920x1080 half-size video
+    for bad in (dict(width=3842), dict(height=2162), dict(lowpass_k=16),
+                dict(width=120, height=120)):             # width / 4 < w
+        c = cfg(flags=_lib.VCA_F_DOWNSAMPLE, **bad)
+        assert L.vca_block_counts(ctypes.byref(c), out) == _lib.VCA_ERR_INVALID_ARG, bad
+    c = cfg(flags=_lib.VCA_F_DOWNSAMPLE | _lib.VCA_F_KEEP_COEFFS)
+    assert L.vca_block_counts(ctypes.byref(c), out) == _lib.VCA_ERR_UNSUPPORTED
+    ctx = ctypes.c_void_p(1234)
+    assert L.vca_open(ctypes.byref(c), None, ctypes.byref(ctx)) == _lib.VCA_ERR_UNSUPPORTED
+    assert not ctx.value
