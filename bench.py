@@ -289,7 +289,7 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
     }
 
 
-KERNEL_SOURCES = ("vca.hip", "vca_tile.h", "vca_host.h", "vca_reduce.h")
+KERNEL_SOURCES = ("vca.hip", "vca_strip.h", "vca_tile.h", "vca_host.h", "vca_reduce.h")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fwd32_2160p.md")
 
 
