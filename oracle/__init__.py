@@ -16,7 +16,9 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvcaref.so")
+# VCAREF_LIB names another build of vcaref.c (the mutation tests plant a
+# mistake in a copy and check that the pins catch it).
+LIB_PATH = os.environ.get("VCAREF_LIB") or os.path.join(HERE, "libvcaref.so")
 
 FEATURE_NAMES = ("E_Y", "h", "L_Y", "E_U", "E_V", "L_U", "L_V")
 
