@@ -124,14 +124,14 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
 }
 
 // Persistent forward kernel over strips (vca_strip.h): wavefront i of S
-// takes strips i, i + S, ...
+// takes the runs of kRun strips i, i + S, ...
 // kDs: the planes are downsampled by two on the fly (VCA_F_DOWNSAMPLE).
 template <int kBits, int kW, int kK, int kDepth, bool kDs>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   PackConsts<kW, kK> pc;
-  pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
+  pc.template load<kBits>(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
   run_strips<kBits, kW, kK, kDepth, kDs>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
                                          gridDim.x * kWavesPerGroup,
                                          p.n_frames * p.geom.strips_per_frame, lane);
@@ -285,7 +285,7 @@ vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_p
   resident = std::max(1, resident);
   if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
   const int64_t waves = keep ? (int64_t)fp.n_frames * fp.tiles_per_frame
-                             : (int64_t)fp.n_frames * fp.geom.strips_per_frame;
+                             : ((int64_t)fp.n_frames * fp.geom.strips_per_frame + kRun - 1) / kRun;
   const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);

@@ -53,6 +53,7 @@ struct StreamDesc {
 
 // Consecutive strips of one stream handed to a wavefront at a time.
 constexpr int kChunkStrips = 32;
+static_assert(kChunkStrips % kRun == 0, "chunks start on a run boundary");
 constexpr int kMaxPack = 4;        // w / K at most
 
 // Descriptors and chunks of one class, ranges in the launch's flat lists
@@ -87,7 +88,7 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw,
                                          const TileOut& o0, int lane) {
   const KindRange kr = p.kinds[kind];
   PackConsts<kW, kK> pc;
-  pc.load(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
+  pc.template load<kBits>(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
   TileOut o = o0;
   int d = kr.desc_begin;
   for (int c = kr.chunk_begin + gw; c < kr.chunk_end; c += W) {
@@ -96,7 +97,7 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw,
     o.validate = sd.validate;
     const int s0 = (c - sd.chunk_begin) * kChunkStrips;
     const int s1 = min(s0 + kChunkStrips, sd.strips);
-    run_strips<kBits, kW, kK, kDepth>(sd.geom, o, pc, s0, 1, s1, lane);
+    run_strips<kBits, kW, kK, kDepth>(sd.geom, o, pc, s0 / kRun, 1, s1, lane);
   }
 }
 

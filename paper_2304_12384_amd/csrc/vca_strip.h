@@ -229,22 +229,39 @@ __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, 
   return d;
 }
 
-// Strips id, id + stride, ... (< end) of G.  Each wavefront keeps kDepth
-// units in flight: while it transforms unit u it has issued the loads of
-// unit u + kDepth, which may belong to its next strip (units per strip %
-// kDepth == 0, so ring slots line up across strips).  Every unit issues the
-// same loads whatever the strip length (tile indices are clamped into the
-// strip, and the last strip prefetches itself again), so the compiler waits
-// for exactly the oldest unit's loads; the missing tiles of a short strip are
-// transformed but never stored.  w = 32 stores H and DC once per strip; w =
-// 16 and 8 reduce each unit over the lanes of its blocks and store them.
+// Strips are taken in runs of kRun consecutive strip ids: this wavefront
+// runs run0, run0 + run_stride, ... (strips below `end`).  Consecutive strips
+// own consecutive output ranges when w = 32 (a tile is a block and the tile
+// grid is the block grid), so a run's H and DC are gathered into the lanes
+// (lane i = block i of the run) and stored with one store each at the run's
+// end: a store's completion counts in vmcnt like a load's, and one per strip
+// stalled the loads queued behind it.
+//
+// Within a run the strips are software-pipelined over their units: while the
+// vertical pass of unit n and the horizontal pass of unit n + 1 run on the
+// matrix cores, the wavefront sums the energies of unit n - 1 and then splits
+// unit n + 1's horizontal result, so no VALU work waits on an MFMA it has
+// just issued.  The unit after the last of a strip is the next strip's first
+// (the last strip's is a repeat of its own, computed and dropped).
+//
+// Loads: ring slot n % kDepth holds unit n until its horizontal pass, and is
+// then refilled with unit n + kDepth, which may lie in the next strip (units
+// per strip % kDepth == 0, and kDepth <= units per strip / 2 keeps it there).
+// Every unit issues the same loads whatever the strip length (tile indices
+// are clamped into the strip, and the last strip prefetches itself again),
+// so the compiler waits for exactly the oldest unit's loads; the missing
+// tiles of a short strip are transformed but never stored.  w = 16 and 8
+// reduce each unit over the lanes of its blocks and store them.
+constexpr int kRun = 8;   // strips per run (w = 32: at most 64 blocks, one per lane)
+
 template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false>
 __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
-                                           const PackConsts<kW, kK>& pc, int id, int stride,
+                                           const PackConsts<kW, kK>& pc, int run0, int run_stride,
                                            int end, int lane) {
   constexpr int kPack = kW / kK;
   constexpr int kUnits = kStrip / kPack;
-  constexpr int kDepth = kDepthMax < kUnits ? kDepthMax : kUnits;
+  constexpr int kDepthCap = kUnits / 2;
+  constexpr int kDepth = kDepthMax < kDepthCap ? kDepthMax : kDepthCap;
   constexpr int kBpt = kTile / kW;
   static_assert(kUnits % kDepth == 0, "ring slots must line up across strips");
   constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
@@ -260,16 +277,32 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     for (int i = 0; i < kPack; i++) d.t[i] = strip_load<kBits, kW, kDs>(S, O, min(u * kPack + i, S.n - 1));
     return d;
   };
+  // the strip after `id` in this wavefront's sequence
+  auto next_id = [&](int id) {
+    return (id + 1) % kRun != 0 ? id + 1 : id + 1 + (run_stride - 1) * kRun;
+  };
 
+  int id = run0 * kRun;
   if (id >= end) return;
   StripWork S = decode_strip<kBits, kW, kDs>(G, id);
   LaneOffsets O = lane_offsets<kBits, kW, kDs>(S, lane);
   Unit ring[kDepth];
 #pragma unroll
   for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
+  // unit 0: horizontal pass and split
+  Split sp;
+  {
+    const Unit d = ring[0];
+    ring[0] = load_unit(S, O, kDepth);
+    sp = split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, pc.c1)));
+  }
+  // w = 32: the current run's blocks, lane i holding block run_out0 + i
+  double hrun = 0.0;
+  int dcrun = 0;
+  int run_out0 = S.out0;
 
   while (true) {
-    const int id2 = id + stride;
+    const int id2 = next_id(id);
     const bool more = id2 < end;
     StripWork S2 = S;
     LaneOffsets O2 = O;
@@ -279,14 +312,11 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     }
     double hs[kUnits];
     int dcs[kUnits];
-#pragma unroll
-    for (int u = 0; u < kUnits; u++) {
-      const Unit d = ring[u % kDepth];
-      const int v = u + kDepth;   // the unit whose loads go out now
-      ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
+    // energies of unit u of this strip from its vertical-pass accumulators
+    auto finish = [&](int u, const v16i& dh, const v16i& dl) {
       double h[kBpt];
       int dc[kBpt];
-      unit_energy<kBits, kW, kK>(out, pc, d.t, h, dc);
+      coeff_energy<kBits, kW, kK>(pc, dh, dl, h, dc);
       if constexpr (kW == 32) {
         hs[u] = h[0];
         dcs[u] = dc[0];
@@ -306,26 +336,58 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
             if (b < S.vr) out.blk_dc[S.out0 + t * kBpt + b * S.out_row + bc] = dc[b] + kDcAdd;
         }
       }
-    }
-    if (kW == 32) {
-      double h;
-      int t;
-      if constexpr (kPack == 1) {
-        h = reduce_scatter8(hs, lane);
-        t = lane >> 3;
-      } else if constexpr (kPack == 2) {
-        h = reduce_scatter4x2(hs, lane);
-        t = 4 * (lane >> 5) + 2 * ((lane >> 3) & 1) + ((lane >> 4) & 1);
-      } else {
-        h = reduce_scatter2x4(hs);
-        t = lane >> 3;
-      }
-      if ((lane & 7) == 0 && t < S.n) out.blk_h[S.out0 + t] = h;
-      // DC of tile u * kPack + q sits in lane q * K (g = 0), register dcs[u]
-      if (g == 0 && cc % kK == 0) {
+    };
+    v16i ph, pl;   // vertical-pass accumulators of the previous unit
 #pragma unroll
-        for (int u = 0; u < kUnits; u++)
-          if (u * kPack + q < S.n) out.blk_dc[S.out0 + u * kPack + q] = dcs[u] + kDcAdd;
+    for (int u = 0; u < kUnits; u++) {
+      v16i dh, dl;
+      mfma2(pc.a2, sp, pc.c2, dh, dl);   // unit u
+      const int n = u + 1;               // the unit whose horizontal pass goes out now
+      const Unit d = ring[n % kDepth];
+      const int v = n + kDepth;          // the unit whose loads go out now
+      ring[n % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
+      const Acc1 a1 = stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, pc.c1);
+      // The scheduler would otherwise pull the split up against its MFMA
+      // and sink every energy to the end of the strip.
+      __builtin_amdgcn_sched_barrier(0);
+      if (u > 0) finish(u - 1, ph, pl);
+      __builtin_amdgcn_sched_barrier(0);
+      sp = split2<kBits, kW>(stage1_sum<kBits>(a1));
+      __builtin_amdgcn_sched_barrier(0);
+      ph = dh;
+      pl = dl;
+    }
+    finish(kUnits - 1, ph, pl);
+    if constexpr (kW == 32) {
+      // Sum each tile's shares; tile_lane(t) is a lane holding tile t's total.
+      double h;
+      auto tile_lane = [](int t) {
+        if constexpr (kPack == 2) return 32 * (t >> 2) + 8 * ((t >> 1) & 1) + 16 * (t & 1);
+        else return 8 * t;
+      };
+      if constexpr (kPack == 1) h = reduce_scatter8(hs, lane);
+      else if constexpr (kPack == 2) h = reduce_scatter4x2(hs, lane);
+      else h = reduce_scatter2x4(hs);
+      // gather into the run's lanes: lane run position + t <- tile t
+      const int t = lane - (S.out0 - run_out0);
+      const bool in_strip = t >= 0 && t < S.n;
+      const double ht = __shfl(h, in_strip ? tile_lane(t) : lane);
+      if (in_strip) hrun = ht;
+      // DC of tile u * kPack + q': register dcs[u] of lane q' * K (g = 0)
+#pragma unroll
+      for (int u = 0; u < kUnits; u++) {
+#pragma unroll
+        for (int qq = 0; qq < kPack; qq++) {
+          const int dcv = __builtin_amdgcn_readlane(dcs[u], qq * kK);
+          if (t == u * kPack + qq) dcrun = dcv;
+        }
+      }
+      if (!more || id2 % kRun == 0) {   // the run ends with this strip
+        if (lane < S.out0 - run_out0 + S.n) {
+          out.blk_h[run_out0 + lane] = hrun;
+          out.blk_dc[run_out0 + lane] = dcrun + kDcAdd;
+        }
+        run_out0 = S2.out0;
       }
     }
     if (!more) break;

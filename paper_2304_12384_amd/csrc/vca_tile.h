@@ -258,31 +258,53 @@ __device__ __forceinline__ void operands10(const TileOut& o, const TileData& d, 
   }
 }
 
+// Horizontal-pass accumulators of one unit: 8-bit needs lo only; 10-bit
+// keeps the products of the high (t) and low bytes apart until the split,
+// T_raw = 256 hi + lo.
+struct Acc1 {
+  v16i lo;
+  v16i hi;
+};
+
 // Horizontal pass of kPack sample tiles into one accumulator: tile p's
 // B operand b1[p] puts its coefficients in its own lanes (kPack = 1: the
-// plain tile).
+// plain tile).  c1 holds the rounding 2^(s1-1) in every element.
 template <int kBits, int kW, int kPack>
-__device__ __forceinline__ v16i stage1(const TileOut& o, const v4i (&b1)[kPack],
-                                       const TileData (&d)[kPack]) {
-  constexpr int kS1 = ilog2c(kW) + kBits - 9;
-  v16i d1 = stage1_bias<kS1>();
+__device__ __forceinline__ Acc1 stage1_acc(const TileOut& o, const v4i (&b1)[kPack],
+                                           const TileData (&d)[kPack], const v16i& c1) {
+  Acc1 r;
+  r.lo = c1;
   if (kBits == 8) {
 #pragma unroll
     for (int p = 0; p < kPack; p++)
-      d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(d[p].a ^ (int)0x80808080, b1[p], d1, 0, 0, 0);   // x - 128
+      r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(d[p].a ^ (int)0x80808080, b1[p], r.lo, 0, 0, 0);   // x - 128
   } else {
-    v16i dh1 = {};
+    r.hi = v16i{};
 #pragma unroll
     for (int p = 0; p < kPack; p++) {
       v4i hi, lo;
       operands10(o, d[p], hi, lo);
-      dh1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], dh1, 0, 0, 0);
-      d1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], d1, 0, 0, 0);
+      r.hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], r.hi, 0, 0, 0);
+      r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], r.lo, 0, 0, 0);
     }
-#pragma unroll
-    for (int j = 0; j < 16; j++) d1[j] = (int)((uint32_t)dh1[j] * 256u + (uint32_t)d1[j]);
   }
+  return r;
+}
+
+// The rounded-up horizontal-pass accumulator X' Cd^T + 2^(s1-1).
+template <int kBits>
+__device__ __forceinline__ v16i stage1_sum(const Acc1& a) {
+  if (kBits == 8) return a.lo;
+  v16i d1;
+#pragma unroll
+  for (int j = 0; j < 16; j++) d1[j] = (int)((uint32_t)a.hi[j] * 256u + (uint32_t)a.lo[j]);
   return d1;
+}
+
+template <int kBits, int kW, int kPack>
+__device__ __forceinline__ v16i stage1(const TileOut& o, const v4i (&b1)[kPack],
+                                       const TileData (&d)[kPack]) {
+  return stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(o, b1, d, stage1_bias<ilog2c(kW) + kBits - 9>()));
 }
 
 // Split of the horizontal-pass result and the vertical pass.  Exact split of
@@ -291,18 +313,17 @@ __device__ __forceinline__ v16i stage1(const TileOut& o, const v4i (&b1)[kPack],
 // C T = 256 C T_hi + C (u - 128) + 128 C 1, the last term being 128 * 64 w
 // on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
 // scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
-// accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
-// Returns the hi and lo accumulators: Y = (256 dh + dl) >> s2 (+128 on each
-// block's row 0).
+// accumulator as 2^(s2-9).  Y = (256 dh + dl) >> s2 (+128 on each block's
+// row 0).
+struct Split {
+  v4i hi;   // T >> 8 bytes
+  v4i lo;   // (T & 255) - 128 bytes
+};
+
 template <int kBits, int kW>
-__device__ __forceinline__ void stage2(const v4i& a2, const v16i& d1, v16i& dh, v16i& dl) {
+__device__ __forceinline__ Split split2(const v16i& d1) {
   constexpr int kS1 = ilog2c(kW) + kBits - 9;
-  constexpr int kS2 = ilog2c(kW) + 6;
-  v16i c2;
-#pragma unroll
-  for (int j = 0; j < 16; j++) c2[j] = 1 << (kS2 - 9);   // 256 * 2^(s2-9) = 2^(s2-1)
-  const v16i zero = {};
-  v4i tlo, thi;
+  Split sp;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const uint32_t s0 = (uint32_t)(d1[4 * q + 0] >> kS1);
@@ -311,11 +332,31 @@ __device__ __forceinline__ void stage2(const v4i& a2, const v16i& d1, v16i& dh, 
     const uint32_t s3 = (uint32_t)(d1[4 * q + 3] >> kS1);
     const uint32_t p01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
     const uint32_t p23 = perm_b32(s3, s2, 0x05010400u);
-    tlo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
-    thi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
+    sp.lo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
+    sp.hi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
   }
-  dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, thi, c2, 0, 0, 0);
-  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, tlo, zero, 0, 0, 0);
+  return sp;
+}
+
+template <int kW>
+__device__ __forceinline__ v16i stage2_bias() {
+  constexpr int kS2 = ilog2c(kW) + 6;
+  v16i c2;
+#pragma unroll
+  for (int j = 0; j < 16; j++) c2[j] = 1 << (kS2 - 9);   // 256 * 2^(s2-9) = 2^(s2-1)
+  return c2;
+}
+
+__device__ __forceinline__ void mfma2(const v4i& a2, const Split& sp, const v16i& c2, v16i& dh,
+                                      v16i& dl) {
+  const v16i zero = {};
+  dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.hi, c2, 0, 0, 0);
+  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.lo, zero, 0, 0, 0);
+}
+
+template <int kBits, int kW>
+__device__ __forceinline__ void stage2(const v4i& a2, const v16i& d1, v16i& dh, v16i& dl) {
+  mfma2(a2, split2<kBits, kW>(d1), stage2_bias<kW>(), dh, dl);
 }
 
 // Both passes of one tile.
@@ -508,6 +549,14 @@ __device__ inline double reduce_scatter2x4(const double (&v)[2]) {
   return c;
 }
 
+// Keeps v in registers as an opaque value: the compiler can neither fold it
+// nor rebuild it from constants at every use (it would otherwise copy the
+// MFMA rounding splats into fresh registers for each tile).
+__device__ inline void pin_value(v16i& v) {
+#pragma unroll
+  for (int j = 0; j < 16; j++) asm volatile("" : "+v"(v[j]));
+}
+
 // Per-wavefront constants of the packed layout (kPack = w / K sample tiles
 // per MFMA tile; kPack = 1 is the plain tile).
 template <int kW, int kK>
@@ -517,7 +566,10 @@ struct PackConsts {
   v4i a2;             // stage-2 A operand
   double wt[16];      // weights (only registers in use are loaded)
   int row0_fix;       // +128 on each block's first coefficient row (lanes g = 0)
+  v16i c1;            // horizontal-pass rounding 2^(s1-1)
+  v16i c2;            // vertical-pass rounding in the hi accumulator
 
+  template <int kBits>
   __device__ void load(const v4i* tab_b1p, const v4i* tab_a2, const double* tab_w, int lane) {
 #pragma unroll
     for (int p = 0; p < kPack; p++) b1[p] = tab_b1p[p * 64 + lane];
@@ -526,21 +578,23 @@ struct PackConsts {
     for (int j = 0; j < 16; j++)
       if (reg_used(j, kW, kK)) wt[j] = tab_w[j * 64 + lane];
     row0_fix = lane < 32 ? 128 : 0;
+    c1 = stage1_bias<ilog2c(kW) + kBits - 9>();
+    c2 = stage2_bias<kW>();
+    pin_value(c1);
+    pin_value(c2);
   }
 };
 
-// Energies of one packed unit: h[b] = this lane's FP64 share of the energy of
-// block row b of its sample tile, dc[b] = the coefficient in register row
-// (b, 0) (the block's DC where the lane is a DC lane: c % K == 0, g = 0).
+// Energies of one packed unit from its vertical-pass accumulators: h[b] =
+// this lane's FP64 share of the energy of block row b of its sample tile,
+// dc[b] = the coefficient in register row (b, 0) (the block's DC where the
+// lane is a DC lane: c % K == 0, g = 0).
 template <int kBits, int kW, int kK, class PC>
-__device__ __forceinline__ void unit_energy(const TileOut& o, const PC& pc,
-                                            const TileData (&d)[kW / kK],
-                                            double (&h)[kTile / kW], int (&dc)[kTile / kW]) {
+__device__ __forceinline__ void coeff_energy(const PC& pc, const v16i& dh, const v16i& dl,
+                                             double (&h)[kTile / kW], int (&dc)[kTile / kW]) {
   constexpr int kS2 = ilog2c(kW) + 6;
   constexpr int kBpt = kTile / kW;
   constexpr int kAcc = kBpt == 1 ? 2 : kBpt;   // two chains when one block row
-  v16i dh, dl;
-  stage2<kBits, kW>(pc.a2, stage1<kBits, kW, kW / kK>(o, pc.b1, d), dh, dl);
   double acc[kAcc];
 #pragma unroll
   for (int a = 0; a < kAcc; a++) acc[a] = 0.0;
