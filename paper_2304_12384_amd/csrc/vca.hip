@@ -130,11 +130,13 @@ template <int kBits, int kW, int kK, int kDepth, bool kDs>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int kStage = stage_bytes(kW) > 0 ? stage_bytes(kW) : 16;
+  __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerGroup][kStage];
   PackConsts<kW, kK> pc;
-  pc.template load<kBits>(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
+  pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
   run_strips<kBits, kW, kK, kDepth, kDs>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
                                          gridDim.x * kWavesPerGroup,
-                                         p.n_frames * p.geom.strips_per_frame, lane);
+                                         p.n_frames * p.geom.strips_per_frame, lane, stage[wave]);
 }
 
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) {

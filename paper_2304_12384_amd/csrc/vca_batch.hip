@@ -85,10 +85,10 @@ struct BatchReduceParams {
 // only moves forward), with the class's operand tables loaded once.
 template <int kBits, int kW, int kK, int kDepth>
 __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw, int W,
-                                         const TileOut& o0, int lane) {
+                                         const TileOut& o0, int lane, uint8_t* stage) {
   const KindRange kr = p.kinds[kind];
   PackConsts<kW, kK> pc;
-  pc.template load<kBits>(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
+  pc.load(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
   TileOut o = o0;
   int d = kr.desc_begin;
   for (int c = kr.chunk_begin + gw; c < kr.chunk_end; c += W) {
@@ -97,7 +97,7 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw,
     o.validate = sd.validate;
     const int s0 = (c - sd.chunk_begin) * kChunkStrips;
     const int s1 = min(s0 + kChunkStrips, sd.strips);
-    run_strips<kBits, kW, kK, kDepth>(sd.geom, o, pc, s0 / kRun, 1, s1, lane);
+    run_strips<kBits, kW, kK, kDepth>(sd.geom, o, pc, s0 / kRun, 1, s1, lane, stage);
   }
 }
 
@@ -105,9 +105,9 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw,
 // loop made the compiler allocate registers for several classes at once).
 template <int kDepth, int kBits, int kW, int kK>
 __device__ __forceinline__ void run_kind_if(const BatchParams& p, int kind, int gw, int W,
-                                            const TileOut& o, int lane) {
+                                            const TileOut& o, int lane, uint8_t* stage) {
   if (p.kinds[kind].chunk_begin < p.kinds[kind].chunk_end)
-    run_kind<kBits, kW, kK, kDepth>(p, kind, gw, W, o, lane);
+    run_kind<kBits, kW, kK, kDepth>(p, kind, gw, W, o, lane, stage);
 }
 
 // Persistent batched kernel: every wavefront walks the classes present in
@@ -125,25 +125,28 @@ __global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
   o.coeffs = nullptr;
   o.err_flag = p.err_flag;
   o.validate = 0;
-  run_kind_if<kDepth, 8, 32, 32>(p, 0, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 32, 16>(p, 1, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 32, 8>(p, 2, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 16, 16>(p, 3, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 16, 8>(p, 4, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 16, 4>(p, 5, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 8, 8>(p, 6, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 8, 4>(p, 7, gw, W, o, lane);
-  run_kind_if<kDepth, 8, 8, 2>(p, 8, gw, W, o, lane);
+  // output staging of the w = 16 and 8 classes (the largest is w = 8's)
+  __shared__ __attribute__((aligned(16))) uint8_t stage_mem[kWaves][stage_bytes(8)];
+  uint8_t* stage = stage_mem[wave];
+  run_kind_if<kDepth, 8, 32, 32>(p, 0, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 32, 16>(p, 1, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 32, 8>(p, 2, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 16, 16>(p, 3, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 16, 8>(p, 4, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 16, 4>(p, 5, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 8, 8>(p, 6, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 8, 4>(p, 7, gw, W, o, lane, stage);
+  run_kind_if<kDepth, 8, 8, 2>(p, 8, gw, W, o, lane, stage);
   if constexpr (!kOnly8) {
-    run_kind_if<kDepth, 10, 32, 32>(p, 9, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 32, 16>(p, 10, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 32, 8>(p, 11, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 16, 16>(p, 12, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 16, 8>(p, 13, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 16, 4>(p, 14, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 8, 8>(p, 15, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 8, 4>(p, 16, gw, W, o, lane);
-    run_kind_if<kDepth, 10, 8, 2>(p, 17, gw, W, o, lane);
+    run_kind_if<kDepth, 10, 32, 32>(p, 9, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 32, 16>(p, 10, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 32, 8>(p, 11, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 16, 16>(p, 12, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 16, 8>(p, 13, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 16, 4>(p, 14, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 8, 8>(p, 15, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 8, 4>(p, 16, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 8, 2>(p, 17, gw, W, o, lane, stage);
   }
 }
 

@@ -72,6 +72,7 @@ struct StripWork {
   int32_t out_row;      // output index step between block rows
   int32_t vr;           // block rows of the strip inside the grid
   int32_t vc_last;      // block columns of the last tile inside the grid
+  int32_t row0;         // output index of block (0, 0) of the strip's tile row
 };
 
 // Strip `id` (frame-major, then Y, U, V, then tile rows, then strips along a
@@ -103,6 +104,7 @@ __device__ inline StripWork decode_strip(const StripGeom& G, int id) {
   w.vr = min(kBpt, pl.nby - by0);
   w.vc_last = min(kBpt, pl.nbx - (tx0 + w.n - 1) * kBpt);
   w.out0 = G.blk_base + f * G.per_frame + pl.boff + by0 * pl.nbx + bx0;
+  w.row0 = w.out0 - bx0;
   w.out_row = pl.nbx;
   return w;
 }
@@ -237,31 +239,31 @@ __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, 
 // end: a store's completion counts in vmcnt like a load's, and one per strip
 // stalled the loads queued behind it.
 //
-// Within a run the strips are software-pipelined over their units: while the
-// vertical pass of unit n and the horizontal pass of unit n + 1 run on the
-// matrix cores, the wavefront sums the energies of unit n - 1 and then splits
-// unit n + 1's horizontal result, so no VALU work waits on an MFMA it has
-// just issued.  The unit after the last of a strip is the next strip's first
-// (the last strip's is a repeat of its own, computed and dropped).
-//
-// Loads: ring slot n % kDepth holds unit n until its horizontal pass, and is
-// then refilled with unit n + kDepth, which may lie in the next strip (units
-// per strip % kDepth == 0, and kDepth <= units per strip / 2 keeps it there).
-// Every unit issues the same loads whatever the strip length (tile indices
-// are clamped into the strip, and the last strip prefetches itself again),
-// so the compiler waits for exactly the oldest unit's loads; the missing
-// tiles of a short strip are transformed but never stored.  w = 16 and 8
-// reduce each unit over the lanes of its blocks and store them.
+// Loads: ring slot u % kDepth holds unit u of the strip until its horizontal
+// pass, and is then refilled with unit u + kDepth, which may lie in the next
+// strip (units per strip % kDepth == 0, so ring slots line up across
+// strips).  Every unit issues the same loads whatever the strip length (tile
+// indices are clamped into the strip, and the last strip prefetches itself
+// again), so the compiler waits for exactly the oldest unit's loads; the
+// missing tiles of a short strip are transformed but never stored.  w = 16
+// and 8 reduce each unit over the lanes of its blocks and write them to a
+// per-wavefront LDS staging area laid out as the segment of the tile row
+// being walked (block row x block column, up to kSegCols columns); the
+// segment is copied out with row-contiguous stores when the next strip
+// leaves the tile row, would overflow it, or the run ends.
 constexpr int kRun = 8;   // strips per run (w = 32: at most 64 blocks, one per lane)
+constexpr int kSegCols = 128;   // block columns of a staged segment (w = 16, 8)
+
+// LDS bytes of one wavefront's staging area (FP64 H, then int32 DC).
+constexpr int stage_bytes(int w) { return w == 32 ? 0 : (kTile / w) * kSegCols * 12; }
 
 template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false>
 __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
                                            const PackConsts<kW, kK>& pc, int run0, int run_stride,
-                                           int end, int lane) {
+                                           int end, int lane, uint8_t* stage) {
   constexpr int kPack = kW / kK;
   constexpr int kUnits = kStrip / kPack;
-  constexpr int kDepthCap = kUnits / 2;
-  constexpr int kDepth = kDepthMax < kDepthCap ? kDepthMax : kDepthCap;
+  constexpr int kDepth = kDepthMax < kUnits ? kDepthMax : kUnits;
   constexpr int kBpt = kTile / kW;
   static_assert(kUnits % kDepth == 0, "ring slots must line up across strips");
   constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
@@ -289,17 +291,15 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   Unit ring[kDepth];
 #pragma unroll
   for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
-  // unit 0: horizontal pass and split
-  Split sp;
-  {
-    const Unit d = ring[0];
-    ring[0] = load_unit(S, O, kDepth);
-    sp = split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, pc.c1)));
-  }
-  // w = 32: the current run's blocks, lane i holding block run_out0 + i
+  const v16i c1 = stage1_bias<ilog2c(kW) + kBits - 9>();
+  const v16i c2 = stage2_bias<kW>();
+  // w = 32: the current run's blocks, lane i holding block run_out0 + i;
+  // w < 32: the staged segment starts at block run_out0 (row 0 of its tile row)
   double hrun = 0.0;
   int dcrun = 0;
   int run_out0 = S.out0;
+  double* st_h = reinterpret_cast<double*>(stage);            // [kBpt][kSegCols]
+  int* st_dc = reinterpret_cast<int*>(st_h + kBpt * kSegCols);  // [kBpt][kSegCols]
 
   while (true) {
     const int id2 = next_id(id);
@@ -329,35 +329,24 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
         const bool mine = t < S.n && bc < vc;
         // one writer per (block, tile): the group's lanes holding a row
         constexpr int kFree = kBpt == 2 ? kK - 1 : kK / 2 - 1;   // in-group bits summed over
-        if ((cc & kFree) == 0 && mine && r < S.vr) out.blk_h[S.out0 + t * kBpt + r * S.out_row + bc] = hr;
+        const int col = S.out0 - run_out0 + t * kBpt + bc;        // column in the segment
+        if ((cc & kFree) == 0 && mine) st_h[r * kSegCols + col] = hr;
         if (g == 0 && cc % kK == 0 && mine) {
 #pragma unroll
-          for (int b = 0; b < kBpt; b++)
-            if (b < S.vr) out.blk_dc[S.out0 + t * kBpt + b * S.out_row + bc] = dc[b] + kDcAdd;
+          for (int b = 0; b < kBpt; b++) st_dc[b * kSegCols + col] = dc[b] + kDcAdd;
         }
       }
     };
-    v16i ph, pl;   // vertical-pass accumulators of the previous unit
 #pragma unroll
     for (int u = 0; u < kUnits; u++) {
+      const Unit d = ring[u % kDepth];
+      const int v = u + kDepth;   // the unit whose loads go out now
+      ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
       v16i dh, dl;
-      mfma2(pc.a2, sp, pc.c2, dh, dl);   // unit u
-      const int n = u + 1;               // the unit whose horizontal pass goes out now
-      const Unit d = ring[n % kDepth];
-      const int v = n + kDepth;          // the unit whose loads go out now
-      ring[n % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
-      const Acc1 a1 = stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, pc.c1);
-      // The scheduler would otherwise pull the split up against its MFMA
-      // and sink every energy to the end of the strip.
-      __builtin_amdgcn_sched_barrier(0);
-      if (u > 0) finish(u - 1, ph, pl);
-      __builtin_amdgcn_sched_barrier(0);
-      sp = split2<kBits, kW>(stage1_sum<kBits>(a1));
-      __builtin_amdgcn_sched_barrier(0);
-      ph = dh;
-      pl = dl;
+      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, c1))),
+            c2, dh, dl);
+      finish(u, dh, dl);
     }
-    finish(kUnits - 1, ph, pl);
     if constexpr (kW == 32) {
       // Sum each tile's shares; tile_lane(t) is a lane holding tile t's total.
       double h;
@@ -386,6 +375,24 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
         if (lane < S.out0 - run_out0 + S.n) {
           out.blk_h[run_out0 + lane] = hrun;
           out.blk_dc[run_out0 + lane] = dcrun + kDcAdd;
+        }
+        run_out0 = S2.out0;
+      }
+    }
+    if constexpr (kW != 32) {
+      // copy the segment out when the next strip leaves it
+      const bool leave = !more || id2 % kRun == 0 || S2.row0 != S.row0 ||
+                         S2.out0 - run_out0 + kStrip * kBpt > kSegCols;
+      if (leave) {
+        const int cols = S.out0 - run_out0 + (S.n - 1) * kBpt + S.vc_last;
+        for (int b = 0; b < S.vr; b++) {
+          for (int cb = 0; cb < cols; cb += 64) {
+            const int col = cb + lane;
+            if (col < cols) {
+              out.blk_h[run_out0 + b * S.out_row + col] = st_h[b * kSegCols + col];
+              out.blk_dc[run_out0 + b * S.out_row + col] = st_dc[b * kSegCols + col];
+            }
+          }
         }
         run_out0 = S2.out0;
       }

@@ -549,14 +549,6 @@ __device__ inline double reduce_scatter2x4(const double (&v)[2]) {
   return c;
 }
 
-// Keeps v in registers as an opaque value: the compiler can neither fold it
-// nor rebuild it from constants at every use (it would otherwise copy the
-// MFMA rounding splats into fresh registers for each tile).
-__device__ inline void pin_value(v16i& v) {
-#pragma unroll
-  for (int j = 0; j < 16; j++) asm volatile("" : "+v"(v[j]));
-}
-
 // Per-wavefront constants of the packed layout (kPack = w / K sample tiles
 // per MFMA tile; kPack = 1 is the plain tile).
 template <int kW, int kK>
@@ -566,10 +558,7 @@ struct PackConsts {
   v4i a2;             // stage-2 A operand
   double wt[16];      // weights (only registers in use are loaded)
   int row0_fix;       // +128 on each block's first coefficient row (lanes g = 0)
-  v16i c1;            // horizontal-pass rounding 2^(s1-1)
-  v16i c2;            // vertical-pass rounding in the hi accumulator
 
-  template <int kBits>
   __device__ void load(const v4i* tab_b1p, const v4i* tab_a2, const double* tab_w, int lane) {
 #pragma unroll
     for (int p = 0; p < kPack; p++) b1[p] = tab_b1p[p * 64 + lane];
@@ -578,10 +567,6 @@ struct PackConsts {
     for (int j = 0; j < 16; j++)
       if (reg_used(j, kW, kK)) wt[j] = tab_w[j * 64 + lane];
     row0_fix = lane < 32 ? 128 : 0;
-    c1 = stage1_bias<ilog2c(kW) + kBits - 9>();
-    c2 = stage2_bias<kW>();
-    pin_value(c1);
-    pin_value(c2);
   }
 };
 
