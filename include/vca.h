@@ -147,6 +147,26 @@ vca_status vca_block_coeffs(vca_ctx* ctx, int64_t frame, int16_t* out_host, size
 vca_status vca_block_stats(vca_ctx* ctx, int64_t frame, double* h_host, int32_t* dc_host,
                            size_t capacity);
 
+/* Per-block feature maps (the summands of the features of Section 2 of the
+ * paper, for encoder decisions per block) of frames [first_frame,
+ * first_frame + count) of the most recent launch -- the frames of the last
+ * max_batch-sized chunk of the most recent vca_analyze_frames call --
+ * written to caller-owned DEVICE memory on the context's stream (enqueued,
+ * no wait; the caller orders later use after the stream):
+ *   h_dev [i * P + b]   block energy H_b of frame first_frame + i (FP64),
+ *                       P = vca_block_counts total, blocks ordered as in
+ *                       vca_block_coeffs (Y, then U, then V, raster order);
+ *   dc_dev[i * P + b]   block DC (int32, the integer transform's (0,0));
+ *   dh_dev[i * C_Y + b] |H_b(t) - H_b(t-1)| of luma block b (FP64), the
+ *                       summand of h; 0 where frame t has no previous frame
+ *                       (the first frame after vca_open or vca_reset).
+ * Any of the three output pointers may be NULL (that map is skipped); each
+ * non-NULL one must be 8-byte aligned and hold count maps.
+ * VCA_ERR_INVALID_ARG for a NULL context, count <= 0 or all outputs NULL;
+ * VCA_ERR_STATE if the range is not inside the most recent launch. */
+vca_status vca_block_maps(vca_ctx* ctx, int64_t first_frame, int32_t count, double* h_dev,
+                          int32_t* dc_dev, double* dh_dev);
+
 /* Waits for the context's stream and returns the kernel times measured with
  * HIP events on that stream (VCA_F_TIMING); reset != 0 clears the counters
  * afterwards.  VCA_ERR_STATE if the context was opened without the flag. */

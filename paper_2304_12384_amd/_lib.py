@@ -26,7 +26,7 @@ VCA_F_DOWNSAMPLE = 0x8
 # Every symbol include/vca.h declares.
 EXPORTS = (
     "vca_block_counts", "vca_open", "vca_analyze_frames", "vca_features", "vca_block_coeffs",
-    "vca_block_stats", "vca_get_timing", "vca_tune", "vca_tuned_launch", "vca_reset",
+    "vca_block_stats", "vca_block_maps", "vca_get_timing", "vca_tune", "vca_tuned_launch", "vca_reset",
     "vca_frames_submitted", "vca_close", "vca_status_str", "vca_last_error",
     "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_tune_batch",
     "vca_batch_tuned_launch", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
             "vca_features": (St, [P, ctypes.c_int64, ctypes.c_int32, P]),
             "vca_block_coeffs": (St, [P, ctypes.c_int64, P, ctypes.c_size_t]),
             "vca_block_stats": (St, [P, ctypes.c_int64, P, P, ctypes.c_size_t]),
+            "vca_block_maps": (St, [P, ctypes.c_int64, ctypes.c_int32, P, P, P]),
             "vca_get_timing": (St, [P, ctypes.POINTER(VcaTiming), ctypes.c_int32]),
             "vca_tune": (St, [P, ctypes.POINTER(VcaFrames), ctypes.c_int32, ctypes.c_int32]),
             "vca_tuned_launch": (St, [P, P, P, P]),

@@ -149,6 +149,22 @@ class Analyzer:
               "vca_block_stats", self._ctx)
         return h, dc
 
+    def block_maps(self, first: int, count: int) -> dict:
+        """Per-block maps of frames [first, first + count) of the last launch as
+        device tensors on the context's stream: ``h`` float64 [count, C_Y + C_U + C_V],
+        ``dc`` int32 (same shape), ``dh`` float64 [count, C_Y] = |H_t - H_{t-1}| of
+        the luma blocks (0 for a frame without a previous one)."""
+        total = sum(self.counts)
+        dev = torch.device("cuda", self.device)
+        with torch.cuda.stream(self.stream):
+            h = torch.empty((count, total), dtype=torch.float64, device=dev)
+            dc = torch.empty((count, total), dtype=torch.int32, device=dev)
+            dh = torch.empty((count, self.counts[0]), dtype=torch.float64, device=dev)
+        check(_lib.lib().vca_block_maps(self._ctx, first, count, ctypes.c_void_p(h.data_ptr()),
+                                        ctypes.c_void_p(dc.data_ptr()), ctypes.c_void_p(dh.data_ptr())),
+              "vca_block_maps", self._ctx)
+        return {"h": h, "dc": dc, "dh": dh}
+
     def timing(self, reset: bool = False) -> dict:
         """Kernel times measured with HIP events on the context's stream."""
         t = _lib.VcaTiming()

@@ -143,6 +143,38 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) 
   reduce_frame(p, blockIdx.x);
 }
 
+// Per-block maps of `count` frames starting at frame f0 of the last launch:
+// H and DC copied, |H_t - H_{t-1}| for luma blocks (prev = the frame before
+// f0 of the launch, the state buffer, or none).
+struct MapsParams {
+  const double* blk_h;
+  const int32_t* blk_dc;
+  const double* prev;   // luma H of the frame before f0, or null
+  double* h_out;
+  int32_t* dc_out;
+  double* dh_out;
+  int64_t per_frame;
+  int64_t cnt_y;
+  int64_t f0;           // first frame, relative to the launch
+  int64_t count;
+};
+
+constexpr int kMapsThreads = 256;
+
+__global__ __launch_bounds__(kMapsThreads) void block_maps_kernel(MapsParams p) {
+  const int64_t i = (int64_t)blockIdx.y;   // frame of the range
+  const int64_t f = p.f0 + i;
+  const double* H = p.blk_h + f * p.per_frame;
+  const int32_t* DC = p.blk_dc + f * p.per_frame;
+  const double* prev = f > 0 ? H - p.per_frame : p.prev;
+  for (int64_t b = (int64_t)blockIdx.x * kMapsThreads + threadIdx.x; b < p.per_frame;
+       b += (int64_t)gridDim.x * kMapsThreads) {
+    if (p.h_out) p.h_out[i * p.per_frame + b] = H[b];
+    if (p.dc_out) p.dc_out[i * p.per_frame + b] = DC[b];
+    if (p.dh_out && b < p.cnt_y) p.dh_out[i * p.cnt_y + b] = prev ? fabs(H[b] - prev[b]) : 0.0;
+  }
+}
+
 // Kernel for (bit depth, w, K, coefficient export, ring depth).  Coefficient
 // export (tests only) always uses depth 1.
 using FwdKernel = void (*)(FwdParams);
@@ -202,6 +234,7 @@ struct vca_ctx {
   float* ring = nullptr;
   int cur_state = 0;
   bool has_prev = false;
+  bool last_chunk_prev = false;    // the last launch's first frame had a previous frame
   int64_t submitted = 0;
   int64_t last_chunk_first = -1;  // global index of frame 0 of the most recent launch
   int32_t last_chunk_len = 0;
@@ -480,6 +513,7 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
     hipLaunchKernelGGL(reduce_kernel, dim3(n), dim3(kReduceThreads), 0, ctx->stream, rp);
     HIP_TRY(ctx, hipGetLastError());
     if (ev) HIP_TRY(ctx, hipEventRecord(ev[2], ctx->stream));
+    ctx->last_chunk_prev = ctx->has_prev;
     ctx->cur_state ^= 1;
     ctx->has_prev = true;
     ctx->last_chunk_first = ctx->submitted;
@@ -608,6 +642,35 @@ vca_status vca_block_coeffs(vca_ctx* ctx, int64_t frame, int16_t* out, size_t ca
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
   HIP_TRY(ctx, hipMemcpy(out, ctx->coeffs + (frame - ctx->last_chunk_first) * per,
                          per * sizeof(int16_t), hipMemcpyDeviceToHost));
+  return VCA_OK;
+}
+
+vca_status vca_block_maps(vca_ctx* ctx, int64_t first_frame, int32_t count, double* h_dev,
+                          int32_t* dc_dev, double* dh_dev) {
+  if (!ctx || count <= 0 || (!h_dev && !dc_dev && !dh_dev))
+    return fail(ctx, VCA_ERR_INVALID_ARG, "null context, count <= 0 or no output");
+  if (first_frame < ctx->last_chunk_first ||
+      first_frame + count > ctx->last_chunk_first + ctx->last_chunk_len)
+    return fail(ctx, VCA_ERR_STATE, "frames not in the most recent launch");
+  if (((uintptr_t)h_dev | (uintptr_t)dh_dev | (uintptr_t)dc_dev) & 7)
+    return fail(ctx, VCA_ERR_INVALID_ARG, "outputs must be 8-byte aligned");
+  DeviceGuard guard(ctx->device);
+  MapsParams mp{};
+  mp.blk_h = ctx->blk_h;
+  mp.blk_dc = ctx->blk_dc;
+  // the launch's reduction read the previous frame's luma H from the state
+  // buffer it did not write, which the next launch has not touched yet
+  mp.prev = ctx->last_chunk_prev ? ctx->state[ctx->cur_state ^ 1] : nullptr;
+  mp.h_out = h_dev;
+  mp.dc_out = dc_dev;
+  mp.dh_out = dh_dev;
+  mp.per_frame = ctx->geo.per_frame;
+  mp.cnt_y = ctx->geo.cnt[0];
+  mp.f0 = first_frame - ctx->last_chunk_first;
+  mp.count = count;
+  const int gx = (int)std::min<int64_t>((mp.per_frame + kMapsThreads - 1) / kMapsThreads, 64);
+  hipLaunchKernelGGL(block_maps_kernel, dim3(gx, count), dim3(kMapsThreads), 0, ctx->stream, mp);
+  HIP_TRY(ctx, hipGetLastError());
   return VCA_OK;
 }
 
