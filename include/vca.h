@@ -48,7 +48,7 @@ typedef struct vca_ctx vca_ctx; /* opaque; owned by the library */
 typedef enum {
   VCA_OK = 0,
   VCA_ERR_INVALID_ARG = 1, /* null pointer, out-of-range field, misaligned buffer      */
-  VCA_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. host-resident frames)     */
+  VCA_ERR_UNSUPPORTED = 2, /* valid but not implemented (e.g. host frames to vca_tune)   */
   VCA_ERR_OOM = 3,         /* device or host allocation failed                          */
   VCA_ERR_DEVICE = 4,      /* a HIP call failed; vca_last_error() holds its message     */
   VCA_ERR_STATE = 5        /* request inconsistent with the context's history           */
@@ -82,8 +82,11 @@ typedef struct {
   int32_t feature_capacity; /* frames of features kept on the device (ring); 0 = 65536     */
 } vca_config;
 
-/* A run of consecutive frames of one video, as device pointers.
- * Alignment: y/u/v, pitches and frame strides must be multiples of 16 bytes. */
+/* A run of consecutive frames of one video.
+ * Device frames (on_device = 1): y/u/v, pitches and frame strides must be
+ * multiples of 16 bytes.  Host frames (on_device = 0, vca_analyze_frames
+ * only): any alignment; the library copies them through pinned staging
+ * buffers before vca_analyze_frames returns. */
 typedef struct {
   const void* y;       /* first sample of frame 0 of each plane                        */
   const void* u;
@@ -92,7 +95,7 @@ typedef struct {
   int64_t pitch_uv;    /* bytes between rows of U and of V (>= width/2 * bytes/sample) */
   int64_t fstride_y;   /* bytes between consecutive frames of Y                        */
   int64_t fstride_uv;  /* bytes between consecutive frames of U and of V               */
-  int32_t on_device;   /* 1: device pointers (the only supported form); 0: host        */
+  int32_t on_device;   /* 1: device pointers; 0: host pointers (staged by the library) */
 } vca_frames;
 
 /* Per-frame feature record, in the order Section 2 lists the features. */
@@ -122,10 +125,33 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out);
 
 /* Enqueues the analysis of n_frames frames (n_frames >= 0) on the context's
  * stream and returns without waiting.  Frames are numbered after those of
- * earlier calls, and h chains across calls.  The caller keeps the frame
- * buffers valid until the stream has finished the work (vca_features waits).
+ * earlier calls, and h chains across calls.  Device frames: the caller keeps
+ * the buffers valid until the stream has finished the work (vca_features
+ * waits).  Host frames (frames->on_device = 0): the library copies them,
+ * batch by batch, into one of two pinned staging buffers (in parallel over
+ * host threads) and from there to the device on a second stream, each
+ * batch's copy overlapping the analysis of the one before; the caller may
+ * reuse its buffers as soon as the call returns.  Host frames are not
+ * accepted with VCA_F_KEEP_COEFFS (VCA_ERR_UNSUPPORTED).
  * With VCA_F_KEEP_COEFFS, n_frames must not exceed max_batch. */
 vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* frames, int32_t n_frames);
+
+/* Analyses frames [first_frame, first_frame + n_frames) of a raw planar
+ * 4:2:0 .yuv file (I420: per frame the Y rows, then U, then V, no row
+ * padding; 10-bit samples as little-endian uint16) of the context's
+ * resolution and bit depth, read with pread straight into the pinned staging
+ * buffers and otherwise handled like host frames.  Returns when every
+ * frame has been read; the analysis is enqueued.  VCA_ERR_INVALID_ARG if the
+ * file cannot be opened or holds fewer frames. */
+vca_status vca_analyze_yuv_file(vca_ctx* ctx, const char* path, int64_t first_frame,
+                                int32_t n_frames);
+
+/* Host only (no device): reads frames [first_frame, first_frame + n_frames)
+ * of a raw .yuv file laid out as above into tight planes y [n][height][width],
+ * u and v [n][height/2][width/2] (samples of 1 or 2 bytes).
+ * VCA_ERR_INVALID_ARG on a bad argument, a missing file or too few frames. */
+vca_status vca_read_yuv(const char* path, int32_t width, int32_t height, int32_t bit_depth,
+                        int64_t first_frame, int32_t n_frames, void* y, void* u, void* v);
 
 /* Waits for the context's stream, then copies the features of frames
  * [first_frame, first_frame + count) into out_host (count records).

@@ -25,7 +25,8 @@ VCA_F_DOWNSAMPLE = 0x8
 
 # Every symbol include/vca.h declares.
 EXPORTS = (
-    "vca_block_counts", "vca_open", "vca_analyze_frames", "vca_features", "vca_block_coeffs",
+    "vca_block_counts", "vca_open", "vca_analyze_frames", "vca_analyze_yuv_file", "vca_read_yuv",
+    "vca_features", "vca_block_coeffs",
     "vca_block_stats", "vca_block_maps", "vca_get_timing", "vca_tune", "vca_tuned_launch", "vca_reset",
     "vca_frames_submitted", "vca_close", "vca_status_str", "vca_last_error",
     "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_tune_batch",
@@ -95,6 +96,9 @@ def lib() -> ctypes.CDLL:
             "vca_block_counts": (St, [ctypes.POINTER(VcaConfig), P]),
             "vca_open": (St, [ctypes.POINTER(VcaConfig), P, ctypes.POINTER(P)]),
             "vca_analyze_frames": (St, [P, ctypes.POINTER(VcaFrames), ctypes.c_int32]),
+            "vca_analyze_yuv_file": (St, [P, ctypes.c_char_p, ctypes.c_int64, ctypes.c_int32]),
+            "vca_read_yuv": (St, [ctypes.c_char_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int64, ctypes.c_int32, P, P, P]),
             "vca_features": (St, [P, ctypes.c_int64, ctypes.c_int32, P]),
             "vca_block_coeffs": (St, [P, ctypes.c_int64, P, ctypes.c_size_t]),
             "vca_block_stats": (St, [P, ctypes.c_int64, P, P, ctypes.c_size_t]),

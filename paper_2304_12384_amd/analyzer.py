@@ -7,6 +7,7 @@ library through the C ABI, on the caller's current torch stream.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 import torch
@@ -120,6 +121,40 @@ class Analyzer:
         self._keep = [y, u, v]
         return first
 
+    def submit_host(self, y, u, v) -> int:
+        """Enqueues host-resident frames (numpy arrays or CPU tensors, [n, H, W]
+        and [n, H/2, W/2], uint8 or 16-bit); the library stages them through
+        pinned buffers and returns once they are copied.  Returns the index of
+        the first frame."""
+        planes = [_host_plane(p, self.bit_depth) for p in (y, u, v)]
+        (ya, py, fy), (ua, pu, fu), (va, pv, fv) = planes
+        n = ya.shape[0]
+        if ua.shape[0] != n or va.shape[0] != n:
+            raise ValueError("planes hold different frame counts")
+        if ya.shape[1:] != (self.height, self.width):
+            raise ValueError(f"luma shape {ya.shape[1:]} != {(self.height, self.width)}")
+        if ua.shape[1:] != (self.height // 2, self.width // 2) or va.shape[1:] != ua.shape[1:]:
+            raise ValueError("chroma planes must be [n, H/2, W/2]")
+        if pu != pv or fu != fv:
+            raise ValueError("U and V must share pitch and frame stride")
+        fr = VcaFrames(ya.ctypes.data, ua.ctypes.data, va.ctypes.data, py, pu, fy, fu, 0)
+        first = self.submitted
+        check(_lib.lib().vca_analyze_frames(self._ctx, ctypes.byref(fr), n), "vca_analyze_frames",
+              self._ctx)
+        return first
+
+    def submit_file(self, path: str, first: int = 0, count: int | None = None) -> int:
+        """Enqueues frames [first, first + count) of a raw 4:2:0 .yuv file of this
+        resolution and bit depth (count None: to the end of the file)."""
+        if count is None:
+            bps = 1 if self.bit_depth == 8 else 2
+            frame = (self.width * self.height + 2 * (self.width // 2) * (self.height // 2)) * bps
+            count = os.path.getsize(path) // frame - first
+        start = self.submitted
+        check(_lib.lib().vca_analyze_yuv_file(self._ctx, os.fsencode(path), first, count),
+              "vca_analyze_yuv_file", self._ctx)
+        return start
+
     def features(self, first: int, count: int) -> np.ndarray:
         """Features of frames [first, first + count) as float32 [count, 7]; waits."""
         out = np.zeros((count, 7), np.float32)
@@ -186,6 +221,48 @@ class Analyzer:
         check(_lib.lib().vca_tuned_launch(self._ctx, ctypes.byref(d), ctypes.byref(g), ctypes.byref(ms)),
               "vca_tuned_launch", self._ctx)
         return {"depth": d.value, "groups_per_cu": g.value, "ms": ms.value}
+
+
+def _host_plane(p, bit_depth):
+    """(contiguous-row numpy array, pitch, frame stride) of a host plane."""
+    if hasattr(p, "is_cuda"):
+        if p.is_cuda:
+            raise ValueError("submit_host takes host arrays")
+        p = p.numpy()
+    a = np.asarray(p)
+    if a.ndim != 3:
+        raise ValueError("planes must be [n, rows, columns]")
+    bps = 1 if bit_depth == 8 else 2
+    if a.itemsize != bps:
+        raise ValueError(f"expected {bps}-byte samples, got {a.dtype}")
+    if a.strides[2] != bps:
+        a = np.ascontiguousarray(a)
+    return a, a.strides[1], a.strides[0]
+
+
+def read_yuv(path: str, width: int, height: int, bit_depth: int = 8, first: int = 0,
+             count: int | None = None):
+    """Frames [first, first + count) of a raw 4:2:0 .yuv file as numpy planes
+    (y [n, H, W], u and v [n, H/2, W/2]; uint8, or uint16 for 10-bit)."""
+    dt = np.uint8 if bit_depth == 8 else np.uint16
+    bps = np.dtype(dt).itemsize
+    frame = (width * height + 2 * (width // 2) * (height // 2)) * bps
+    if count is None:
+        count = os.path.getsize(path) // frame - first
+    y = np.empty((count, height, width), dt)
+    u = np.empty((count, height // 2, width // 2), dt)
+    v = np.empty_like(u)
+    check(_lib.lib().vca_read_yuv(os.fsencode(path), width, height, bit_depth, first, count,
+                                  y.ctypes.data, u.ctypes.data, v.ctypes.data), "vca_read_yuv")
+    return y, u, v
+
+
+def write_yuv(path: str, y, u, v) -> None:
+    """Writes planes ([n, H, W], [n, H/2, W/2]) as a raw 4:2:0 .yuv file."""
+    with open(path, "wb") as f:
+        for t in range(y.shape[0]):
+            for p in (y[t], u[t], v[t]):
+                f.write(np.ascontiguousarray(p).astype(p.dtype.newbyteorder("<"), copy=False).tobytes())
 
 
 def _frames(owner, y, u, v) -> VcaFrames:

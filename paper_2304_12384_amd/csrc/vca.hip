@@ -21,11 +21,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/vca.h"
 #include "vca_host.h"
+#include "vca_ingest.h"
 #include "vca_reduce.h"
 #include "vca_strip.h"
 #include "vca_tile.h"
@@ -242,6 +244,20 @@ struct vca_ctx {
   std::vector<hipEvent_t> ev_pool;
   std::vector<int32_t> ev_frames;
   size_t ev_used = 0;
+  // host-resident frames: two staging slots (pinned host + device), filled
+  // by the worker pool and copied on copy_stream; created on first use
+  struct IngestSlot {
+    uint8_t* pinned = nullptr;
+    uint8_t* dev = nullptr;
+    hipEvent_t copied = nullptr;   // its host-to-device copy is done
+    hipEvent_t used = nullptr;     // the analysis reading it is done
+    bool busy = false;
+  };
+  IngestSlot ing[2];
+  int32_t ing_batch = 0;           // frames per slot
+  int ing_next = 0;
+  hipStream_t copy_stream = nullptr;
+  std::unique_ptr<WorkerPool> pool;
   std::string err;
 };
 
@@ -377,6 +393,14 @@ void vca_close(vca_ctx* ctx) {
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
+    for (auto& sl : ctx->ing) {
+      if (sl.pinned) (void)hipHostFree(sl.pinned);
+      if (sl.dev) (void)hipFree(sl.dev);
+      if (sl.copied) (void)hipEventDestroy(sl.copied);
+      if (sl.used) (void)hipEventDestroy(sl.used);
+    }
+    if (ctx->copy_stream) (void)hipStreamDestroy(ctx->copy_stream);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   }
   delete ctx;
@@ -462,16 +486,13 @@ vca_status vca_reset(vca_ctx* ctx) {
   return VCA_OK;
 }
 
-vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames) {
-  if (!ctx || !fr || n_frames < 0) return fail(ctx, VCA_ERR_INVALID_ARG, "null argument or n < 0");
-  if (!fr->on_device) return fail(ctx, VCA_ERR_UNSUPPORTED, "host-resident frames");
-  if (n_frames == 0) return VCA_OK;
-  const vca_config& cfg = ctx->cfg;
-  if (const char* msg = check_frames(cfg, fr, n_frames)) return fail(ctx, VCA_ERR_INVALID_ARG, msg);
-  if ((cfg.flags & VCA_F_KEEP_COEFFS) && n_frames > cfg.max_batch)
-    return fail(ctx, VCA_ERR_INVALID_ARG, "VCA_F_KEEP_COEFFS: n_frames exceeds max_batch");
+}  // extern "C"
 
-  DeviceGuard guard(ctx->device);
+namespace {
+
+// Enqueues the analysis of n_frames validated device frames.
+vca_status analyze_device(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames) {
+  const vca_config& cfg = ctx->cfg;
   const double ww = (double)cfg.block_size * cfg.block_size;
   const int depth = ctx->tuned.depth > 0 ? ctx->tuned.depth : kDefaultDepth;
   const int gpc = ctx->env_groups_per_cu > 0 ? ctx->env_groups_per_cu : ctx->tuned.groups_per_cu;
@@ -522,6 +543,179 @@ vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_fram
     done += n;
   }
   return VCA_OK;
+}
+
+// Staging layout of one ingest slot: planes of ing_batch frames, Y then U
+// then V, rows padded to 16 bytes (the device path's alignment rule).
+struct SlotLayout {
+  int64_t pitch_y, pitch_uv, fstride_y, fstride_uv, off_u, off_v, bytes;
+};
+
+SlotLayout slot_layout(const vca_config& cfg, int32_t batch) {
+  const YuvLayout L = YuvLayout::of(cfg.width, cfg.height, cfg.bit_depth);
+  SlotLayout s;
+  s.pitch_y = (L.row_y + 15) / 16 * 16;
+  s.pitch_uv = (L.row_uv + 15) / 16 * 16;
+  s.fstride_y = s.pitch_y * L.rows_y;
+  s.fstride_uv = s.pitch_uv * L.rows_uv;
+  s.off_u = s.fstride_y * batch;
+  s.off_v = s.off_u + s.fstride_uv * batch;
+  s.bytes = s.off_v + s.fstride_uv * batch;
+  return s;
+}
+
+constexpr int64_t kIngestSlotBytes = 64ll << 20;   // target staging per slot
+
+vca_status ingest_setup(vca_ctx* ctx) {
+  if (ctx->copy_stream) return VCA_OK;
+  const SlotLayout one = slot_layout(ctx->cfg, 1);
+  ctx->ing_batch = (int32_t)std::max<int64_t>(
+      1, std::min<int64_t>(kIngestSlotBytes / one.bytes, ctx->cfg.max_batch));
+  const SlotLayout sl = slot_layout(ctx->cfg, ctx->ing_batch);
+  for (auto& slot : ctx->ing) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&slot.pinned), (size_t)sl.bytes,
+                                 hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ctx, VCA_ERR_OOM, "hipHostMalloc: staging buffer");
+    vca_status s = dev_alloc(ctx, &slot.dev, (size_t)sl.bytes);
+    if (s != VCA_OK) return s;
+    HIP_TRY(ctx, hipEventCreateWithFlags(&slot.copied, hipEventDisableTiming));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&slot.used, hipEventDisableTiming));
+  }
+  ctx->pool.reset(new WorkerPool(ingest_threads()));
+  HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking));
+  return VCA_OK;
+}
+
+// Analyses n_frames frames that `fill` writes into host memory: fill(first,
+// count, dst, part, parts) writes part `part` of `parts` of frames [first,
+// first + count) of the run.  Double-buffered: while the device copies slot
+// s and analyses the other slot's frames, the pool fills the next batch.
+template <class Fill>
+vca_status analyze_staged(vca_ctx* ctx, int32_t n_frames, Fill fill) {
+  vca_status st = ingest_setup(ctx);
+  if (st != VCA_OK) return st;
+  const SlotLayout sl = slot_layout(ctx->cfg, ctx->ing_batch);
+  for (int32_t done = 0; done < n_frames;) {
+    const int32_t b = std::min(ctx->ing_batch, n_frames - done);
+    vca_ctx::IngestSlot& slot = ctx->ing[ctx->ing_next];
+    ctx->ing_next ^= 1;
+    // the pinned buffer is free once its previous copy has finished
+    if (slot.busy) HIP_TRY(ctx, hipEventSynchronize(slot.copied));
+    const PlanarDst dst{slot.pinned, slot.pinned + sl.off_u, slot.pinned + sl.off_v,
+                        sl.pitch_y,  sl.pitch_uv,            sl.fstride_y,
+                        sl.fstride_uv};
+    std::atomic<bool> ok{true};
+    const int parts = ctx->pool->size();
+    ctx->pool->run([&](int part) {
+      if (!fill(done, b, dst, part, parts)) ok = false;
+    });
+    if (!ok) return fail(ctx, VCA_ERR_INVALID_ARG, "reading the frames failed");
+    // the device buffer is free once the analysis of its previous batch is done
+    if (slot.busy) HIP_TRY(ctx, hipStreamWaitEvent(ctx->copy_stream, slot.used, 0));
+    // copy the used part of each plane region
+    HIP_TRY(ctx, hipMemcpyAsync(slot.dev, slot.pinned, (size_t)(sl.fstride_y * b),
+                                hipMemcpyHostToDevice, ctx->copy_stream));
+    HIP_TRY(ctx, hipMemcpyAsync(slot.dev + sl.off_u, slot.pinned + sl.off_u,
+                                (size_t)(sl.fstride_uv * b), hipMemcpyHostToDevice, ctx->copy_stream));
+    HIP_TRY(ctx, hipMemcpyAsync(slot.dev + sl.off_v, slot.pinned + sl.off_v,
+                                (size_t)(sl.fstride_uv * b), hipMemcpyHostToDevice, ctx->copy_stream));
+    HIP_TRY(ctx, hipEventRecord(slot.copied, ctx->copy_stream));
+    HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, slot.copied, 0));
+    vca_frames df{};
+    df.y = slot.dev;
+    df.u = slot.dev + sl.off_u;
+    df.v = slot.dev + sl.off_v;
+    df.pitch_y = sl.pitch_y;
+    df.pitch_uv = sl.pitch_uv;
+    df.fstride_y = sl.fstride_y;
+    df.fstride_uv = sl.fstride_uv;
+    df.on_device = 1;
+    st = analyze_device(ctx, &df, b);
+    if (st != VCA_OK) return st;
+    HIP_TRY(ctx, hipEventRecord(slot.used, ctx->stream));
+    slot.busy = true;
+    done += b;
+  }
+  return VCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames) {
+  if (!ctx || !fr || n_frames < 0) return fail(ctx, VCA_ERR_INVALID_ARG, "null argument or n < 0");
+  if (n_frames == 0) return VCA_OK;
+  const vca_config& cfg = ctx->cfg;
+  if ((cfg.flags & VCA_F_KEEP_COEFFS) && n_frames > cfg.max_batch)
+    return fail(ctx, VCA_ERR_INVALID_ARG, "VCA_F_KEEP_COEFFS: n_frames exceeds max_batch");
+  DeviceGuard guard(ctx->device);
+  if (fr->on_device) {
+    if (const char* msg = check_frames(cfg, fr, n_frames)) return fail(ctx, VCA_ERR_INVALID_ARG, msg);
+    return analyze_device(ctx, fr, n_frames);
+  }
+  if (const char* msg = check_host_frames(cfg, fr, n_frames)) return fail(ctx, VCA_ERR_INVALID_ARG, msg);
+  if ((cfg.flags & VCA_F_KEEP_COEFFS) && n_frames > 0)
+    return fail(ctx, VCA_ERR_UNSUPPORTED, "VCA_F_KEEP_COEFFS with host-resident frames");
+  const YuvLayout L = YuvLayout::of(cfg.width, cfg.height, cfg.bit_depth);
+  const vca_frames src = *fr;
+  return analyze_staged(ctx, n_frames, [&](int32_t first, int32_t b, const PlanarDst& d, int part,
+                                           int parts) {
+    int64_t y0, y1, c0, c1;
+    band(L.rows_y, part, parts, y0, y1);
+    band(L.rows_uv, part, parts, c0, c1);
+    for (int32_t i = 0; i < b; i++) {
+      const int64_t f = first + i;
+      copy_rows(d.y + i * d.fstride_y, d.pitch_y,
+                static_cast<const uint8_t*>(src.y) + f * src.fstride_y, src.pitch_y, L.row_y, y0, y1);
+      copy_rows(d.u + i * d.fstride_uv, d.pitch_uv,
+                static_cast<const uint8_t*>(src.u) + f * src.fstride_uv, src.pitch_uv, L.row_uv, c0, c1);
+      copy_rows(d.v + i * d.fstride_uv, d.pitch_uv,
+                static_cast<const uint8_t*>(src.v) + f * src.fstride_uv, src.pitch_uv, L.row_uv, c0, c1);
+    }
+    return true;
+  });
+}
+
+vca_status vca_analyze_yuv_file(vca_ctx* ctx, const char* path, int64_t first_frame,
+                                int32_t n_frames) {
+  if (!ctx || !path || first_frame < 0 || n_frames < 0)
+    return fail(ctx, VCA_ERR_INVALID_ARG, "null argument or negative frame range");
+  if (n_frames == 0) return VCA_OK;
+  const vca_config& cfg = ctx->cfg;
+  if (cfg.flags & VCA_F_KEEP_COEFFS)
+    return fail(ctx, VCA_ERR_UNSUPPORTED, "VCA_F_KEEP_COEFFS with host-resident frames");
+  const YuvLayout L = YuvLayout::of(cfg.width, cfg.height, cfg.bit_depth);
+  const int64_t avail = yuv_frames_in_file(path, L);
+  if (avail < 0) return fail(ctx, VCA_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  if (first_frame + n_frames > avail)
+    return fail(ctx, VCA_ERR_INVALID_ARG, "the file holds fewer frames than requested");
+  const int fd = ::open(path, O_RDONLY);
+  if (fd < 0) return fail(ctx, VCA_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  DeviceGuard guard(ctx->device);
+  const vca_status st = analyze_staged(
+      ctx, n_frames, [&](int32_t first, int32_t b, const PlanarDst& d, int part, int parts) {
+        return read_yuv_part(fd, L, first_frame + first, b, d, part, parts);
+      });
+  ::close(fd);
+  return st;
+}
+
+vca_status vca_read_yuv(const char* path, int32_t width, int32_t height, int32_t bit_depth,
+                        int64_t first_frame, int32_t n_frames, void* y, void* u, void* v) {
+  if (!path || !y || !u || !v || first_frame < 0 || n_frames < 0) return VCA_ERR_INVALID_ARG;
+  if (width <= 0 || height <= 0 || (width & 1) || (height & 1) || (bit_depth != 8 && bit_depth != 10))
+    return VCA_ERR_INVALID_ARG;
+  const YuvLayout L = YuvLayout::of(width, height, bit_depth);
+  const int64_t avail = yuv_frames_in_file(path, L);
+  if (avail < 0 || first_frame + n_frames > avail) return VCA_ERR_INVALID_ARG;
+  const int fd = ::open(path, O_RDONLY);
+  if (fd < 0) return VCA_ERR_INVALID_ARG;
+  const PlanarDst d{static_cast<uint8_t*>(y), static_cast<uint8_t*>(u), static_cast<uint8_t*>(v),
+                    L.row_y, L.row_uv, L.plane_y, L.plane_uv};
+  const bool ok = read_yuv_part(fd, L, first_frame, n_frames, d, 0, 1);
+  ::close(fd);
+  return ok ? VCA_OK : VCA_ERR_INVALID_ARG;
 }
 
 vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_t reps) {

@@ -109,6 +109,20 @@ inline const char* check_frames(const vca_config& cfg, const vca_frames* fr, int
   return nullptr;
 }
 
+// Host-resident frames (vca_frames.on_device == 0): any alignment, the
+// same row and frame-stride rules.  nullptr when valid.
+inline const char* check_host_frames(const vca_config& cfg, const vca_frames* fr, int32_t n_frames) {
+  const int bps = cfg.bit_depth == 8 ? 1 : 2;
+  if (fr->on_device) return "device frames";
+  if (!fr->y || !fr->u || !fr->v) return "null plane pointer";
+  if (fr->pitch_y < (int64_t)cfg.width * bps || fr->pitch_uv < (int64_t)cfg.width / 2 * bps)
+    return "pitch smaller than a row";
+  if (n_frames > 1 && (fr->fstride_y < fr->pitch_y * cfg.height ||
+                       fr->fstride_uv < fr->pitch_uv * (cfg.height / 2)))
+    return "frame stride smaller than a frame";
+  return nullptr;
+}
+
 // Launch parameters chosen by the autotuner (depth 0 = not tuned).
 struct LaunchChoice {
   int depth = 0;          // work units in flight per wavefront (1..4)
