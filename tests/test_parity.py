@@ -90,11 +90,17 @@ def test_2160p_bench_launch_sampled(vca):
     print_case(test="bench_launch_600x2160p")
     an.submit(*buf.planes())
     feats = an.features(0, 600)
+    sampled = (0, 1, 119, 120, 121, 240, 359, 480, 599)
+    maps = {t: an.block_maps(t, 1) for t in sampled}
+    torch.cuda.synchronize()
     an.close()
-    for t in (0, 1, 119, 120, 121, 240, 359, 480, 599):
+    for t in sampled:
         t0 = max(0, t - 1)
-        ref = oracle_run(sv.frames(t0, t + 1), threads=8).features[-1]
-        assert_features_close(feats[t:t + 1], ref[None])
+        ref = oracle_run(sv.frames(t0, t + 1), threads=8)
+        assert_features_close(feats[t:t + 1], ref.features[-1][None])
+        # every block of the sampled frame: DC exact, H to 1e-12
+        assert (maps[t]["dc"].cpu().numpy()[0] == ref.block_dc[-1]).all(), f"frame {t}"
+        np.testing.assert_allclose(maps[t]["h"].cpu().numpy()[0], ref.block_h[-1], rtol=1e-12, atol=0)
 
 
 def test_call_boundaries_reset_and_chunking(vca, patches):

@@ -65,6 +65,29 @@ def test_10bit_stress_bit_exact(vca, w, res):
     check_bit_exact(vca, video, w, 0)
 
 
+@pytest.mark.parametrize("w,k", [(32, 0), (16, 0), (8, 0), (32, 16), (16, 8), (8, 2)])
+@pytest.mark.parametrize("res", [(1920, 1080), (3840, 2160)])
+def test_10bit_stress_strip_path(vca, w, k, res):
+    """The production strip kernels (no coefficient export): every block's DC
+    bit-exact and H to 1e-12 -- a wrong |coefficient| anywhere in a block
+    moves H by at least its weight (>= 1) -- on the 10-bit worst cases."""
+    width, height = res
+    print_case(test="10bit_stress_strip", w=w, k=k, width=width, height=height)
+    video = synth.stress_video(width, height, 3, cell=w, stream=200 + w + k)
+    an = vca.Analyzer(width, height, bit_depth=10, block_size=w, lowpass_k=k, validate=True)
+    y, u, v = to_device(video)
+    an.submit(y, u, v)
+    feats = an.features(0, 3)
+    maps = an.block_maps(0, 3)
+    torch.cuda.synchronize()
+    an.close()
+    cfg = oracle.Config(width, height, 10, w, k)
+    ref = oracle.analyze(cfg, video.y, video.u, video.v, threads=8, want_blocks=True)
+    assert (maps["dc"].cpu().numpy() == ref.block_dc).all()
+    np.testing.assert_allclose(maps["h"].cpu().numpy(), ref.block_h, rtol=1e-12, atol=0)
+    assert_features_close(feats, ref.features)
+
+
 @pytest.mark.parametrize("w,k", [(32, 16), (32, 8), (16, 8), (8, 4), (8, 2)])
 def test_10bit_lowpass_bit_exact(vca, w, k):
     print_case(test="10bit_lowpass", w=w, k=k)
