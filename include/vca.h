@@ -248,7 +248,9 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
  * stream's work is done (vca_batch_features waits). */
 vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames);
 
-/* Features of frames [first, first + count) of stream `stream`; waits. */
+/* Features of frames [first, first + count) of stream `stream`; waits.
+ * VCA_ERR_STATE if that stream was opened with VCA_F_VALIDATE and a 10-bit
+ * sample above 1023 was submitted to it (other streams are unaffected). */
 vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32_t count,
                               vca_frame_features* out_host);
 

@@ -127,8 +127,9 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
 
 // Persistent forward kernel over strips (vca_strip.h): wavefront i of S
 // takes the runs of kRun strips i, i + S, ...
-// kDs: the planes are downsampled by two on the fly (VCA_F_DOWNSAMPLE).
-template <int kBits, int kW, int kK, int kDepth, bool kDs>
+// kDs: the planes are downsampled by two on the fly (VCA_F_DOWNSAMPLE);
+// kValidate (10-bit): samples above 1023 set the error flag.
+template <int kBits, int kW, int kK, int kDepth, bool kDs, bool kValidate>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerGroup][kStage];
   PackConsts<kW, kK> pc;
   pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
-  run_strips<kBits, kW, kK, kDepth, kDs>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
+  run_strips<kBits, kW, kK, kDepth, kDs, kValidate>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
                                          gridDim.x * kWavesPerGroup,
                                          p.n_frames * p.geom.strips_per_frame, lane, stage[wave]);
 }
@@ -181,33 +182,37 @@ __global__ __launch_bounds__(kMapsThreads) void block_maps_kernel(MapsParams p) 
 // export (tests only) always uses depth 1.
 using FwdKernel = void (*)(FwdParams);
 
+// validate (10-bit only): the validating kernel, one depth
 template <int B, int W, int K, bool kDs>
-FwdKernel pick_depth(int depth) {
-  if (depth == 1) return strip_kernel<B, W, K, 1, kDs>;
-  if (depth >= 4) return strip_kernel<B, W, K, 4, kDs>;   // capped at the units per strip
-  return strip_kernel<B, W, K, 2, kDs>;
+FwdKernel pick_depth(int depth, bool validate) {
+  if constexpr (B != 8) {
+    if (validate) return strip_kernel<B, W, K, 1, kDs, true>;
+  }
+  if (depth == 1) return strip_kernel<B, W, K, 1, kDs, false>;
+  if (depth >= 4) return strip_kernel<B, W, K, 4, kDs, false>;   // capped at the units per strip
+  return strip_kernel<B, W, K, 2, kDs, false>;
 }
 
 template <int B, int W>
-FwdKernel pick_k(int K, bool keep, bool ds, int depth) {
-  if (ds) return K == W ? pick_depth<B, W, W, true>(depth) : nullptr;
-  if (K == W) return keep ? fwd_kernel<B, W, W, true, 1> : pick_depth<B, W, W, false>(depth);
-  if (K == W / 2) return keep ? fwd_kernel<B, W, W / 2, true, 1> : pick_depth<B, W, W / 2, false>(depth);
-  if (K == W / 4) return keep ? fwd_kernel<B, W, W / 4, true, 1> : pick_depth<B, W, W / 4, false>(depth);
+FwdKernel pick_k(int K, bool keep, bool ds, int depth, bool v) {
+  if (ds) return K == W ? pick_depth<B, W, W, true>(depth, v) : nullptr;
+  if (K == W) return keep ? fwd_kernel<B, W, W, true, 1> : pick_depth<B, W, W, false>(depth, v);
+  if (K == W / 2) return keep ? fwd_kernel<B, W, W / 2, true, 1> : pick_depth<B, W, W / 2, false>(depth, v);
+  if (K == W / 4) return keep ? fwd_kernel<B, W, W / 4, true, 1> : pick_depth<B, W, W / 4, false>(depth, v);
   return nullptr;
 }
 
 template <int B>
-FwdKernel pick_w(int w, int K, bool keep, bool ds, int depth) {
-  if (w == 32) return pick_k<B, 32>(K, keep, ds, depth);
-  if (w == 16) return pick_k<B, 16>(K, keep, ds, depth);
-  if (w == 8) return pick_k<B, 8>(K, keep, ds, depth);
+FwdKernel pick_w(int w, int K, bool keep, bool ds, int depth, bool v) {
+  if (w == 32) return pick_k<B, 32>(K, keep, ds, depth, v);
+  if (w == 16) return pick_k<B, 16>(K, keep, ds, depth, v);
+  if (w == 8) return pick_k<B, 8>(K, keep, ds, depth, v);
   return nullptr;
 }
 
-FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, bool ds, int depth) {
-  return bits == 8 ? pick_w<8>(w, K, keep, ds, depth)
-                   : (bits == 10 ? pick_w<10>(w, K, keep, ds, depth) : nullptr);
+FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, bool ds, int depth, bool validate) {
+  return bits == 8 ? pick_w<8>(w, K, keep, ds, depth, false)
+                   : (bits == 10 ? pick_w<10>(w, K, keep, ds, depth, validate) : nullptr);
 }
 
 }  // namespace
@@ -327,7 +332,8 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
 vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu) {
   const bool keep = ctx->coeffs != nullptr;
   FwdKernel kern =
-      select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth);
+      select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth,
+                        (ctx->cfg.flags & VCA_F_VALIDATE) != 0);
   if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
   // Persistent grid: at most as many workgroups as can be resident at once,
   // so no workgroup waits for another to drain before it starts its loop.
@@ -739,7 +745,8 @@ vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_
   for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
     int resident = 0;
     FwdKernel kern =
-        select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, ctx->geo.ds, depth);
+        select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, ctx->geo.ds, depth,
+                          (ctx->cfg.flags & VCA_F_VALIDATE) != 0);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0) != hipSuccess)
       resident = 1;
     for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {

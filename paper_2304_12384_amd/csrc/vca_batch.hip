@@ -49,6 +49,7 @@ struct StreamDesc {
   int32_t strips;                  // strips of the stream in this launch
   int32_t chunk_begin, chunk_end;  // the stream's chunks in the launch's flat list
   int32_t validate;
+  int32_t stream;                  // index of the stream (its error flag)
 };
 
 // Consecutive strips of one stream handed to a wavefront at a time.
@@ -72,7 +73,7 @@ struct BatchParams {
   const double* tab_wp;  // [kKinds][16][64] packed-layout weights
   double* blk_h;
   int32_t* blk_dc;
-  int32_t* err_flag;
+  int32_t* err_flag;      // [n_streams]: a validated 10-bit sample above 1023
 };
 
 struct BatchReduceParams {
@@ -95,9 +96,10 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw,
     while (d < kr.desc_end - 1 && c >= p.streams[d].chunk_end) d++;
     const StreamDesc& sd = p.streams[d];
     o.validate = sd.validate;
+    o.err_flag = p.err_flag + sd.stream;
     const int s0 = (c - sd.chunk_begin) * kChunkStrips;
     const int s1 = min(s0 + kChunkStrips, sd.strips);
-    run_strips<kBits, kW, kK, kDepth>(sd.geom, o, pc, s0 / kRun, 1, s1, lane, stage);
+    run_strips<kBits, kW, kK, kDepth, false, (kBits != 8)>(sd.geom, o, pc, s0 / kRun, 1, s1, lane, stage);
   }
 }
 
@@ -284,6 +286,7 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
       chunks += (sd.strips + kChunkStrips - 1) / kChunkStrips;
       sd.chunk_end = chunks;
       sd.validate = (c.flags & VCA_F_VALIDATE) && c.bit_depth == 10 ? 1 : 0;
+      sd.stream = s;
     }
     kr.desc_end = i;
     kr.chunk_end = chunks;
@@ -486,13 +489,14 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   if ((s = balloc(b, &b->blk_dc, (size_t)blk)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->state, (size_t)st_total)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->rings, (size_t)ring_total)) != VCA_OK) return bail(s);
-  if ((s = balloc(b, &b->err_flag, 1)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->err_flag, (size_t)n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->d_streams, n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->d_red, n_streams)) != VCA_OK) return bail(s);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_streams), sizeof(StreamDesc) * n_streams, 0) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(ReduceParams) * n_streams, 0) != hipSuccess)
     return bail(VCA_ERR_OOM);
-  if (hipMemset(b->err_flag, 0, sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
+  if (hipMemset(b->err_flag, 0, sizeof(int32_t) * (size_t)n_streams) != hipSuccess)
+    return bail(VCA_ERR_DEVICE);
   // operand and weight tables of every kind (packed layout)
   std::vector<int8_t> b1all((size_t)kKinds * kMaxPack * 64 * 16, 0), a2all(kKinds * 64 * 16);
   std::vector<double> wall(kKinds * 16 * 64);
@@ -652,8 +656,8 @@ vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32
   DeviceGuard guard(b->device);
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
   int32_t bad = 0;
-  BHIP_TRY(b, hipMemcpy(&bad, b->err_flag, sizeof(bad), hipMemcpyDeviceToHost));
-  if (bad) return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
+  BHIP_TRY(b, hipMemcpy(&bad, b->err_flag + stream, sizeof(bad), hipMemcpyDeviceToHost));
+  if (bad) return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to this stream");
   const float* ring = b->rings + b->ring_off[stream];
   int64_t done = 0;
   while (done < count) {

@@ -257,7 +257,7 @@ constexpr int kSegCols = 128;   // block columns of a staged segment (w = 16, 8)
 // LDS bytes of one wavefront's staging area (FP64 H, then int32 DC).
 constexpr int stage_bytes(int w) { return w == 32 ? 0 : (kTile / w) * kSegCols * 12; }
 
-template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false>
+template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false, bool kValidate = false>
 __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
                                            const PackConsts<kW, kK>& pc, int run0, int run_stride,
                                            int end, int lane, uint8_t* stage) {
@@ -298,6 +298,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   double hrun = 0.0;
   int dcrun = 0;
   int run_out0 = S.out0;
+  uint32_t seen = 0;   // kValidate: OR of every sample walked
   double* st_h = reinterpret_cast<double*>(stage);            // [kBpt][kSegCols]
   int* st_dc = reinterpret_cast<int*>(st_h + kBpt * kSegCols);  // [kBpt][kSegCols]
 
@@ -343,7 +344,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
       const int v = u + kDepth;   // the unit whose loads go out now
       ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
       v16i dh, dl;
-      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, c1))),
+      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, c1, seen))),
             c2, dh, dl);
       finish(u, dh, dl);
     }
@@ -402,6 +403,8 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     S = S2;
     O = O2;
   }
+  // kValidate: one test per call, a flagged sample of any strip sets the error
+  if (kValidate && out.validate && (seen & kOver10Bits)) *out.err_flag = 1;
 }
 
 }  // namespace vca

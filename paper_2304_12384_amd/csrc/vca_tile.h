@@ -237,7 +237,7 @@ __device__ __forceinline__ v16i stage1_bias() {
 // so the T >> 8 byte of the split still fits int8, and DC needs no
 // correction.  A pair of samples x0 | x1 << 16 gives t0 and t1 in bytes 0 and
 // 2 of ((pair + 0x00800080) >> 8).
-__device__ __forceinline__ void operands10(const TileOut& o, const TileData& d, v4i& hi, v4i& lo) {
+__device__ __forceinline__ void operands10(const TileData& d, v4i& hi, v4i& lo) {
   uint32_t tv[8];
 #pragma unroll
   for (int q = 0; q < 4; q++) {
@@ -250,13 +250,20 @@ __device__ __forceinline__ void operands10(const TileOut& o, const TileData& d, 
   lo[3] = (int)perm_b32((uint32_t)d.b[3], (uint32_t)d.b[2], 0x06040200u);
 #pragma unroll
   for (int q = 0; q < 4; q++) hi[q] = (int)perm_b32(tv[2 * q + 1], tv[2 * q], 0x06040200u);
-  if (o.validate) {
-    uint32_t any = 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) any |= (uint32_t)d.a[q] | (uint32_t)d.b[q];
-    if (any & 0xFC00FC00u) *o.err_flag = 1;
-  }
 }
+
+// 10-bit validation: the OR of a lane's samples; a bit in 0xFC00FC00 marks a
+// sample above 1023.  Callers accumulate it and test it once per strip run
+// (a conditional store per unit split the unit loop into branches and
+// doubled the register allocation of the w = 32 kernels).
+__device__ __forceinline__ uint32_t samples_or(const TileData& d) {
+  uint32_t any = 0;
+#pragma unroll
+  for (int q = 0; q < 4; q++) any |= (uint32_t)d.a[q] | (uint32_t)d.b[q];
+  return any;
+}
+
+constexpr uint32_t kOver10Bits = 0xFC00FC00u;
 
 // Horizontal-pass accumulators of one unit: 8-bit needs lo only; 10-bit
 // keeps the products of the high (t) and low bytes apart until the split,
@@ -271,7 +278,8 @@ struct Acc1 {
 // plain tile).  c1 holds the rounding 2^(s1-1) in every element.
 template <int kBits, int kW, int kPack>
 __device__ __forceinline__ Acc1 stage1_acc(const TileOut& o, const v4i (&b1)[kPack],
-                                           const TileData (&d)[kPack], const v16i& c1) {
+                                           const TileData (&d)[kPack], const v16i& c1,
+                                           uint32_t& seen) {
   Acc1 r;
   r.lo = c1;
   if (kBits == 8) {
@@ -283,7 +291,8 @@ __device__ __forceinline__ Acc1 stage1_acc(const TileOut& o, const v4i (&b1)[kPa
 #pragma unroll
     for (int p = 0; p < kPack; p++) {
       v4i hi, lo;
-      operands10(o, d[p], hi, lo);
+      operands10(d[p], hi, lo);
+      seen |= samples_or(d[p]);
       r.hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], r.hi, 0, 0, 0);
       r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], r.lo, 0, 0, 0);
     }
@@ -304,7 +313,8 @@ __device__ __forceinline__ v16i stage1_sum(const Acc1& a) {
 template <int kBits, int kW, int kPack>
 __device__ __forceinline__ v16i stage1(const TileOut& o, const v4i (&b1)[kPack],
                                        const TileData (&d)[kPack]) {
-  return stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(o, b1, d, stage1_bias<ilog2c(kW) + kBits - 9>()));
+  uint32_t seen = 0;   // validated by the caller
+  return stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(o, b1, d, stage1_bias<ilog2c(kW) + kBits - 9>(), seen));
 }
 
 // Split of the horizontal-pass result and the vertical pass.  Exact split of
@@ -379,6 +389,7 @@ __device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, con
   constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;   // 8-bit samples are offset by -128
   const int g = lane >> 5, r = lane & 31;
   v16i dh, dl;
+  if (kBits != 8 && o.validate && (samples_or(d) & kOver10Bits)) *o.err_flag = 1;
   tile_transform<kBits, kW>(o, tc, d, dh, dl);
 
   // FP64 energy per block row (two partial sums when the tile is one block).

@@ -138,3 +138,29 @@ def test_plain_tune(vca, frames):
     f = an.features(0, d["n"])
     an.close()
     assert f.tobytes() == plain_features(vca, d, frames[5], 1).tobytes()
+
+
+def test_batch_10bit_validation(vca):
+    """A validating 10-bit stream in a batch: a sample above 1023 inside its
+    block grid fails that stream's features only."""
+    from paper_2304_12384_amd import VcaError
+    print_case(test="batch_10bit_validation")
+    rng = np.random.default_rng(21)
+    def planes(w, h, bits, n):
+        top = (1 << bits) - 1
+        dt = np.uint8 if bits == 8 else np.uint16
+        ps = [rng.integers(0, top + 1, (n, hh, ww)).astype(dt) for hh, ww in ((h, w), (h // 2, w // 2),
+                                                                            (h // 2, w // 2))]
+        return ps
+    p10 = planes(256, 128, 10, 2)
+    p8 = planes(320, 192, 8, 2)
+    p10[0][1, 64, 100] = 1024
+    dev10 = [torch.from_numpy(a.view(np.int16)).cuda() for a in p10]
+    dev8 = [torch.from_numpy(a).cuda() for a in p8]
+    b = vca.Batch([dict(width=256, height=128, bit_depth=10, block_size=16, validate=True),
+                   dict(width=320, height=192, block_size=32)])
+    b.submit([tuple(dev10), tuple(dev8)])
+    assert b.features(1, 0, 2).shape == (2, 7)
+    with pytest.raises(VcaError):
+        b.features(0, 0, 2)
+    b.close()

@@ -146,21 +146,28 @@ def test_10bit_scene_features(vca):
     assert_features_close(f, ref)
 
 
-def test_10bit_validation(vca):
+@pytest.mark.parametrize("w,k", [(32, 0), (32, 16), (16, 0), (16, 4), (8, 0), (8, 2)])
+@pytest.mark.parametrize("plane,pos", [(0, (40, 40)), (0, (100, 180)), (1, (10, 70))])
+def test_10bit_validation(vca, w, k, plane, pos):
+    """VCA_F_VALIDATE: a sample above 1023 inside a block walked by the
+    kernel (a strip's first or last tile, luma or chroma) fails the call's
+    features; outside the block grid it is ignored."""
     from paper_2304_12384_amd import VcaError
-    print_case(test="10bit_validation")
+    print_case(test="10bit_validation", w=w, k=k, plane=plane, pos=pos)
     rng = np.random.default_rng(9)
-    width, height = 208, 136            # w=32: luma grid 192 x 128, margins outside
+    width, height = 208, 140            # luma grids: 136 rows at w = 8, 128 at w = 16, 32
     y = rng.integers(0, 1024, size=(2, height, width)).astype(np.uint16)
     u = rng.integers(0, 1024, size=(2, height // 2, width // 2)).astype(np.uint16)
-    y[1, 130, 200] = 4000               # outside the block grid: ignored
+    y[1, 138, 100] = 4000               # below every block grid: ignored
     dev = [torch.from_numpy(a.view(np.int16)).cuda() for a in (y, u, u.copy())]
-    an = vca.Analyzer(width, height, bit_depth=10, block_size=32, validate=True)
+    an = vca.Analyzer(width, height, bit_depth=10, block_size=w, lowpass_k=k, validate=True)
     an.submit(*dev)
     assert an.features(0, 2).shape == (2, 7)
-    y[1, 40, 40] = 1024                 # inside a block: rejected
-    dev[0] = torch.from_numpy(y.view(np.int16)).cuda()
-    an.submit(*dev)
+    bad = [y, u][plane].copy()
+    bad[1, pos[0], pos[1]] = 1024       # inside a block: rejected
+    planes = [y, u, u.copy()]
+    planes[plane] = bad
+    an.submit(*[torch.from_numpy(a.view(np.int16)).cuda() for a in planes])
     with pytest.raises(VcaError):
         an.features(2, 2)
     an.close()
