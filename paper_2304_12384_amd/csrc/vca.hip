@@ -236,9 +236,11 @@ struct vca_ctx {
   double* blk_h = nullptr;
   int32_t* blk_dc = nullptr;
   int16_t* coeffs = nullptr;
-  int32_t* err_flag = nullptr;
+  int32_t* err_flag = nullptr;     // device view of err_host
+  int32_t* err_host = nullptr;     // pinned, mapped
   double* state[2] = {nullptr, nullptr};
-  float* ring = nullptr;
+  float* ring = nullptr;           // device view of ring_host
+  float* ring_host = nullptr;      // pinned, mapped: [feature_capacity][7]
   int cur_state = 0;
   bool has_prev = false;
   bool last_chunk_prev = false;    // the last launch's first frame had a previous frame
@@ -395,9 +397,11 @@ void vca_close(vca_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     void* bufs[] = {ctx->tab_b1,   ctx->tab_a2,   ctx->tab_w,    ctx->tab_b1p,
                     ctx->tab_wp,   ctx->blk_h,    ctx->blk_dc,   ctx->coeffs,
-                    ctx->err_flag, ctx->state[0], ctx->state[1], ctx->ring};
+                    ctx->state[0], ctx->state[1]};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
+    if (ctx->ring_host) (void)hipHostFree(ctx->ring_host);
+    if (ctx->err_host) (void)hipHostFree(ctx->err_host);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
     for (auto& sl : ctx->ing) {
@@ -461,9 +465,12 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   if ((s = dev_alloc(c, &c->blk_dc, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->state[0], c->geo.cnt[0])) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->state[1], c->geo.cnt[0])) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->ring, (size_t)c->cfg.feature_capacity * 7)) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->err_flag, 1)) != VCA_OK) return bail(s);
-  if (hipMemset(c->err_flag, 0, sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
+  if (host_mapped_alloc((size_t)c->cfg.feature_capacity * 7 * sizeof(float),
+                        reinterpret_cast<void**>(&c->ring_host),
+                        reinterpret_cast<void**>(&c->ring)) != hipSuccess ||
+      host_mapped_alloc(sizeof(int32_t), reinterpret_cast<void**>(&c->err_host),
+                        reinterpret_cast<void**>(&c->err_flag)) != hipSuccess)
+    return bail(VCA_ERR_OOM);
   if (cfg->flags & VCA_F_KEEP_COEFFS)
     if ((s = dev_alloc(c, &c->coeffs, mb * c->geo.per_frame * K * K)) != VCA_OK) return bail(s);
 
@@ -792,17 +799,15 @@ vca_status vca_features(vca_ctx* ctx, int64_t first, int32_t count, vca_frame_fe
   if (first < ctx->submitted - cap) return fail(ctx, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(ctx->device);
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  if (ctx->cfg.flags & VCA_F_VALIDATE) {
-    int32_t bad = 0;
-    HIP_TRY(ctx, hipMemcpy(&bad, ctx->err_flag, sizeof(bad), hipMemcpyDeviceToHost));
-    if (bad) return fail(ctx, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
-  }
+  // the ring and the flag are host memory the kernels wrote before the stream drained
+  if ((ctx->cfg.flags & VCA_F_VALIDATE) && *static_cast<volatile int32_t*>(ctx->err_host))
+    return fail(ctx, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
   int64_t done = 0;
   while (done < count) {
     const int64_t slot = (first + done) % cap;
     const int64_t n = std::min<int64_t>(count - done, cap - slot);
-    HIP_TRY(ctx, hipMemcpy(reinterpret_cast<float*>(out) + done * 7, ctx->ring + slot * 7,
-                           (size_t)n * 7 * sizeof(float), hipMemcpyDeviceToHost));
+    std::memcpy(reinterpret_cast<float*>(out) + done * 7, ctx->ring_host + slot * 7,
+                (size_t)n * 7 * sizeof(float));
     done += n;
   }
   return VCA_OK;

@@ -198,9 +198,11 @@ struct vca_batch {
   std::vector<int64_t> blk_base;   // per stream, into blk_h / blk_dc
   double* state = nullptr;
   std::vector<int64_t> state_off;  // per stream: two buffers of C_Y doubles
-  float* rings = nullptr;
+  float* rings = nullptr;          // device view of rings_host
+  float* rings_host = nullptr;     // pinned, mapped
   std::vector<int64_t> ring_off;   // per stream, in floats
-  int32_t* err_flag = nullptr;
+  int32_t* err_flag = nullptr;     // device view of err_host
+  int32_t* err_host = nullptr;     // pinned, mapped: [n_streams]
   std::vector<int> cur_state;
   std::vector<char> has_prev;
   std::vector<int64_t> submitted;
@@ -404,10 +406,12 @@ void vca_close_batch(vca_batch* b) {
     DeviceGuard g(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    void* bufs[] = {b->tab_b1p, b->tab_a2, b->tab_wp,   b->blk_h,     b->blk_dc,
-                    b->state,  b->rings,  b->err_flag, b->d_streams, b->d_red};
+    void* bufs[] = {b->tab_b1p, b->tab_a2, b->tab_wp,     b->blk_h,
+                    b->blk_dc,  b->state,  b->d_streams, b->d_red};
     for (void* p : bufs)
       if (p) (void)hipFree(p);
+    if (b->rings_host) (void)hipHostFree(b->rings_host);
+    if (b->err_host) (void)hipHostFree(b->err_host);
     if (b->h_streams) (void)hipHostFree(b->h_streams);
     if (b->h_red) (void)hipHostFree(b->h_red);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
@@ -488,15 +492,17 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   if ((s = balloc(b, &b->blk_h, (size_t)blk)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->blk_dc, (size_t)blk)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->state, (size_t)st_total)) != VCA_OK) return bail(s);
-  if ((s = balloc(b, &b->rings, (size_t)ring_total)) != VCA_OK) return bail(s);
-  if ((s = balloc(b, &b->err_flag, (size_t)n_streams)) != VCA_OK) return bail(s);
+  if (host_mapped_alloc((size_t)ring_total * sizeof(float), reinterpret_cast<void**>(&b->rings_host),
+                        reinterpret_cast<void**>(&b->rings)) != hipSuccess ||
+      host_mapped_alloc((size_t)n_streams * sizeof(int32_t), reinterpret_cast<void**>(&b->err_host),
+                        reinterpret_cast<void**>(&b->err_flag)) != hipSuccess)
+    return bail(VCA_ERR_OOM);
   if ((s = balloc(b, &b->d_streams, n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->d_red, n_streams)) != VCA_OK) return bail(s);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_streams), sizeof(StreamDesc) * n_streams, 0) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(ReduceParams) * n_streams, 0) != hipSuccess)
     return bail(VCA_ERR_OOM);
-  if (hipMemset(b->err_flag, 0, sizeof(int32_t) * (size_t)n_streams) != hipSuccess)
-    return bail(VCA_ERR_DEVICE);
+
   // operand and weight tables of every kind (packed layout)
   std::vector<int8_t> b1all((size_t)kKinds * kMaxPack * 64 * 16, 0), a2all(kKinds * 64 * 16);
   std::vector<double> wall(kKinds * 16 * 64);
@@ -655,16 +661,15 @@ vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32
   if (first < b->submitted[stream] - cap) return bfail(b, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(b->device);
   BHIP_TRY(b, hipStreamSynchronize(b->stream));
-  int32_t bad = 0;
-  BHIP_TRY(b, hipMemcpy(&bad, b->err_flag + stream, sizeof(bad), hipMemcpyDeviceToHost));
-  if (bad) return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to this stream");
-  const float* ring = b->rings + b->ring_off[stream];
+  // the rings and flags are host memory the kernels wrote before the stream drained
+  if (static_cast<volatile int32_t*>(b->err_host)[stream])
+    return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to this stream");
+  const float* ring = b->rings_host + b->ring_off[stream];
   int64_t done = 0;
   while (done < count) {
     const int64_t slot = (first + done) % cap;
     const int64_t n = std::min<int64_t>(count - done, cap - slot);
-    BHIP_TRY(b, hipMemcpy(reinterpret_cast<float*>(out) + done * 7, ring + slot * 7,
-                          (size_t)n * 7 * sizeof(float), hipMemcpyDeviceToHost));
+    std::memcpy(reinterpret_cast<float*>(out) + done * 7, ring + slot * 7, (size_t)n * 7 * sizeof(float));
     done += n;
   }
   return VCA_OK;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -121,6 +122,17 @@ inline const char* check_host_frames(const vca_config& cfg, const vca_frames* fr
                        fr->fstride_uv < fr->pitch_uv * (cfg.height / 2)))
     return "frame stride smaller than a frame";
   return nullptr;
+}
+
+// Pinned host memory the device reads and writes directly (fine-grained,
+// mapped), zeroed: the feature rings and error flags live there, so reading
+// features after a stream synchronisation is a host memcpy, not a device
+// copy per call.  Freed with hipHostFree(*host).
+inline hipError_t host_mapped_alloc(size_t bytes, void** host, void** dev) {
+  hipError_t e = hipHostMalloc(host, bytes ? bytes : 1, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  std::memset(*host, 0, bytes ? bytes : 1);
+  return hipHostGetDevicePointer(dev, *host, 0);
 }
 
 // Launch parameters chosen by the autotuner (depth 0 = not tuned).
