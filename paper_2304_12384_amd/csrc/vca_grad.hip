@@ -215,10 +215,18 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
     a2[h] = ld8(p.tab->a2[h], lane);
   }
   const int total = p.n_frames * p.tiles_per_frame;
-  for (int id = blockIdx.x * kGWaves + wave; id < total; id += gridDim.x * kGWaves) {
-    const FTile<kW> t = decode_ftile<kW>(p, id);
-    float x[16];
-    load_ftile<kW>(p, t, lane, x);
+  const int stride = gridDim.x * kGWaves;
+  int id = blockIdx.x * kGWaves + wave;
+  if (id >= total) return;
+  // the next tile's samples are loaded while this one is transformed (the
+  // last tile loads itself again, so every iteration issues the same loads)
+  FTile<kW> t = decode_ftile<kW>(p, id);
+  float x[16];
+  load_ftile<kW>(p, t, lane, x);
+  for (; id < total; id += stride) {
+    const FTile<kW> tn = decode_ftile<kW>(p, min(id + stride, total - 1));
+    float xn[16];
+    load_ftile<kW>(p, tn, lane, xn);
     const v16f y = tile_y(b1, a2, x);
     double h[kBpt];
 #pragma unroll
@@ -242,6 +250,9 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
       for (int b = 0; b < kBpt; b++)
         if (b < t.vr) p.blk_h[t.out0 + b * p.nbx + r / kW] = h[b];
     }
+    t = tn;
+#pragma unroll
+    for (int i = 0; i < 16; i++) x[i] = xn[i];
   }
 }
 
@@ -292,9 +303,37 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
 #pragma unroll
   for (int h = 0; h < 2; h++) ct[h] = ld8(p.tab->ct[h], lane);
   const int total = p.n_frames * p.tiles_per_frame;
-  for (int id = blockIdx.x * kGWaves + wave; id < total; id += gridDim.x * kGWaves) {
-    const FTile<kW> t = decode_ftile<kW>(p, id);
-    const uint32_t mask = p.masks[(int64_t)id * 64 + lane];
+  const int stride = gridDim.x * kGWaves;
+  // a tile's inputs: its sign masks and, per block column of the lane's
+  // block row, H of the block in this, the previous and the next frame
+  // (the block's own index where a neighbour frame is not used)
+  struct In {
+    FTile<kW> t;
+    uint32_t mask;
+    double hc[kBpt], hp[kBpt], hn[kBpt];
+  };
+  auto fetch = [&](int tid) {
+    In in;
+    in.t = decode_ftile<kW>(p, tid);
+    in.mask = p.masks[(int64_t)tid * 64 + lane];
+    const int f = in.t.f, pos = f % p.seq_len;
+    const int br = min(r / kW, in.t.vr - 1);
+#pragma unroll
+    for (int b = 0; b < kBpt; b++) {
+      const int idx = in.t.out0 + br * p.nbx + min(b, in.t.vc - 1);
+      in.hc[b] = p.blk_h[idx];
+      in.hp[b] = p.blk_h[pos > 0 ? idx - p.per_frame : idx];
+      in.hn[b] = p.blk_h[pos + 1 < p.seq_len ? idx + p.per_frame : idx];
+    }
+    return in;
+  };
+  int id = blockIdx.x * kGWaves + wave;
+  if (id >= total) return;
+  In cur = fetch(id);   // the next tile's inputs are loaded while this one is transformed
+  for (; id < total; id += stride) {
+    const In nxt = fetch(min(id + stride, total - 1));
+    const FTile<kW> t = cur.t;
+    const uint32_t mask = cur.mask;
     // S = W o sign(Y): lane (c + 32 g) register j is coefficient (m_j, c);
     // as S^T's A operand, slot s of MFMA h is register 8 h + s
     v16f u = {};
@@ -338,15 +377,12 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
     const float gE = p.gE[f];
     const float ghf = has_prev ? p.gh[f] : 0.f;
     const float ghn = has_next ? p.gh[f + 1] : 0.f;
-    const int br = min(r / kW, t.vr - 1);
     float cb[kBpt];
 #pragma unroll
     for (int b = 0; b < kBpt; b++) {
-      const int idx = t.out0 + br * p.nbx + min(b, t.vc - 1);
-      const double hc = p.blk_h[idx];
       float c = gE;
-      if (has_prev) c += ghf * sgn(hc - p.blk_h[idx - p.per_frame]);
-      if (has_next) c -= ghn * sgn(p.blk_h[idx + p.per_frame] - hc);
+      if (has_prev) c += ghf * sgn(cur.hc[b] - cur.hp[b]);
+      if (has_next) c -= ghn * sgn(cur.hn[b] - cur.hc[b]);
       cb[b] = c * p.grad_scale;
     }
     // pixel (r, m_j): registers 4q..4q+3 are columns 8q + 4g + 0..3
@@ -363,6 +399,7 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
         }
       }
     }
+    cur = nxt;
   }
 }
 
@@ -544,17 +581,36 @@ vca_status prepare(const vca_grad_config* c, void* workspace, GradParams& p) {
   return get_tables(c, K, &p.tab);
 }
 
+// Workgroups of `kern` that fit on device `dev` at once: CUs x resident
+// groups per CU, computed once per (kernel, device) -- the queries cost more
+// host time than these short launches themselves.
+hipError_t occupancy_slots(GradKernel kern, int dev, int* slots) {
+  static std::mutex m;
+  static std::map<std::pair<const void*, int>, int> cache;
+  std::lock_guard<std::mutex> lock(m);
+  const auto key = std::make_pair(reinterpret_cast<const void*>(kern), dev);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int resident = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGThreads, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    it = cache.emplace(key, cus * std::max(1, resident)).first;
+  }
+  *slots = it->second;
+  return hipSuccess;
+}
+
 vca_status launch_grad(const vca_grad_config* c, const GradParams& p, bool bwd, hipStream_t st) {
   const int w = c->block_size, K = c->lowpass_k == 0 ? w : c->lowpass_k;
   GradKernel kern = select_grad(w, K, bwd);
   if (!kern) return VCA_ERR_UNSUPPORTED;
-  int resident = 0, dev = 0;
-  hipDeviceProp_t prop;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGThreads, 0) != hipSuccess ||
-      hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
-    return VCA_ERR_DEVICE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return VCA_ERR_DEVICE;
+  int slots = 0;   // resident workgroups on the whole device (cached per kernel and device)
+  if (occupancy_slots(kern, dev, &slots) != hipSuccess) return VCA_ERR_DEVICE;
   const int64_t groups = ((int64_t)p.n_frames * p.tiles_per_frame + kGWaves - 1) / kGWaves;
-  const int grid = (int)std::min<int64_t>(groups, (int64_t)prop.multiProcessorCount * std::max(1, resident));
+  const int grid = (int)std::min<int64_t>(groups, (int64_t)slots);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kGThreads), 0, st, p);
   return hipGetLastError() == hipSuccess ? VCA_OK : VCA_ERR_DEVICE;
 }
