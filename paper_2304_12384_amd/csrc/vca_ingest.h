@@ -8,6 +8,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <cerrno>
 #include <atomic>
 #include <condition_variable>
 #include <cstdint>
@@ -139,6 +140,7 @@ inline bool pread_rows(int fd, int64_t off, uint8_t* dst, int64_t dp, int64_t ro
   auto read_all = [&](uint8_t* p, int64_t n, int64_t at) {
     while (n > 0) {
       const ssize_t got = ::pread(fd, p, (size_t)n, (off_t)at);
+      if (got < 0 && errno == EINTR) continue;
       if (got <= 0) return false;
       p += got;
       n -= got;
