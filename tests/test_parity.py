@@ -175,3 +175,42 @@ def test_argument_errors(vca, patches):
     with pytest.raises(VcaError):                 # not opened with keep_coeffs
         an.block_coeffs(0)
     an.close()
+
+
+@pytest.mark.parametrize("w,k", [(32, 0), (16, 8), (8, 0)])
+def test_8k_frames_strip_path(vca, w, k):
+    """7680x4320 (the largest common frame size; 32 strips per luma tile
+    row): every block's DC exact and H to 1e-12 through the production strip
+    kernels, features to 1e-5."""
+    print_case(test="8k", w=w, k=k)
+    rng = np.random.default_rng(8000 + w + k)
+    width, height, n = 7680, 4320, 2
+    y = rng.integers(0, 256, size=(n, height, width), dtype=np.uint8)
+    u = rng.integers(0, 256, size=(n, height // 2, width // 2), dtype=np.uint8)
+    v = rng.integers(0, 256, size=(n, height // 2, width // 2), dtype=np.uint8)
+    video = synth.Video(y, u, v, 8)
+    an = vca.Analyzer(width, height, block_size=w, lowpass_k=k)
+    an.submit(*to_device(video))
+    f = an.features(0, n)
+    maps = an.block_maps(0, n)
+    torch.cuda.synchronize()
+    an.close()
+    ref = oracle_run(video, k=k, w=w)
+    assert (maps["dc"].cpu().numpy() == ref.block_dc).all()
+    np.testing.assert_allclose(maps["h"].cpu().numpy(), ref.block_h, rtol=1e-12, atol=0)
+    assert_features_close(f, ref.features)
+
+
+def test_empty_submission_is_a_no_op(vca, patches):
+    print_case(test="empty_submission")
+    an = vca.Analyzer(patches.width, patches.height)
+    y, u, v = to_device(patches)
+    assert an.submit(y[:0], u[:0], v[:0]) == 0
+    assert an.submitted == 0
+    an.submit(y, u, v)
+    f = an.features(0, 10)
+    assert an.submit_host(patches.y[:0], patches.u[:0], patches.v[:0]) == 10
+    assert an.submitted == 10
+    an.close()
+    ref, _, _ = run_gpu(vca, patches)
+    assert f.tobytes() == ref.tobytes()
