@@ -344,7 +344,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
       const int v = u + kDepth;   // the unit whose loads go out now
       ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
       v16i dh, dl;
-      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(out, pc.b1, d.t, c1, seen))),
+      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(pc.b1, d.t, c1, seen))),
             c2, dh, dl);
       finish(u, dh, dl);
     }

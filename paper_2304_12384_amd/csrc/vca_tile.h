@@ -10,8 +10,10 @@
 //     m_j = 8 (j/4) + 4 g + j%4) is already the B-operand layout of the
 //     vertical pass once its 16-bit values are split into int8 bytes;
 //   * vertical pass Y = Cd T on two int8 MFMAs (hi and lo bytes of T);
-//   * per lane, FP64 sums of W |Y| per block row; a butterfly over the
-//     lanes of a block column gives the block energy H; DC is read in place.
+//   * per lane, FP64 sums of W |Y| per block row, reduced over the lanes of
+//     a block (a shuffle butterfly in the one-tile kernel, permlane swaps
+//     and DPP in the strip kernels) to the block energy H; DC is read in
+//     place.
 // Transform definition (Section 2 of the paper names the block-DCT features;
 // the integer transform is the H.265 core transform): per block
 //   T = floor((X C^T + 2^(s1-1)) / 2^s1),  s1 = log2 w + B - 9
@@ -214,15 +216,7 @@ struct TileOut {
   int32_t validate;
 };
 
-// Both passes of one tile.  Exact split of the horizontal-pass result T
-// (-2^14 <= T < 2^15 for every w and B):
-//   T = 256 T_hi + u,  T_hi = T >> 8 in [-64, 127],  u = T & 255,
-// C T = 256 C T_hi + C (u - 128) + 128 C 1, the last term being 128 * 64 w
-// on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
-// scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
-// accumulator as 2^(s2-9); both accumulator biases are MFMA inline constants.
-// Returns the hi and lo accumulators: Y = (256 dh + dl) >> s2 (+128 on each
-// block's row 0).
+// Rounding of the horizontal pass, 2^(s1-1), as the initial accumulator.
 template <int kS1>
 __device__ __forceinline__ v16i stage1_bias() {
   v16i c1;
@@ -277,7 +271,7 @@ struct Acc1 {
 // B operand b1[p] puts its coefficients in its own lanes (kPack = 1: the
 // plain tile).  c1 holds the rounding 2^(s1-1) in every element.
 template <int kBits, int kW, int kPack>
-__device__ __forceinline__ Acc1 stage1_acc(const TileOut& o, const v4i (&b1)[kPack],
+__device__ __forceinline__ Acc1 stage1_acc(const v4i (&b1)[kPack],
                                            const TileData (&d)[kPack], const v16i& c1,
                                            uint32_t& seen) {
   Acc1 r;
@@ -311,10 +305,10 @@ __device__ __forceinline__ v16i stage1_sum(const Acc1& a) {
 }
 
 template <int kBits, int kW, int kPack>
-__device__ __forceinline__ v16i stage1(const TileOut& o, const v4i (&b1)[kPack],
+__device__ __forceinline__ v16i stage1(const v4i (&b1)[kPack],
                                        const TileData (&d)[kPack]) {
   uint32_t seen = 0;   // validated by the caller
-  return stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(o, b1, d, stage1_bias<ilog2c(kW) + kBits - 9>(), seen));
+  return stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(b1, d, stage1_bias<ilog2c(kW) + kBits - 9>(), seen));
 }
 
 // Split of the horizontal-pass result and the vertical pass.  Exact split of
@@ -371,11 +365,11 @@ __device__ __forceinline__ void stage2(const v4i& a2, const v16i& d1, v16i& dh, 
 
 // Both passes of one tile.
 template <int kBits, int kW, class Consts>
-__device__ __forceinline__ void tile_transform(const TileOut& o, const Consts& tc, const TileData& d,
+__device__ __forceinline__ void tile_transform(const Consts& tc, const TileData& d,
                                                v16i& dh, v16i& dl) {
   const v4i b1[1] = {tc.b1};
   const TileData dd[1] = {d};
-  stage2<kBits, kW>(tc.a2, stage1<kBits, kW, 1>(o, b1, dd), dh, dl);
+  stage2<kBits, kW>(tc.a2, stage1<kBits, kW, 1>(b1, dd), dh, dl);
 }
 
 // Transform, energies and DC of one tile, reduced and stored per block.
@@ -390,7 +384,7 @@ __device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, con
   const int g = lane >> 5, r = lane & 31;
   v16i dh, dl;
   if (kBits != 8 && o.validate && (samples_or(d) & kOver10Bits)) *o.err_flag = 1;
-  tile_transform<kBits, kW>(o, tc, d, dh, dl);
+  tile_transform<kBits, kW>(tc, d, dh, dl);
 
   // FP64 energy per block row (two partial sums when the tile is one block).
   constexpr int kAcc = kBpt == 1 ? 2 : kBpt;
@@ -454,33 +448,7 @@ __device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, con
 
 // ------------------------------------------------------- w = 32 strips
 // A 32 x 32 tile is one block: its energy is a sum over all 64 lanes.  The
-// functions below leave each lane's FP64 share, and reduce the shares of
-// eight tiles at once.
-
-// Lane share of the block energy of one w = 32 tile; the block's DC (without
-// the 8-bit offset) is returned in dc of lane 0.
-template <int kBits, int kK, class Consts>
-__device__ __forceinline__ double tile_energy32(const TileOut& o, const Consts& tc,
-                                                const TileData& d, int& dc) {
-  constexpr int kS2 = ilog2c(32) + 6;
-  v16i dh, dl;
-  tile_transform<kBits, 32>(o, tc, d, dh, dl);
-  double h0 = 0.0, h1 = 0.0;
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    if (!reg_used(j, 32, kK)) continue;
-    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
-    if (j == 0) {
-      yv += tc.row0_fix;   // row 0 lives in register 0 of lanes g = 0
-      dc = yv;
-    }
-    if (j & 1)
-      h1 = fma(tc.wt[j], fabs((double)yv), h1);
-    else
-      h0 = fma(tc.wt[j], fabs((double)yv), h0);
-  }
-  return h0 + h1;
-}
+// functions below reduce the lanes' FP64 shares of eight tiles at once.
 
 __device__ inline uint32_t lo32(double v) { return (uint32_t)__double_as_longlong(v); }
 __device__ inline uint32_t hi32(double v) { return (uint32_t)(__double_as_longlong(v) >> 32); }
