@@ -126,8 +126,8 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out);
 /* Enqueues the analysis of n_frames frames (n_frames >= 0) on the context's
  * stream and returns without waiting.  Frames are numbered after those of
  * earlier calls, and h chains across calls.  Device frames: the caller keeps
- * the buffers valid until the stream has finished the work (vca_features
- * waits).  Host frames (frames->on_device = 0): the library copies them,
+ * the buffers valid until the stream has finished the work (vca_features of
+ * the call's last frame waits for it).  Host frames (frames->on_device = 0): the library copies them,
  * batch by batch, into one of two pinned staging buffers (in parallel over
  * host threads) and from there to the device on a second stream, each
  * batch's copy overlapping the analysis of the one before; the caller may
@@ -153,8 +153,10 @@ vca_status vca_analyze_yuv_file(vca_ctx* ctx, const char* path, int64_t first_fr
 vca_status vca_read_yuv(const char* path, int32_t width, int32_t height, int32_t bit_depth,
                         int64_t first_frame, int32_t n_frames, void* y, void* u, void* v);
 
-/* Waits for the context's stream, then copies the features of frames
- * [first_frame, first_frame + count) into out_host (count records).
+/* Waits for the launch that produced frame first_frame + count - 1 (not for
+ * work queued after it, so the next call may already be enqueued), then
+ * copies the features of frames [first_frame, first_frame + count) into
+ * out_host (count records).
  * VCA_ERR_STATE if a frame was not yet submitted or has left the ring, or if
  * VCA_F_VALIDATE found an out-of-range sample. */
 vca_status vca_features(vca_ctx* ctx, int64_t first_frame, int32_t count,
@@ -245,10 +247,12 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
 /* Enqueues frames[s] (n_frames[s] >= 0 frames) for every stream s; returns
  * without waiting.  Streams whose count exceeds their max_batch are
  * processed in several rounds.  Frame buffers must stay valid until the
- * stream's work is done (vca_batch_features waits). */
+ * round that reads them is done (vca_batch_features of a stream's last
+ * submitted frame waits for it). */
 vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames);
 
-/* Features of frames [first, first + count) of stream `stream`; waits.
+/* Features of frames [first, first + count) of stream `stream`; waits for
+ * the round that produced frame first + count - 1 (not for later rounds).
  * VCA_ERR_STATE if that stream was opened with VCA_F_VALIDATE and a 10-bit
  * sample above 1023 was submitted to it (other streams are unaffected). */
 vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32_t count,

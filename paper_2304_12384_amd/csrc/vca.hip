@@ -247,6 +247,7 @@ struct vca_ctx {
   int64_t submitted = 0;
   int64_t last_chunk_first = -1;  // global index of frame 0 of the most recent launch
   int32_t last_chunk_len = 0;
+  DoneMarks done;                  // completion of the recent launches
   // VCA_F_TIMING: one (start, middle, end) event triple per launch pair
   std::vector<hipEvent_t> ev_pool;
   std::vector<int32_t> ev_frames;
@@ -403,6 +404,7 @@ void vca_close(vca_ctx* ctx) {
     if (ctx->ring_host) (void)hipHostFree(ctx->ring_host);
     if (ctx->err_host) (void)hipHostFree(ctx->err_host);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    ctx->done.destroy();
     if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
     for (auto& sl : ctx->ing) {
       if (sl.pinned) (void)hipHostFree(sl.pinned);
@@ -454,6 +456,7 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
       return bail(VCA_ERR_DEVICE);
     c->own_stream = true;
   }
+  if (c->done.init(1) != hipSuccess) return bail(VCA_ERR_DEVICE);
   const size_t mb = (size_t)c->cfg.max_batch;
   const int K = c->geo.K;
   if ((s = dev_alloc(c, &c->tab_b1, 64)) != VCA_OK) return bail(s);
@@ -553,6 +556,7 @@ vca_status analyze_device(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames) 
     ctx->last_chunk_first = ctx->submitted;
     ctx->last_chunk_len = n;
     ctx->submitted += n;
+    HIP_TRY(ctx, ctx->done.record(ctx->stream, &ctx->submitted));
     done += n;
   }
   return VCA_OK;
@@ -798,8 +802,10 @@ vca_status vca_features(vca_ctx* ctx, int64_t first, int32_t count, vca_frame_fe
   const int64_t cap = ctx->cfg.feature_capacity;
   if (first < ctx->submitted - cap) return fail(ctx, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(ctx->device);
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  // the ring and the flag are host memory the kernels wrote before the stream drained
+  HIP_TRY(ctx, ctx->done.wait(0, first + count, ctx->stream));
+  // the ring and the flag are host memory the kernels wrote before the launch
+  // that produced the last frame asked for completed (later launches may
+  // still run: they write other ring slots)
   if ((ctx->cfg.flags & VCA_F_VALIDATE) && *static_cast<volatile int32_t*>(ctx->err_host))
     return fail(ctx, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
   int64_t done = 0;

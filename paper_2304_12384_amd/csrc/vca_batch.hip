@@ -2,10 +2,12 @@
 //
 // Many independent video streams of different resolution, block size, bit
 // depth and frame count are analysed by ONE persistent launch: every
-// wavefront walks a flat list of chunks (runs of kChunkStrips consecutive
-// strips of one stream, vca_strip.h; a stream's chunks are contiguous),
-// copies the chunk's stream descriptor into registers, and runs the strip
-// loop specialised for the stream's (bit depth, w, K) class.  A second launch
+// wavefront takes chunks of a flat list (runs of kChunkStrips consecutive
+// strips of one stream, vca_strip.h; a stream's chunks are contiguous) from a
+// device-wide counter, so that waves that drew cheap chunks take more and
+// all finish together, copies the chunk's stream descriptor into registers,
+// and runs the strip loop specialised for the stream's (bit depth, w, K)
+// class.  A second launch
 // reduces every (stream, frame) pair to its seven features (vca_reduce.h).
 // Both launches are captured once into a hipGraph per frame-count signature
 // and replayed; per call only the descriptor tables (frame pointers, state
@@ -74,6 +76,7 @@ struct BatchParams {
   double* blk_h;
   int32_t* blk_dc;
   int32_t* err_flag;      // [n_streams]: a validated 10-bit sample above 1023
+  int32_t* queue;         // next chunk to hand out; zero at launch
 };
 
 struct BatchReduceParams {
@@ -81,18 +84,28 @@ struct BatchReduceParams {
   int32_t n_streams;
 };
 
-// All chunks of one class: wavefront gw of W takes chunks gw, gw + W, ... of
-// the class's range (its descriptors are contiguous, so the stream search
-// only moves forward), with the class's operand tables loaded once.
+// The next chunk of the launch for the calling wavefront (one atomic per
+// wavefront, result broadcast).  Chunks are handed out in increasing order.
+__device__ __forceinline__ int next_chunk(int32_t* queue, int lane) {
+  int c = 0;
+  if (lane == 0) c = __hip_atomic_fetch_add(queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_amdgcn_readfirstlane(c);
+}
+
+// The chunks of one class that the calling wavefront draws: c is its current
+// chunk on entry (at or after the class's first chunk) and its first chunk
+// past the class on return.  The class's descriptors are contiguous and c
+// only grows, so the stream search only moves forward; the class's operand
+// tables are loaded once.
 template <int kBits, int kW, int kK, int kDepth>
-__device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw, int W,
-                                         const TileOut& o0, int lane, uint8_t* stage) {
+__device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int& c, const TileOut& o0,
+                                         int lane, uint8_t* stage) {
   const KindRange kr = p.kinds[kind];
   PackConsts<kW, kK> pc;
   pc.load(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
   TileOut o = o0;
   int d = kr.desc_begin;
-  for (int c = kr.chunk_begin + gw; c < kr.chunk_end; c += W) {
+  for (; c < kr.chunk_end; c = next_chunk(p.queue, lane)) {
     while (d < kr.desc_end - 1 && c >= p.streams[d].chunk_end) d++;
     const StreamDesc& sd = p.streams[d];
     o.validate = sd.validate;
@@ -106,21 +119,24 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int gw,
 // The classes one after the other, each its own loop (a switch inside one
 // loop made the compiler allocate registers for several classes at once).
 template <int kDepth, int kBits, int kW, int kK>
-__device__ __forceinline__ void run_kind_if(const BatchParams& p, int kind, int gw, int W,
+__device__ __forceinline__ void run_kind_if(const BatchParams& p, int kind, int& c,
                                             const TileOut& o, int lane, uint8_t* stage) {
-  if (p.kinds[kind].chunk_begin < p.kinds[kind].chunk_end)
-    run_kind<kBits, kW, kK, kDepth>(p, kind, gw, W, o, lane, stage);
+  if (c < p.kinds[kind].chunk_end)
+    run_kind<kBits, kW, kK, kDepth>(p, kind, c, o, lane, stage);
 }
 
-// Persistent batched kernel: every wavefront walks the classes present in
-// the launch in order and, within each, its share of the class's chunks.
+// Persistent batched kernel: every wavefront draws chunks until the list is
+// exhausted, walking the classes in the list's order.
 // kOnly8: every stream of the launch is 8-bit (the 10-bit classes are left
-// out, which lowers the kernel's register allocation).
+// out, which lowers the kernel's register allocation).  The register budget
+// is held at three wavefronts per SIMD for the 8-bit kernel and two for the
+// one that serves both bit depths (which then keeps a few values in scratch
+// rather than drop to one wavefront per SIMD).
 template <int kDepth, bool kOnly8>
-__global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kOnly8 ? 3 : 2)))
+void batch_fwd_kernel(BatchParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int gw = blockIdx.x * kWaves + wave, W = gridDim.x * kWaves;
   TileOut o;
   o.blk_h = p.blk_h;
   o.blk_dc = p.blk_dc;
@@ -130,26 +146,33 @@ __global__ __launch_bounds__(kThreads) void batch_fwd_kernel(BatchParams p) {
   // output staging of the w = 16 and 8 classes (the largest is w = 8's)
   __shared__ __attribute__((aligned(16))) uint8_t stage_mem[kWaves][stage_bytes(8)];
   uint8_t* stage = stage_mem[wave];
-  run_kind_if<kDepth, 8, 32, 32>(p, 0, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 32, 16>(p, 1, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 32, 8>(p, 2, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 16, 16>(p, 3, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 16, 8>(p, 4, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 16, 4>(p, 5, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 8, 8>(p, 6, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 8, 4>(p, 7, gw, W, o, lane, stage);
-  run_kind_if<kDepth, 8, 8, 2>(p, 8, gw, W, o, lane, stage);
+  int c = next_chunk(p.queue, lane);
+  run_kind_if<kDepth, 8, 32, 32>(p, 0, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 32, 16>(p, 1, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 32, 8>(p, 2, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 16, 16>(p, 3, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 16, 8>(p, 4, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 16, 4>(p, 5, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 8, 8>(p, 6, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 8, 4>(p, 7, c, o, lane, stage);
+  run_kind_if<kDepth, 8, 8, 2>(p, 8, c, o, lane, stage);
   if constexpr (!kOnly8) {
-    run_kind_if<kDepth, 10, 32, 32>(p, 9, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 32, 16>(p, 10, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 32, 8>(p, 11, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 16, 16>(p, 12, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 16, 8>(p, 13, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 16, 4>(p, 14, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 8, 8>(p, 15, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 8, 4>(p, 16, gw, W, o, lane, stage);
-    run_kind_if<kDepth, 10, 8, 2>(p, 17, gw, W, o, lane, stage);
+    run_kind_if<kDepth, 10, 32, 32>(p, 9, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 32, 16>(p, 10, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 32, 8>(p, 11, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 16, 16>(p, 12, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 16, 8>(p, 13, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 16, 4>(p, 14, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 8, 8>(p, 15, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 8, 4>(p, 16, c, o, lane, stage);
+    run_kind_if<kDepth, 10, 8, 2>(p, 17, c, o, lane, stage);
   }
+}
+
+// Zeroes the chunk counter ahead of the forward launch (a kernel node rather
+// than a memset, so the captured graph holds kernels only).
+__global__ void queue_reset_kernel(int32_t* queue) {
+  if (threadIdx.x == 0) *queue = 0;
 }
 
 __global__ __launch_bounds__(kReduceThreads) void batch_reduce_kernel(BatchReduceParams p) {
@@ -203,9 +226,11 @@ struct vca_batch {
   std::vector<int64_t> ring_off;   // per stream, in floats
   int32_t* err_flag = nullptr;     // device view of err_host
   int32_t* err_host = nullptr;     // pinned, mapped: [n_streams]
+  int32_t* queue = nullptr;        // chunk counter of the forward launch
   std::vector<int> cur_state;
   std::vector<char> has_prev;
   std::vector<int64_t> submitted;
+  DoneMarks done;                  // completion of the recent rounds
   // descriptors (device + pinned staging)
   StreamDesc* d_streams = nullptr;
   ReduceParams* d_red = nullptr;
@@ -339,6 +364,9 @@ vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_chunks, 
   bp.blk_h = b->blk_h;
   bp.blk_dc = b->blk_dc;
   bp.err_flag = b->err_flag;
+  bp.queue = b->queue;
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, b->queue);
+  BHIP_TRY(b, hipGetLastError());
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, bp);
   BHIP_TRY(b, hipGetLastError());
   if (total_frames > 0) {
@@ -407,7 +435,7 @@ void vca_close_batch(vca_batch* b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     void* bufs[] = {b->tab_b1p, b->tab_a2, b->tab_wp,     b->blk_h,
-                    b->blk_dc,  b->state,  b->d_streams, b->d_red};
+                    b->blk_dc,  b->state,  b->d_streams, b->d_red, b->queue};
     for (void* p : bufs)
       if (p) (void)hipFree(p);
     if (b->rings_host) (void)hipHostFree(b->rings_host);
@@ -416,6 +444,7 @@ void vca_close_batch(vca_batch* b) {
     if (b->h_red) (void)hipHostFree(b->h_red);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+    b->done.destroy();
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   }
@@ -483,7 +512,8 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   }
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess)
     return bail(VCA_ERR_DEVICE);
-  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess)
+  if (hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess ||
+      b->done.init(n_streams) != hipSuccess)
     return bail(VCA_ERR_DEVICE);
   vca_status s;
   if ((s = balloc(b, &b->tab_b1p, kKinds * kMaxPack * 64)) != VCA_OK) return bail(s);
@@ -499,6 +529,7 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
     return bail(VCA_ERR_OOM);
   if ((s = balloc(b, &b->d_streams, n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->d_red, n_streams)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->queue, 1)) != VCA_OK) return bail(s);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_streams), sizeof(StreamDesc) * n_streams, 0) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(ReduceParams) * n_streams, 0) != hipSuccess)
     return bail(VCA_ERR_OOM);
@@ -592,6 +623,7 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
       b->submitted[s] += cnt[s];
       off[s] += cnt[s];
     }
+    BHIP_TRY(b, b->done.record(b->stream, b->submitted.data()));
   }
   return VCA_OK;
 }
@@ -660,8 +692,9 @@ vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32
   const int64_t cap = b->cfgs[stream].feature_capacity;
   if (first < b->submitted[stream] - cap) return bfail(b, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(b->device);
-  BHIP_TRY(b, hipStreamSynchronize(b->stream));
-  // the rings and flags are host memory the kernels wrote before the stream drained
+  BHIP_TRY(b, b->done.wait(stream, first + count, b->stream));
+  // the rings and flags are host memory the kernels wrote before the round
+  // that produced the last frame asked for completed
   if (static_cast<volatile int32_t*>(b->err_host)[stream])
     return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to this stream");
   const float* ring = b->rings_host + b->ring_off[stream];

@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/vca.h"
 #include "vca_reduce.h"
@@ -134,6 +135,60 @@ inline hipError_t host_mapped_alloc(size_t bytes, void** host, void** dev) {
   std::memset(*host, 0, bytes ? bytes : 1);
   return hipHostGetDevicePointer(dev, *host, 0);
 }
+
+// Completion marks of the most recent launches on one stream.  After each
+// launch an event is recorded together with, per video stream, the number of
+// frames submitted up to and including that launch; a feature read then waits
+// for the oldest launch that covers the frames it asks for instead of
+// draining the whole stream, so a caller can queue the next batch before
+// reading the last one.  A read older than every remembered mark waits for
+// the oldest remembered launch (later than needed, never earlier).
+class DoneMarks {
+ public:
+  static constexpr int kMarks = 16;
+
+  hipError_t init(int n_streams) {
+    n_ = n_streams;
+    end_.assign((size_t)kMarks * n_streams, 0);
+    for (int i = 0; i < kMarks; i++) {
+      hipError_t e = hipEventCreateWithFlags(&ev_[i], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  void destroy() {
+    for (hipEvent_t& e : ev_)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+  }
+  // ends[s]: frames of stream s submitted up to and including the launch
+  // just enqueued on `stream`.
+  hipError_t record(hipStream_t stream, const int64_t* ends) {
+    const int i = next_;
+    hipError_t e = hipEventRecord(ev_[i], stream);
+    if (e != hipSuccess) return e;
+    std::copy(ends, ends + n_, end_.begin() + (size_t)i * n_);
+    next_ = (next_ + 1) % kMarks;
+    used_ = std::min(used_ + 1, kMarks);
+    return hipSuccess;
+  }
+  // Blocks until every frame of stream s below `upto` has been written.
+  hipError_t wait(int s, int64_t upto, hipStream_t stream) const {
+    for (int k = 0; k < used_; k++) {
+      const int i = (next_ - used_ + k + kMarks) % kMarks;
+      if (end_[(size_t)i * n_ + s] >= upto) return hipEventSynchronize(ev_[i]);
+    }
+    return hipStreamSynchronize(stream);   // nothing recorded covers it
+  }
+
+ private:
+  int n_ = 0;
+  hipEvent_t ev_[kMarks] = {};
+  std::vector<int64_t> end_;
+  int next_ = 0, used_ = 0;
+};
 
 // Launch parameters chosen by the autotuner (depth 0 = not tuned).
 struct LaunchChoice {

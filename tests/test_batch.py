@@ -77,6 +77,25 @@ def test_batch_graph_replays_match_plain(vca, frames):
         assert got[s].tobytes() == ref.tobytes(), f"stream {s} ({d}) differs from the plain path"
 
 
+def test_batch_features_read_while_later_rounds_are_queued(vca, frames):
+    """vca_batch_features waits for the round that produced the frames asked
+    for: the first call's features read after a second call was queued (one
+    frame per round: 24 rounds, more than the batch remembers) equal the plain
+    path's."""
+    print_case(test="batch_pipelined")
+    one = [dict(d, max_batch=1) for d in STREAMS]
+    b = vca.Batch(one)
+    first = b.submit(list(frames))
+    b.submit(list(frames))
+    got = [b.features(s, first[s], d["n"]) for s, d in enumerate(STREAMS)]
+    second = [b.features(s, d["n"], d["n"]) for s, d in enumerate(STREAMS)]
+    b.close()
+    for s, d in enumerate(STREAMS):
+        ref = plain_features(vca, d, frames[s], 2)
+        assert got[s].tobytes() == ref[:d["n"]].tobytes(), f"stream {s} ({d})"
+        assert second[s].tobytes() == ref[d["n"]:].tobytes(), f"stream {s} ({d})"
+
+
 def test_batch_oracle_spot_checks(vca, frames):
     print_case(test="batch_oracle")
     b = vca.Batch(STREAMS)

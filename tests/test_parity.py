@@ -122,6 +122,34 @@ def test_call_boundaries_reset_and_chunking(vca, patches):
     assert (f[:4] == whole[:4]).all()
 
 
+def test_features_read_while_later_calls_are_queued(vca, patches):
+    """A feature read waits for the launch that produced the frames asked for,
+    not for the whole stream: reading call i's frames after call i + 1 was
+    queued gives call i's features, also with one launch per frame
+    (max_batch 1) and for frames older than every launch the context still
+    remembers (30 launches queued, frames 0-2 read last)."""
+    print_case(test="features_pipelined")
+    y, u, v = to_device(patches)
+    for mb in (0, 1):
+        ref_an = vca.Analyzer(patches.width, patches.height, max_batch=mb)
+        for _ in range(3):
+            ref_an.submit(y, u, v)
+        ref = ref_an.features(0, 30)
+        ref_an.close()
+        an = vca.Analyzer(patches.width, patches.height, max_batch=mb)
+        got, prev = [], None
+        for _ in range(3):
+            first = an.submit(y, u, v)
+            if prev is not None:
+                got.append(an.features(prev, 10))
+            prev = first
+        got.append(an.features(prev, 10))
+        oldest = an.features(0, 3)
+        an.close()
+        assert np.concatenate(got).tobytes() == ref.tobytes(), f"max_batch {mb}"
+        assert oldest.tobytes() == ref[:3].tobytes()
+
+
 def test_static_sequence_and_determinism(vca, patches):
     print_case(test="static_sequence")
     rep = synth.Video(np.repeat(patches.y[:1], 5, 0), np.repeat(patches.u[:1], 5, 0),
