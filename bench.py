@@ -76,10 +76,24 @@ def cpu_baseline(sv, frames: int, lowpass_k: int = 0) -> dict:
     t0 = time.perf_counter()
     oracle.analyze(cfg, video.y, video.u, video.v, threads=threads)
     dt = time.perf_counter() - t0
+    # beside it: K = 16 on a quarter of the sample, and one thread on 8 frames
+    nk = max(1, frames // 4)
+    t0 = time.perf_counter()
+    oracle.analyze(oracle.Config(WIDTH, HEIGHT, 8, BLOCK, 16), video.y[:nk], video.u[:nk],
+                   video.v[:nk], threads=threads)
+    dt_k16 = time.perf_counter() - t0
+    n1 = min(8, frames)
+    t0 = time.perf_counter()
+    oracle.analyze(cfg, video.y[:n1], video.u[:n1], video.v[:n1], threads=1)
+    dt_1 = time.perf_counter() - t0
     return {"value": frames / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
             "sample": f"first {frames} frames of the 600-frame 2160p workload, "
                       f"{'full DCT' if lowpass_k == 0 else f'K={lowpass_k}'}, "
                       f"{threads} OpenMP threads, {dt:.1f} s wall",
+            "lowpass_k16_value": nk / dt_k16,
+            "lowpass_k16_sample": f"first {nk} frames, K=16, {threads} threads, {dt_k16:.1f} s",
+            "single_thread_value": n1 / dt_1,
+            "single_thread_sample": f"first {n1} frames, full DCT, 1 thread, {dt_1:.1f} s",
             "cpu": platform.processor() or platform.machine()}
 
 
