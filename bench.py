@@ -13,7 +13,6 @@ Prints one JSON line.  ``--gpus`` above 1 is refused: the path runs on one GPU.
 from __future__ import annotations
 
 import argparse
-import contextlib
 import gc
 import json
 import os
@@ -35,19 +34,6 @@ FP16_PEAK_TFLOPS = 2500.0       # MI355X dense fp16 MFMA
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-@contextlib.contextmanager
-def timed_region():
-    """Python's cyclic collector off inside a timed loop (as timeit does): a
-    full collection over torch's object graph pauses the host for tens of ms
-    at random steps, which is the interpreter's cost, not the path's."""
-    gc.collect()
-    gc.disable()
-    try:
-        yield
-    finally:
-        gc.enable()
 
 
 def algorithmic_bytes_per_frame(width: int, height: int, w: int) -> int:
@@ -115,13 +101,12 @@ def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool,
         an.features(first, FRAMES)
     an.timing(reset=True)
     torch.cuda.synchronize()
-    with timed_region():
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            first = an.submit(*planes)
-            feats = an.features(first, FRAMES)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        first = an.submit(*planes)
+        feats = an.features(first, FRAMES)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
     tm = an.timing(reset=True)
     an.close()
     fwd_ms = tm["forward_ms"] / max(1, tm["forward_launches"])
@@ -177,14 +162,13 @@ def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
         b.submit(frames)
     b.timing(reset=True)
     torch.cuda.synchronize()
-    with timed_region():
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            first = b.submit(frames)
-            for s, d in enumerate(descs):
-                b.features(s, first[s], d["n_frames"])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        first = b.submit(frames)
+        for s, d in enumerate(descs):
+            b.features(s, first[s], d["n_frames"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
     tm = b.timing(reset=True)
     b.close()
     # the same streams through plain contexts, one after another
@@ -193,15 +177,14 @@ def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
     for an, fr in zip(ans, frames):
         an.submit(*fr)
     torch.cuda.synchronize()
-    with timed_region():
-        t1 = time.perf_counter()
-        for _ in range(steps):
-            for an, fr in zip(ans, frames):
-                an.submit(*fr)
-            for an, d in zip(ans, descs):
-                an.features(an.submitted - d["n_frames"], d["n_frames"])
-        torch.cuda.synchronize()
-        dt_plain = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for an, fr in zip(ans, frames):
+            an.submit(*fr)
+        for an, d in zip(ans, descs):
+            an.features(an.submitted - d["n_frames"], d["n_frames"])
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t1
     for an in ans:
         an.close()
     dev_ms = tm["ms"] / max(1, tm["launches"])
@@ -238,23 +221,21 @@ def run_ingest(vca, dev, steps: int) -> dict:
     nbytes = y.nbytes + u.nbytes + v.nbytes
     an = vca.Analyzer(WIDTH, HEIGHT, block_size=BLOCK, max_batch=MAX_BATCH)
     an.features(an.submit_host(y, u, v), INGEST_FRAMES)            # warm-up (allocates staging)
-    with timed_region():
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            first = an.submit_host(y, u, v)
-            an.features(first, INGEST_FRAMES)
-        dt_host = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        first = an.submit_host(y, u, v)
+        an.features(first, INGEST_FRAMES)
+    dt_host = (time.perf_counter() - t0) / steps
     fd, path = tempfile.mkstemp(suffix=".yuv", dir="/tmp")
     os.close(fd)
     try:
         vca.write_yuv(path, y, u, v)
         an.features(an.submit_file(path), INGEST_FRAMES)            # warm the page cache
-        with timed_region():
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                first = an.submit_file(path)
-                an.features(first, INGEST_FRAMES)
-            dt_file = (time.perf_counter() - t0) / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            first = an.submit_file(path)
+            an.features(first, INGEST_FRAMES)
+        dt_file = (time.perf_counter() - t0) / steps
     finally:
         os.unlink(path)
     an.close()
@@ -296,12 +277,11 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    with timed_region():
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            gx = step()
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gx = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
 
     # the two C-ABI calls alone, preallocated buffers, events on their stream
     L = _lib.lib()
@@ -334,12 +314,11 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
     for _ in range(warmup):
         an.features(an.submit(dv.y, dv.u, dv.v), n)
     torch.cuda.synchronize()
-    with timed_region():
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            an.features(an.submit(dv.y, dv.u, dv.v), n)
-        torch.cuda.synchronize()
-        dt_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        an.features(an.submit(dv.y, dv.u, dv.v), n)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
     an.close()
 
     tiles = (W // w) * (H // w) * n                # w = 32: one 32 x 32 tile per block
@@ -454,6 +433,14 @@ def main() -> int:
     import synth
     from synth.device import scene_to_device
 
+    # Python's cyclic collector is off for the rest of the run (collected
+    # once here): a full collection over torch's object graph stalls the host
+    # for tens of milliseconds at random steps, which is the interpreter's
+    # cost, not the path's.  Collecting per mode instead would idle the GPU
+    # between the autotuner and the timed steps and start them at a lowered
+    # clock.
+    gc.collect()
+    gc.disable()
     results = {}
     modes = args.modes.split(",")
     sv = dev = None
