@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
   constexpr int kBpt = kTile / kW;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int r = lane & 31, g = lane >> 5;
+  const int r = lane & 31;
   double wd[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) wd[j] = reg_used(j, kW, kK) ? p.tab->wd[j][lane] : 0.0;
@@ -239,16 +239,19 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
       mask |= (y[j] > 0.f ? 1u << j : 0u) | (y[j] < 0.f ? 1u << (16 + j) : 0u);
     }
     p.masks[(int64_t)id * 64 + lane] = mask;
-#pragma unroll
-    for (int off = 1; off < kW; off <<= 1)
-#pragma unroll
-      for (int b = 0; b < kBpt; b++) h[b] += __shfl_xor(h[b], off);
-#pragma unroll
-    for (int b = 0; b < kBpt; b++) h[b] += __shfl_xor(h[b], 32);
-    if (g == 0 && r % kW == 0 && r / kW < t.vc) {
-#pragma unroll
-      for (int b = 0; b < kBpt; b++)
-        if (b < t.vr) p.blk_h[t.out0 + b * p.nbx + r / kW] = h[b];
+    // Each block's shares lie in the kW lanes of its block column in both
+    // halves, one per block row in h[]; they are summed across lanes with
+    // permlane swaps and DPP (no LDS round trips), leaving one block per
+    // lane group, which one lane of the group stores.
+    if constexpr (kW == 32) {
+      double v = fold32(h[0], h[0]);
+      v = dpp_allreduce<16>(fold16(v, v));
+      if (lane == 0) p.blk_h[t.out0] = v;
+    } else {
+      const double v = rows_reduce<kW, kW>(h, lane);
+      const int row = rows_lane_row<kW, kW>(lane), col = r / kW;
+      if ((lane & (kW == 16 ? 15 : 3)) == 0 && row < t.vr && col < t.vc)
+        p.blk_h[t.out0 + row * p.nbx + col] = v;
     }
     t = tn;
 #pragma unroll
