@@ -139,14 +139,21 @@ def plane_bytes(d: dict) -> int:
     return algorithmic_bytes_per_frame(d["width"], d["height"], d["block_size"])
 
 
-def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
-    """64 uneven streams (resolution, block size, frame count drawn per
-    stream) in one persistent graph-replayed launch per step, against the same
-    streams analysed one after another by plain contexts."""
+def small_streams(n: int = 256, frames: int = 8) -> list:
+    """Many small live streams: n streams of 640x360 8-bit 4:2:0, `frames`
+    frames each per step, block size 8, 16, 32 in turn."""
+    return [dict(width=640, height=360, block_size=(8, 16, 32)[s % 3], n_frames=frames, stream=s + 1)
+            for s in range(n)]
+
+
+def run_batch(vca, steps: int, warmup: int, tune: bool, descs: list, workload: str) -> dict:
+    """The streams `descs` in one persistent graph-replayed launch per step,
+    against the same streams analysed one after another by plain contexts
+    (each on its own stream).  Both sides submit descriptors prepared once
+    for the fixed frame buffers; the batch reads every stream's features
+    with one call, the plain contexts with one call each."""
     import torch
-    import synth
     from synth.device import generated_scene_video
-    descs = synth.batch_streams(64)
     log(f"generating {len(descs)} streams, {sum(d['n_frames'] for d in descs)} frames on the device")
     vids = [generated_scene_video(d["width"], d["height"], d["n_frames"], seed=3000 + d["stream"])
             for d in descs]
@@ -158,15 +165,15 @@ def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
                 max_batch=d["n_frames"]) for d in descs]
     b = vca.Batch(cfg, timing=True)
     launch = b.tune(frames, reps=1) if tune else b.tuned_launch()
+    prepared = b.prepare(frames)
     for _ in range(warmup):
-        b.submit(frames)
+        b.submit(prepared)
     b.timing(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        first = b.submit(frames)
-        for s, d in enumerate(descs):
-            b.features(s, first[s], d["n_frames"])
+        first = b.submit(prepared)
+        b.features_many([(s, first[s], d["n_frames"]) for s, d in enumerate(descs)])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tm = b.timing(reset=True)
@@ -174,13 +181,14 @@ def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
     # the same streams through plain contexts, one after another
     ans = [vca.Analyzer(d["width"], d["height"], block_size=d["block_size"], max_batch=d["n_frames"])
            for d in descs]
-    for an, fr in zip(ans, frames):
-        an.submit(*fr)
+    preps = [an.prepare(*fr) for an, fr in zip(ans, frames)]
+    for an, pf in zip(ans, preps):
+        an.submit(pf)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(steps):
-        for an, fr in zip(ans, frames):
-            an.submit(*fr)
+        for an, pf in zip(ans, preps):
+            an.submit(pf)
         for an, d in zip(ans, descs):
             an.features(an.submitted - d["n_frames"], d["n_frames"])
     torch.cuda.synchronize()
@@ -190,6 +198,7 @@ def run_batch(vca, steps: int, warmup: int, tune: bool) -> dict:
     dev_ms = tm["ms"] / max(1, tm["launches"])
     gbs = total_bytes / (dev_ms * 1e-3) / 1e9
     return {
+        "workload": workload,
         "streams": len(descs), "frames_per_step": total_frames,
         "bytes_per_step": total_bytes,
         "value": steps * total_frames / dt, "unit": "frames/s",
@@ -463,14 +472,22 @@ def main() -> int:
         ingest = run_ingest(vca, dev, max(2, args.steps // 8))
         log(f"ingest: {ingest['value']:.0f} frames/s from host memory ({ingest['GBps']:.1f} GB/s), "
             f"{ingest['file_value']:.0f} frames/s from a .yuv file")
-    batch = None
+    batch = batch_small = None
     if "batch" in modes:
         del dev
         torch.cuda.empty_cache()
         log("timing the batched form")
-        batch = run_batch(vca, max(2, args.steps // 4), 1, not args.no_tune)
+        batch = run_batch(vca, max(2, args.steps // 4), 1, not args.no_tune, synth.batch_streams(64),
+                          "64 streams, resolution 360p..2160p, w in {8, 16, 32}, 30-300 frames "
+                          "each (drawn per stream), 8-bit 4:2:0")
         log(f"batched: {batch['value']:.0f} frames/s over {batch['streams']} streams, "
             f"{batch['speedup_vs_plain']:.2f}x the plain path")
+        torch.cuda.empty_cache()
+        batch_small = run_batch(vca, max(20, args.steps), 3, not args.no_tune, small_streams(),
+                                "256 streams of 640x360 8-bit 4:2:0, 8 frames each per step, "
+                                "w = 8, 16, 32 in turn")
+        log(f"batched, small streams: {batch_small['value']:.0f} frames/s over "
+            f"{batch_small['streams']} streams, {batch_small['speedup_vs_plain']:.2f}x the plain path")
 
     backward = None
     if "backward" in modes:
@@ -488,7 +505,8 @@ def main() -> int:
     copy = calibration_copy(args.calibrate_copy) if args.calibrate_copy > 0 else None
 
     if not results:
-        print(json.dumps({"metric": METRIC, "batched": batch, "backward": backward,
+        print(json.dumps({"metric": METRIC, "batched": batch, "batched_small_streams": batch_small,
+                          "backward": backward,
                           "host_ingest": ingest, "calibration_copy": copy}), flush=True)
         return 0
     head = results.get("full") or next(iter(results.values()))
@@ -540,6 +558,7 @@ def main() -> int:
         line["host_ingest"] = ingest
     if batch is not None:
         line["batched"] = batch
+        line["batched_small_streams"] = batch_small
     if backward is not None:
         line["backward"] = backward
     print(json.dumps(line), flush=True)

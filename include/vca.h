@@ -258,6 +258,19 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
 vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32_t count,
                               vca_frame_features* out_host);
 
+/* Several feature reads in one call: request r is frames [first[r],
+ * first[r] + count[r]) of stream streams[r] (host arrays of n_requests
+ * entries); their records go to out_host one request after another
+ * (sum of count[r] records, caller-owned).  Waits once, for the latest round
+ * any request needs.  Every request is checked before anything is copied
+ * (VCA_ERR_INVALID_ARG for a bad stream or range, VCA_ERR_STATE for frames
+ * not submitted or out of the ring); a stream whose validation flag is set
+ * gives VCA_ERR_STATE after the records of the requests before it are
+ * written. */
+vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32_t* streams,
+                                   const int64_t* first, const int32_t* count,
+                                   vca_frame_features* out_host);
+
 /* Autotuner of the batched launch shape (as vca_tune, over the first round
  * of the given frames of every stream); cached under the batch's stream
  * list.  Features and h state are unchanged. */

@@ -29,7 +29,8 @@ EXPORTS = (
     "vca_features", "vca_block_coeffs",
     "vca_block_stats", "vca_block_maps", "vca_get_timing", "vca_tune", "vca_tuned_launch", "vca_reset",
     "vca_frames_submitted", "vca_close", "vca_status_str", "vca_last_error",
-    "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_tune_batch",
+    "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_batch_features_many",
+    "vca_tune_batch",
     "vca_batch_tuned_launch", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
     "vca_batch_last_error", "vca_close_batch",
     "vca_grad_workspace", "vca_energy_forward", "vca_energy_backward",
@@ -110,6 +111,7 @@ def lib() -> ctypes.CDLL:
             "vca_open_batch": (St, [ctypes.POINTER(VcaConfig), ctypes.c_int32, P, ctypes.POINTER(P)]),
             "vca_analyze_batch": (St, [P, ctypes.POINTER(VcaFrames), P]),
             "vca_batch_features": (St, [P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, P]),
+            "vca_batch_features_many": (St, [P, ctypes.c_int32, P, P, P, P]),
             "vca_tune_batch": (St, [P, ctypes.POINTER(VcaFrames), P, ctypes.c_int32]),
             "vca_batch_tuned_launch": (St, [P, P, P, P]),
             "vca_batch_timing": (St, [P, P, P, P, ctypes.c_int32]),

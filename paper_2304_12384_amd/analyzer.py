@@ -45,6 +45,16 @@ def _plane_geometry(t: torch.Tensor, bps: int):
     return t, t.stride(1) * bps, t.stride(0) * bps
 
 
+class PreparedFrames:
+    """Frame descriptors of device buffers, validated once by ``prepare`` of
+    one Analyzer or Batch and submitted any number of times (the caller
+    refills the buffers in between; they stay referenced here)."""
+    __slots__ = ("owner", "frames", "counts", "keep")
+
+    def __init__(self, owner, frames, counts, keep):
+        self.owner, self.frames, self.counts, self.keep = owner, frames, counts, keep
+
+
 class Analyzer:
     """Wraps one ``vca_ctx``.
 
@@ -99,8 +109,9 @@ class Analyzer:
     def submitted(self) -> int:
         return int(_lib.lib().vca_frames_submitted(self._ctx))
 
-    def submit(self, y: torch.Tensor, u: torch.Tensor, v: torch.Tensor) -> int:
-        """Enqueues frames (asynchronous).  Returns the index of the first one."""
+    def prepare(self, y: torch.Tensor, u: torch.Tensor, v: torch.Tensor) -> PreparedFrames:
+        """Validates device planes once; ``submit`` takes the result in place
+        of the planes."""
         bps = 1 if self.bit_depth == 8 else 2
         y, py, fy = _plane_geometry(y, bps)
         u, pu, fu = _plane_geometry(u, bps)
@@ -115,10 +126,19 @@ class Analyzer:
         if u.shape[1:] != (self.height // 2, self.width // 2) or v.shape[1:] != u.shape[1:]:
             raise ValueError("chroma planes must be [n, H/2, W/2]")
         fr = VcaFrames(y.data_ptr(), u.data_ptr(), v.data_ptr(), py, pu, fy, fu, 1)
+        return PreparedFrames(self, fr, n, (y, u, v))
+
+    def submit(self, y, u: torch.Tensor | None = None, v: torch.Tensor | None = None) -> int:
+        """Enqueues frames (asynchronous): device planes y, u, v, or a
+        ``prepare`` result of this Analyzer.  Returns the index of the first
+        frame."""
+        p = y if isinstance(y, PreparedFrames) else self.prepare(y, u, v)
+        if p.owner is not self:
+            raise ValueError("frames prepared by another Analyzer")
         first = self.submitted
-        check(_lib.lib().vca_analyze_frames(self._ctx, ctypes.byref(fr), n), "vca_analyze_frames",
-              self._ctx)
-        self._keep = [y, u, v]
+        check(_lib.lib().vca_analyze_frames(self._ctx, ctypes.byref(p.frames), p.counts),
+              "vca_analyze_frames", self._ctx)
+        self._keep = p.keep
         return first
 
     def submit_host(self, y, u, v) -> int:
@@ -318,6 +338,7 @@ class Batch:
         check(_lib.lib().vca_open_batch(cfgs, n, ctypes.c_void_p(self.stream.cuda_stream),
                                         ctypes.byref(self._b)), "vca_open_batch")
         self._keep = []
+        self._submitted = [0] * n     # mirrors vca_batch_submitted
 
     def close(self) -> None:
         if self._b:
@@ -351,13 +372,27 @@ class Batch:
     def submitted(self, s: int) -> int:
         return int(_lib.lib().vca_batch_submitted(self._b, s))
 
-    def submit(self, frames: list) -> list:
-        """frames[s] = (y, u, v) device planes of stream s, or None.  Returns
-        the index of each stream's first submitted frame (asynchronous)."""
+    def prepare(self, frames: list) -> PreparedFrames:
+        """Validates every stream's device planes once; ``submit`` takes the
+        result in place of the list."""
         fr, counts, keep = self._descr(frames)
-        first = [self.submitted(s) for s in range(self.n)]
-        check(_lib.lib().vca_analyze_batch(self._b, fr, counts), "vca_analyze_batch", batch=self._b)
-        self._keep = keep
+        return PreparedFrames(self, fr, counts, keep)
+
+    def submit(self, frames) -> list:
+        """frames[s] = (y, u, v) device planes of stream s, or None; or a
+        ``prepare`` result of this Batch.  Returns the index of each stream's
+        first submitted frame (asynchronous)."""
+        p = frames if isinstance(frames, PreparedFrames) else self.prepare(frames)
+        if p.owner is not self:
+            raise ValueError("frames prepared by another Batch")
+        first = list(self._submitted)
+        st = _lib.lib().vca_analyze_batch(self._b, p.frames, p.counts)
+        if st == 0:
+            self._submitted = [f + c for f, c in zip(first, p.counts)]
+        else:   # a failure may come after some rounds were enqueued
+            self._submitted = [self.submitted(s) for s in range(self.n)]
+        check(st, "vca_analyze_batch", batch=self._b)
+        self._keep = p.keep
         return first
 
     def features(self, s: int, first: int, count: int) -> np.ndarray:
@@ -366,6 +401,20 @@ class Batch:
                                             out.ctypes.data_as(ctypes.c_void_p)),
               "vca_batch_features", batch=self._b)
         return out
+
+    def features_many(self, requests: list) -> list:
+        """Features of several (stream, first, count) requests in one call,
+        waiting once: a list of numpy [count, 7] arrays in request order."""
+        n = len(requests)
+        streams = np.fromiter((r[0] for r in requests), np.int32, n)
+        first = np.fromiter((r[1] for r in requests), np.int64, n)
+        count = np.fromiter((r[2] for r in requests), np.int32, n)
+        out = np.zeros((int(count.sum()), 7), np.float32)
+        check(_lib.lib().vca_batch_features_many(
+            self._b, n, streams.ctypes.data_as(ctypes.c_void_p), first.ctypes.data_as(ctypes.c_void_p),
+            count.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p)),
+            "vca_batch_features_many", batch=self._b)
+        return np.split(out, np.cumsum(count)[:-1]) if n else []
 
     def tune(self, frames: list, reps: int = 3) -> dict:
         fr, counts, keep = self._descr(frames)

@@ -708,6 +708,42 @@ vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32
   return VCA_OK;
 }
 
+vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32_t* streams,
+                                   const int64_t* first, const int32_t* count,
+                                   vca_frame_features* out) {
+  if (!b || n_requests < 0 || (n_requests > 0 && (!streams || !first || !count || !out)))
+    return bfail(b, VCA_ERR_INVALID_ARG, "bad vca_batch_features_many arguments");
+  int rank = 0;
+  for (int32_t r = 0; r < n_requests; r++) {
+    const int32_t s = streams[r];
+    if (s < 0 || s >= b->n || count[r] < 0 || first[r] < 0)
+      return bfail(b, VCA_ERR_INVALID_ARG, "request " + std::to_string(r) + ": bad stream or range");
+    if (first[r] + count[r] > b->submitted[s])
+      return bfail(b, VCA_ERR_STATE, "request " + std::to_string(r) + ": frame not yet submitted");
+    if (first[r] < b->submitted[s] - b->cfgs[s].feature_capacity)
+      return bfail(b, VCA_ERR_STATE, "request " + std::to_string(r) + ": frame left the feature ring");
+    rank = std::max(rank, b->done.cover(s, first[r] + count[r]));
+  }
+  DeviceGuard guard(b->device);
+  BHIP_TRY(b, b->done.wait_rank(rank, b->stream));
+  float* dst = reinterpret_cast<float*>(out);
+  for (int32_t r = 0; r < n_requests; r++) {
+    const int32_t s = streams[r];
+    if (static_cast<volatile int32_t*>(b->err_host)[s])
+      return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to stream " + std::to_string(s));
+    const int64_t cap = b->cfgs[s].feature_capacity;
+    const float* ring = b->rings_host + b->ring_off[s];
+    for (int64_t done = 0; done < count[r];) {
+      const int64_t slot = (first[r] + done) % cap;
+      const int64_t n = std::min<int64_t>(count[r] - done, cap - slot);
+      std::memcpy(dst, ring + slot * 7, (size_t)n * 7 * sizeof(float));
+      dst += n * 7;
+      done += n;
+    }
+  }
+  return VCA_OK;
+}
+
 vca_status vca_batch_timing(vca_batch* b, double* total_ms, int64_t* launches, int64_t* frames,
                             int32_t reset) {
   if (!b) return VCA_ERR_INVALID_ARG;

@@ -174,16 +174,28 @@ class DoneMarks {
     used_ = std::min(used_ + 1, kMarks);
     return hipSuccess;
   }
+  // Age rank (0 = oldest remembered) of the oldest launch after which every
+  // frame of stream s below `upto` has been written, or kMarks if no
+  // remembered launch covers it.
+  int cover(int s, int64_t upto) const {
+    for (int k = 0; k < used_; k++)
+      if (end_[(size_t)slot(k) * n_ + s] >= upto) return k;
+    return kMarks;
+  }
+  // Blocks until the launch of age rank k has completed (k = kMarks: until
+  // the stream drains).  Launches complete in order, so this also covers
+  // every older one.
+  hipError_t wait_rank(int k, hipStream_t stream) const {
+    if (k >= used_) return hipStreamSynchronize(stream);
+    return hipEventSynchronize(ev_[slot(k)]);
+  }
   // Blocks until every frame of stream s below `upto` has been written.
   hipError_t wait(int s, int64_t upto, hipStream_t stream) const {
-    for (int k = 0; k < used_; k++) {
-      const int i = (next_ - used_ + k + kMarks) % kMarks;
-      if (end_[(size_t)i * n_ + s] >= upto) return hipEventSynchronize(ev_[i]);
-    }
-    return hipStreamSynchronize(stream);   // nothing recorded covers it
+    return wait_rank(cover(s, upto), stream);
   }
 
  private:
+  int slot(int k) const { return (next_ - used_ + k + kMarks) % kMarks; }
   int n_ = 0;
   hipEvent_t ev_[kMarks] = {};
   std::vector<int64_t> end_;

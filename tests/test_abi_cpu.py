@@ -81,6 +81,8 @@ def test_null_arguments():
     assert L.vca_features(None, 0, 0, None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_reset(None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_block_maps(None, 0, 1, None, None, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_batch_features(None, 0, 0, 0, None) == _lib.VCA_ERR_INVALID_ARG
+    assert L.vca_batch_features_many(None, 0, None, None, None, None) == _lib.VCA_ERR_INVALID_ARG
     assert L.vca_frames_submitted(None) == -1
     assert L.vca_last_error(None) == b""
     L.vca_close(None)

@@ -96,6 +96,47 @@ def test_batch_features_read_while_later_rounds_are_queued(vca, frames):
         assert second[s].tobytes() == ref[d["n"]:].tobytes(), f"stream {s} ({d})"
 
 
+def test_batch_features_many_and_prepared_frames(vca, frames):
+    """vca_batch_features_many returns, request by request, what
+    vca_batch_features returns (two calls, several rounds each, requests out
+    of stream order, repeated and empty); prepared frames submit exactly as
+    the planes they were prepared from; bad requests fail before anything is
+    copied."""
+    print_case(test="batch_features_many")
+    small = [dict(d, max_batch=4) for d in STREAMS]
+    b = vca.Batch(small)
+    p = b.prepare(list(frames))
+    b.submit(p)
+    b.submit(list(frames))
+    reqs = [(s, 0, 2 * d["n"]) for s, d in reversed(list(enumerate(STREAMS)))]
+    reqs += [(1, 3, 5), (1, 0, 0), (0, STREAMS[0]["n"], 1)]
+    got = b.features_many(reqs)
+    for (s, f, c), g in zip(reqs, got):
+        assert g.shape == (c, 7)
+        assert g.tobytes() == b.features(s, f, c).tobytes(), (s, f, c)
+    for s, d in enumerate(STREAMS):
+        ref = plain_features(vca, d, frames[s], 2)
+        assert b.features(s, 0, 2 * d["n"]).tobytes() == ref.tobytes(), f"stream {s}"
+    with pytest.raises(vca.VcaError):
+        b.features_many([(0, 0, 1), (len(STREAMS), 0, 1)])
+    with pytest.raises(vca.VcaError):
+        b.features_many([(0, 0, 2 * STREAMS[0]["n"] + 1)])
+    assert b.features_many([]) == []
+    other = vca.Batch(small)
+    with pytest.raises(ValueError):
+        other.submit(p)
+    other.close()
+    b.close()
+    # the plain path's prepared frames
+    d = STREAMS[1]
+    an = vca.Analyzer(d["width"], d["height"], block_size=d["block_size"], lowpass_k=d.get("lowpass_k", 0))
+    pf = an.prepare(*frames[1])
+    an.submit(pf)
+    an.submit(*frames[1])
+    assert an.features(0, 2 * d["n"]).tobytes() == plain_features(vca, d, frames[1], 2).tobytes()
+    an.close()
+
+
 def test_batch_oracle_spot_checks(vca, frames):
     print_case(test="batch_oracle")
     b = vca.Batch(STREAMS)
