@@ -7,12 +7,12 @@
 // device-wide counter, so that waves that drew cheap chunks take more and
 // all finish together, copies the chunk's stream descriptor into registers,
 // and runs the strip loop specialised for the stream's (bit depth, w, K)
-// class.  A second launch
-// reduces every (stream, frame) pair to its seven features (vca_reduce.h).
-// Both launches are captured once into a hipGraph per frame-count signature
-// and replayed; per call only the descriptor tables (frame pointers, state
-// buffers) are uploaded.  The ring depth and workgroups per CU come from
-// vca_tune_batch.
+// class.  A second launch reduces every (stream, frame) pair to its seven
+// features (vca_reduce.h).  The three kernels of a round (counter reset,
+// forward, reduction) are captured once into a hipGraph per frame-count
+// signature and replayed; per call only the descriptor tables (frame
+// pointers, state buffers) are uploaded.  The ring depth and workgroups per
+// CU come from vca_tune_batch.
 
 #include <hip/hip_runtime.h>
 
