@@ -218,15 +218,8 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
   const int stride = gridDim.x * kGWaves;
   int id = blockIdx.x * kGWaves + wave;
   if (id >= total) return;
-  // the next tile's samples are loaded while this one is transformed (the
-  // last tile loads itself again, so every iteration issues the same loads)
-  FTile<kW> t = decode_ftile<kW>(p, id);
-  float x[16];
-  load_ftile<kW>(p, t, lane, x);
-  for (; id < total; id += stride) {
-    const FTile<kW> tn = decode_ftile<kW>(p, min(id + stride, total - 1));
-    float xn[16];
-    load_ftile<kW>(p, tn, lane, xn);
+  // Energies and coefficient signs of tile `id` (samples x).
+  auto tile = [&](const FTile<kW>& t, const float (&x)[16], int id) {
     const v16f y = tile_y(b1, a2, x);
     double h[kBpt];
 #pragma unroll
@@ -253,9 +246,27 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
       if ((lane & (kW == 16 ? 15 : 3)) == 0 && row < t.vr && col < t.vc)
         p.blk_h[t.out0 + row * p.nbx + col] = v;
     }
-    t = tn;
-#pragma unroll
-    for (int i = 0; i < 16; i++) x[i] = xn[i];
+  };
+  // Two sample buffers in turn: the next tile's loads are issued before this
+  // tile is transformed and stay there (a scheduling barrier keeps the
+  // compiler from sinking them below the matrix products), and the loop is
+  // unrolled by two so that no buffer is copied (a copy would wait for the
+  // loads).  Past the end the last tile loads itself again, so every step
+  // issues the same loads.
+  FTile<kW> ta = decode_ftile<kW>(p, id), tb;
+  float xa[16], xb[16];
+  load_ftile<kW>(p, ta, lane, xa);
+  for (;;) {
+    tb = decode_ftile<kW>(p, min(id + stride, total - 1));
+    load_ftile<kW>(p, tb, lane, xb);
+    __builtin_amdgcn_sched_barrier(0);
+    tile(ta, xa, id);
+    if ((id += stride) >= total) break;
+    ta = decode_ftile<kW>(p, min(id + stride, total - 1));
+    load_ftile<kW>(p, ta, lane, xa);
+    __builtin_amdgcn_sched_barrier(0);
+    tile(tb, xb, id);
+    if ((id += stride) >= total) break;
   }
 }
 
