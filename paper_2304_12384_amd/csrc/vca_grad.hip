@@ -318,19 +318,26 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
   for (int h = 0; h < 2; h++) ct[h] = ld8(p.tab->ct[h], lane);
   const int total = p.n_frames * p.tiles_per_frame;
   const int stride = gridDim.x * kGWaves;
-  // a tile's inputs: its sign masks and, per block column of the lane's
-  // block row, H of the block in this, the previous and the next frame
-  // (the block's own index where a neighbour frame is not used)
+  // a tile's inputs: its sign masks; per block column of the lane's block
+  // row, H of the block in this, the previous and the next frame (the
+  // block's own index where a neighbour frame is not used); and the frame's
+  // upstream gradients dL/dE_t, dL/dh_t and dL/dh_{t+1} (the last index
+  // clamped; a term whose frame is not used is dropped where it is applied).
+  // Every load is unconditional, so the compiler can count what is in flight.
   struct In {
     FTile<kW> t;
     uint32_t mask;
     double hc[kBpt], hp[kBpt], hn[kBpt];
+    float gE, gh, ghn;
   };
   auto fetch = [&](int tid) {
     In in;
     in.t = decode_ftile<kW>(p, tid);
     in.mask = p.masks[(int64_t)tid * 64 + lane];
     const int f = in.t.f, pos = f % p.seq_len;
+    in.gE = p.gE[f];
+    in.gh = p.gh[f];
+    in.ghn = p.gh[min(f + 1, p.n_frames - 1)];
     const int br = min(r / kW, in.t.vr - 1);
 #pragma unroll
     for (int b = 0; b < kBpt; b++) {
@@ -341,11 +348,8 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
     }
     return in;
   };
-  int id = blockIdx.x * kGWaves + wave;
-  if (id >= total) return;
-  In cur = fetch(id);   // the next tile's inputs are loaded while this one is transformed
-  for (; id < total; id += stride) {
-    const In nxt = fetch(min(id + stride, total - 1));
+  // dL/dx of one tile from its inputs
+  auto tile = [&](const In& cur) {
     const FTile<kW> t = cur.t;
     const uint32_t mask = cur.mask;
     // S = W o sign(Y): lane (c + 32 g) register j is coefficient (m_j, c);
@@ -388,9 +392,9 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
     const int f = t.f;
     const int pos = f % p.seq_len;
     const bool has_prev = pos > 0, has_next = pos + 1 < p.seq_len;
-    const float gE = p.gE[f];
-    const float ghf = has_prev ? p.gh[f] : 0.f;
-    const float ghn = has_next ? p.gh[f + 1] : 0.f;
+    const float gE = cur.gE;
+    const float ghf = has_prev ? cur.gh : 0.f;
+    const float ghn = has_next ? cur.ghn : 0.f;
     float cb[kBpt];
 #pragma unroll
     for (int b = 0; b < kBpt; b++) {
@@ -413,7 +417,22 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
         }
       }
     }
-    cur = nxt;
+  };
+  // Two input sets in turn, as in the forward kernel: the next tile's loads
+  // are issued before this tile is transformed and stay there, and no set
+  // is copied.  Past the end the last tile is fetched again.
+  int id = blockIdx.x * kGWaves + wave;
+  if (id >= total) return;
+  In ia = fetch(id), ib;
+  for (;;) {
+    ib = fetch(min(id + stride, total - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    tile(ia);
+    if ((id += stride) >= total) break;
+    ia = fetch(min(id + stride, total - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    tile(ib);
+    if ((id += stride) >= total) break;
   }
 }
 
