@@ -493,7 +493,7 @@ def main() -> int:
     if "backward" in modes:
         torch.cuda.empty_cache()
         log("timing the backward form")
-        backward = run_backward(vca, max(3, args.steps // 2), 2)
+        backward = run_backward(vca, max(50, 5 * args.steps), 20)
         log(f"backward: {backward['value']:.0f} frames/s forward+backward, kernels "
             f"{backward['forward_kernel_ms']:.3f} + {backward['backward_kernel_ms']:.3f} ms")
 
