@@ -127,11 +127,11 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out);
  * stream and returns without waiting.  Frames are numbered after those of
  * earlier calls, and h chains across calls.  Device frames: the caller keeps
  * the buffers valid until the stream has finished the work (vca_features of
- * the call's last frame waits for it).  Host frames (frames->on_device = 0): the library copies them,
- * batch by batch, into one of two pinned staging buffers (in parallel over
- * host threads) and from there to the device on a second stream, each
- * batch's copy overlapping the analysis of the one before; the caller may
- * reuse its buffers as soon as the call returns.  Host frames are not
+ * the call's last frame waits for it).  Host frames (frames->on_device = 0):
+ * the library copies them, batch by batch, into one of two pinned staging
+ * buffers (in parallel over host threads) and from there to the device on a
+ * second stream, each batch's copy overlapping the analysis of the one
+ * before; the caller may reuse its buffers as soon as the call returns.  Host frames are not
  * accepted with VCA_F_KEEP_COEFFS (VCA_ERR_UNSUPPORTED).
  * With VCA_F_KEEP_COEFFS, n_frames must not exceed max_batch. */
 vca_status vca_analyze_frames(vca_ctx* ctx, const vca_frames* frames, int32_t n_frames);
@@ -231,10 +231,11 @@ void vca_close(vca_ctx* ctx);
 /* ------------------------------------------------------------ batched form
  * Many independent streams -- each with its own resolution, block size,
  * low-pass size, bit depth and frame count -- analysed by ONE persistent
- * kernel launch over all their tiles plus one reduction launch, both
- * captured into a hipGraph on the first call with a given frame-count
- * signature and replayed afterwards (only the per-stream descriptor tables
- * are uploaded per call).  Per stream the results are identical to a
+ * kernel launch over all their tiles (its wavefronts draw work from a
+ * device counter that a one-thread kernel zeroes first) plus one reduction
+ * launch, captured into a hipGraph on the first call with a given
+ * frame-count signature and replayed afterwards (only the per-stream
+ * descriptor tables are uploaded per call).  Per stream the results are identical to a
  * vca_ctx opened with the same configuration and fed the same frames. */
 typedef struct vca_batch vca_batch; /* opaque; owned by the library */
 
