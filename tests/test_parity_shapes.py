@@ -171,3 +171,38 @@ def test_10bit_validation(vca, w, k, plane, pos):
     with pytest.raises(VcaError):
         an.features(2, 2)
     an.close()
+
+
+@pytest.mark.parametrize("w", [32, 16])
+@pytest.mark.parametrize("res", [(1920, 1080), (3840, 2160)])
+def test_10bit_300_frames_one_launch(vca, w, res):
+    """The precision-stress workload at full size: 300 frames of 10-bit
+    4:2:0 in one launch (max_batch 300, 7.5 GB at 2160p).  Three stress
+    frames -- full-range noise, saturated edges and sign-matched worst-case
+    blocks -- repeat on the device as frames t % 3; sampled frames (with the
+    frame before them, for h) are checked against the oracle: every block's
+    DC bit-exact, H to 1e-12, the features to 1e-5."""
+    width, height = res
+    n = 300
+    print_case(test="10bit_300_frames", w=w, width=width, height=height, frames=n)
+    base = synth.stress_video(width, height, 3, cell=w, stream=300 + w)
+    planes = []
+    for p in (base.y, base.u, base.v):
+        src = torch.from_numpy(p.view(np.int16)).cuda()
+        planes.append(src[torch.arange(n, device="cuda") % 3].contiguous())
+    an = vca.Analyzer(width, height, bit_depth=10, block_size=w, max_batch=n, validate=True)
+    an.submit(*planes)
+    feats = an.features(0, n)
+    sampled = (0, 1, 2, 150, 298, 299)
+    maps = {t: an.block_maps(t, 1) for t in sampled}
+    torch.cuda.synchronize()
+    an.close()
+    del planes
+    torch.cuda.empty_cache()
+    cfg = oracle.Config(width, height, 10, w, 0)
+    for t in sampled:
+        idx = [(t - 1) % 3, t % 3] if t > 0 else [0]
+        ref = oracle.analyze(cfg, base.y[idx], base.u[idx], base.v[idx], threads=8, want_blocks=True)
+        assert_features_close(feats[t:t + 1], ref.features[-1][None])
+        assert (maps[t]["dc"].cpu().numpy()[0] == ref.block_dc[-1]).all(), f"frame {t}"
+        np.testing.assert_allclose(maps[t]["h"].cpu().numpy()[0], ref.block_h[-1], rtol=1e-12, atol=0)
