@@ -80,25 +80,44 @@ def test_scene_cut_2160p_bit_exact(vca):
         assert_features_close(feats, ref.features)
 
 
-def test_2160p_bench_launch_sampled(vca):
-    """600 UHD frames in the benchmark's launch configuration; sampled frames
-    (around every scene cut, first and last) checked against the oracle."""
-    sv = synth.scene_video(3840, 2160, 600)
-    an = vca.Analyzer(3840, 2160, block_size=32, max_batch=600)
+@pytest.fixture(scope="module")
+def uhd600():
+    """The 600-frame 2160p workload the benchmark times, once on the host (for
+    the oracle) and once on the device."""
     from synth.device import scene_to_device
-    buf = scene_to_device(sv)
-    print_case(test="bench_launch_600x2160p")
+    sv = synth.scene_video(3840, 2160, 600)
+    return sv, scene_to_device(sv)
+
+
+@pytest.mark.parametrize("mode", ["full", "k16", "downsample"])
+def test_2160p_bench_launch_sampled(vca, uhd600, mode):
+    """600 UHD frames in the benchmark's launch configuration (one launch,
+    tuned as the benchmark tunes it) for each mode it times: full DCT,
+    low-pass K = 16 and the paper's 2x downsampled low-pass.  Sampled frames
+    (around every scene cut, first and last) checked against the oracle:
+    features to 1e-5, every block's DC bit-exact and H to 1e-12."""
+    sv, buf = uhd600
+    k = 16 if mode == "k16" else 0
+    ds = mode == "downsample"
+    an = vca.Analyzer(3840, 2160, block_size=32, lowpass_k=k, max_batch=600, downsample=ds)
+    print_case(test="bench_launch_600x2160p", mode=mode)
+    an.tune(*buf.planes(), reps=1)
     an.submit(*buf.planes())
-    feats = an.features(0, 600)
+    feats = an.features(an.submitted - 600, 600)
+    first = an.submitted - 600
     sampled = (0, 1, 119, 120, 121, 240, 359, 480, 599)
-    maps = {t: an.block_maps(t, 1) for t in sampled}
+    maps = {t: an.block_maps(first + t, 1) for t in sampled}
     torch.cuda.synchronize()
     an.close()
     for t in sampled:
         t0 = max(0, t - 1)
-        ref = oracle_run(sv.frames(t0, t + 1), threads=8)
+        v = sv.frames(t0, t + 1)
+        if ds:
+            cfg = oracle.Config(3840, 2160, 8, 32, 0)
+            ref = oracle.analyze_downsampled(cfg, v.y, v.u, v.v, threads=8, want_blocks=True)
+        else:
+            ref = oracle_run(v, k=k, threads=8)
         assert_features_close(feats[t:t + 1], ref.features[-1][None])
-        # every block of the sampled frame: DC exact, H to 1e-12
         assert (maps[t]["dc"].cpu().numpy()[0] == ref.block_dc[-1]).all(), f"frame {t}"
         np.testing.assert_allclose(maps[t]["h"].cpu().numpy()[0], ref.block_h[-1], rtol=1e-12, atol=0)
 
