@@ -126,10 +126,10 @@ __global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
 }
 
 // Persistent forward kernel over strips (vca_strip.h): wavefront i of S
-// takes the runs of kRun strips i, i + S, ...
+// takes the runs of kRunLen strips i, i + S, ...
 // kDs: the planes are downsampled by two on the fly (VCA_F_DOWNSAMPLE);
 // kValidate (10-bit): samples above 1023 set the error flag.
-template <int kBits, int kW, int kK, int kDepth, bool kDs, bool kValidate>
+template <int kBits, int kW, int kK, int kDepth, bool kDs, bool kValidate, int kRunLen = kRun>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -137,7 +137,8 @@ __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerGroup][kStage];
   PackConsts<kW, kK> pc;
   pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
-  run_strips<kBits, kW, kK, kDepth, kDs, kValidate>(p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave,
+  run_strips<kBits, kW, kK, kDepth, kDs, kValidate, kRunLen>(p.geom, p.out, pc,
+                                                     blockIdx.x * kWavesPerGroup + wave,
                                          gridDim.x * kWavesPerGroup,
                                          p.n_frames * p.geom.strips_per_frame, lane, stage[wave]);
 }
@@ -182,37 +183,41 @@ __global__ __launch_bounds__(kMapsThreads) void block_maps_kernel(MapsParams p) 
 // export (tests only) always uses depth 1.
 using FwdKernel = void (*)(FwdParams);
 
-// validate (10-bit only): the validating kernel, one depth
+// validate (10-bit only): the validating kernel, one depth.  short_runs:
+// runs of one strip for launches too small to fill the device with runs of
+// kRun (one depth, the untuned default; one for validation).
 template <int B, int W, int K, bool kDs>
-FwdKernel pick_depth(int depth, bool validate) {
+FwdKernel pick_depth(int depth, bool validate, bool short_runs) {
   if constexpr (B != 8) {
-    if (validate) return strip_kernel<B, W, K, 1, kDs, true>;
+    if (validate) return short_runs ? strip_kernel<B, W, K, 1, kDs, true, 1> : strip_kernel<B, W, K, 1, kDs, true>;
   }
+  if (short_runs) return strip_kernel<B, W, K, kDefaultDepth, kDs, false, 1>;
   if (depth == 1) return strip_kernel<B, W, K, 1, kDs, false>;
   if (depth >= 4) return strip_kernel<B, W, K, 4, kDs, false>;   // capped at the units per strip
   return strip_kernel<B, W, K, 2, kDs, false>;
 }
 
 template <int B, int W>
-FwdKernel pick_k(int K, bool keep, bool ds, int depth, bool v) {
-  if (ds) return K == W ? pick_depth<B, W, W, true>(depth, v) : nullptr;
-  if (K == W) return keep ? fwd_kernel<B, W, W, true, 1> : pick_depth<B, W, W, false>(depth, v);
-  if (K == W / 2) return keep ? fwd_kernel<B, W, W / 2, true, 1> : pick_depth<B, W, W / 2, false>(depth, v);
-  if (K == W / 4) return keep ? fwd_kernel<B, W, W / 4, true, 1> : pick_depth<B, W, W / 4, false>(depth, v);
+FwdKernel pick_k(int K, bool keep, bool ds, int depth, bool v, bool sr) {
+  if (ds) return K == W ? pick_depth<B, W, W, true>(depth, v, sr) : nullptr;
+  if (K == W) return keep ? fwd_kernel<B, W, W, true, 1> : pick_depth<B, W, W, false>(depth, v, sr);
+  if (K == W / 2) return keep ? fwd_kernel<B, W, W / 2, true, 1> : pick_depth<B, W, W / 2, false>(depth, v, sr);
+  if (K == W / 4) return keep ? fwd_kernel<B, W, W / 4, true, 1> : pick_depth<B, W, W / 4, false>(depth, v, sr);
   return nullptr;
 }
 
 template <int B>
-FwdKernel pick_w(int w, int K, bool keep, bool ds, int depth, bool v) {
-  if (w == 32) return pick_k<B, 32>(K, keep, ds, depth, v);
-  if (w == 16) return pick_k<B, 16>(K, keep, ds, depth, v);
-  if (w == 8) return pick_k<B, 8>(K, keep, ds, depth, v);
+FwdKernel pick_w(int w, int K, bool keep, bool ds, int depth, bool v, bool sr) {
+  if (w == 32) return pick_k<B, 32>(K, keep, ds, depth, v, sr);
+  if (w == 16) return pick_k<B, 16>(K, keep, ds, depth, v, sr);
+  if (w == 8) return pick_k<B, 8>(K, keep, ds, depth, v, sr);
   return nullptr;
 }
 
-FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, bool ds, int depth, bool validate) {
-  return bits == 8 ? pick_w<8>(w, K, keep, ds, depth, false)
-                   : (bits == 10 ? pick_w<10>(w, K, keep, ds, depth, validate) : nullptr);
+FwdKernel select_fwd_kernel(int bits, int w, int K, bool keep, bool ds, int depth, bool validate,
+                            bool short_runs = false) {
+  return bits == 8 ? pick_w<8>(w, K, keep, ds, depth, false, short_runs)
+                   : (bits == 10 ? pick_w<10>(w, K, keep, ds, depth, validate, short_runs) : nullptr);
 }
 
 }  // namespace
@@ -334,9 +339,14 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
 // Enqueues one forward launch with the given ring depth and workgroup cap.
 vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu) {
   const bool keep = ctx->coeffs != nullptr;
+  // A launch whose runs of kRun strips would give fewer than four
+  // wavefronts per CU (a frame or two at 2160p) takes runs of one strip, so
+  // that a single frame spreads over the device instead of 47 workgroups.
+  const int64_t strips = (int64_t)fp.n_frames * fp.geom.strips_per_frame;
+  const bool short_runs = !keep && (strips + kRun - 1) / kRun < 4 * (int64_t)ctx->num_cus;
   FwdKernel kern =
       select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth,
-                        (ctx->cfg.flags & VCA_F_VALIDATE) != 0);
+                        (ctx->cfg.flags & VCA_F_VALIDATE) != 0, short_runs);
   if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
   // Persistent grid: at most as many workgroups as can be resident at once,
   // so no workgroup waits for another to drain before it starts its loop.
@@ -345,7 +355,7 @@ vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_p
   resident = std::max(1, resident);
   if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
   const int64_t waves = keep ? (int64_t)fp.n_frames * fp.tiles_per_frame
-                             : ((int64_t)fp.n_frames * fp.geom.strips_per_frame + kRun - 1) / kRun;
+                             : short_runs ? strips : (strips + kRun - 1) / kRun;
   const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);

@@ -231,8 +231,9 @@ __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, 
   return d;
 }
 
-// Strips are taken in runs of kRun consecutive strip ids: this wavefront
-// runs run0, run0 + run_stride, ... (strips below `end`).  Consecutive strips
+// Strips are taken in runs of kRunLen consecutive strip ids (kRun unless a
+// launch is too small to fill the device with runs that long): this
+// wavefront runs run0, run0 + run_stride, ... (strips below `end`).  Consecutive strips
 // own consecutive output ranges when w = 32 (a tile is a block and the tile
 // grid is the block grid), so a run's H and DC are gathered into the lanes
 // (lane i = block i of the run) and stored with one store each at the run's
@@ -257,7 +258,8 @@ constexpr int kSegCols = 128;   // block columns of a staged segment (w = 16, 8)
 // LDS bytes of one wavefront's staging area (FP64 H, then int32 DC).
 constexpr int stage_bytes(int w) { return w == 32 ? 0 : (kTile / w) * kSegCols * 12; }
 
-template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false, bool kValidate = false>
+template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false, bool kValidate = false,
+          int kRunLen = kRun>
 __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
                                            const PackConsts<kW, kK>& pc, int run0, int run_stride,
                                            int end, int lane, uint8_t* stage) {
@@ -281,10 +283,10 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   };
   // the strip after `id` in this wavefront's sequence
   auto next_id = [&](int id) {
-    return (id + 1) % kRun != 0 ? id + 1 : id + 1 + (run_stride - 1) * kRun;
+    return (id + 1) % kRunLen != 0 ? id + 1 : id + 1 + (run_stride - 1) * kRunLen;
   };
 
-  int id = run0 * kRun;
+  int id = run0 * kRunLen;
   if (id >= end) return;
   StripWork S = decode_strip<kBits, kW, kDs>(G, id);
   LaneOffsets O = lane_offsets<kBits, kW, kDs>(S, lane);
@@ -372,7 +374,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
           if (t == u * kPack + qq) dcrun = dcv;
         }
       }
-      if (!more || id2 % kRun == 0) {   // the run ends with this strip
+      if (!more || id2 % kRunLen == 0) {   // the run ends with this strip
         if (lane < S.out0 - run_out0 + S.n) {
           out.blk_h[run_out0 + lane] = hrun;
           out.blk_dc[run_out0 + lane] = dcrun + kDcAdd;
@@ -382,7 +384,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     }
     if constexpr (kW != 32) {
       // copy the segment out when the next strip leaves it
-      const bool leave = !more || id2 % kRun == 0 || S2.row0 != S.row0 ||
+      const bool leave = !more || id2 % kRunLen == 0 || S2.row0 != S.row0 ||
                          S2.out0 - run_out0 + kStrip * kBpt > kSegCols;
       if (leave) {
         const int cols = S.out0 - run_out0 + (S.n - 1) * kBpt + S.vc_last;
