@@ -13,7 +13,7 @@
 
 namespace vca {
 
-constexpr int kReduceThreads = 256;
+constexpr int kReduceThreads = 1024;
 
 struct ReduceParams {
   const double* blk_h;     // block energies of frame 0 of the launch
