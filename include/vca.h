@@ -210,7 +210,9 @@ vca_status vca_get_timing(vca_ctx* ctx, vca_timing* out, int32_t reset);
  * bit depth, w, K, resolution); later vca_open calls with the same key use
  * it.  Features, h state and frame numbering are unchanged; the per-block
  * exports of the previous call are overwritten.  Not available with
- * VCA_F_KEEP_COEFFS (VCA_ERR_STATE). */
+ * VCA_F_KEEP_COEFFS (VCA_ERR_STATE).  Launches too small to fill the device
+ * (about two 2160p frames or fewer) take runs of one strip at the untuned
+ * depth instead; the tuned shape applies to all others. */
 vca_status vca_tune(vca_ctx* ctx, const vca_frames* frames, int32_t n_frames, int32_t reps);
 
 /* Launch shape in use: tiles in flight per wavefront (0: untuned default),

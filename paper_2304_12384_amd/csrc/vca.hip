@@ -337,13 +337,17 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
 }
 
 // Enqueues one forward launch with the given ring depth and workgroup cap.
-vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu) {
+// allow_short = false: always runs of kRun (the autotuner times those; the
+// tuned depth applies to them only).
+vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu,
+                      bool allow_short = true) {
   const bool keep = ctx->coeffs != nullptr;
   // A launch whose runs of kRun strips would give fewer than four
   // wavefronts per CU (a frame or two at 2160p) takes runs of one strip, so
   // that a single frame spreads over the device instead of 47 workgroups.
   const int64_t strips = (int64_t)fp.n_frames * fp.geom.strips_per_frame;
-  const bool short_runs = !keep && (strips + kRun - 1) / kRun < 4 * (int64_t)ctx->num_cus;
+  const bool short_runs =
+      allow_short && !keep && (strips + kRun - 1) / kRun < 4 * (int64_t)ctx->num_cus;
   FwdKernel kern =
       select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth,
                         (ctx->cfg.flags & VCA_F_VALIDATE) != 0, short_runs);
@@ -771,13 +775,13 @@ vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0) != hipSuccess)
       resident = 1;
     for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
-      st = launch_fwd(ctx, fp, depth, gpc);   // warm-up
+      st = launch_fwd(ctx, fp, depth, gpc, false);   // warm-up
       if (st != VCA_OK) break;
       if (hipEventRecord(a, ctx->stream) != hipSuccess) {
         st = fail(ctx, VCA_ERR_DEVICE, "hipEventRecord");
         break;
       }
-      for (int r = 0; r < reps && st == VCA_OK; r++) st = launch_fwd(ctx, fp, depth, gpc);
+      for (int r = 0; r < reps && st == VCA_OK; r++) st = launch_fwd(ctx, fp, depth, gpc, false);
       if (st != VCA_OK) break;
       if (hipEventRecord(b, ctx->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
         st = fail(ctx, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
