@@ -13,7 +13,8 @@
 
 namespace vca {
 
-constexpr int kReduceThreads = 1024;
+constexpr int kReduceThreads = 1024;   // a power of two
+static_assert((kReduceThreads & (kReduceThreads - 1)) == 0, "first_at uses a mask");
 
 struct ReduceParams {
   const double* blk_h;     // block energies of frame 0 of the launch
@@ -39,12 +40,23 @@ __device__ inline void reduce_frame(const ReduceParams& p, int f) {
   const double* prev = f > 0 ? H - p.per_frame : p.state_in;
   double s[7] = {0, 0, 0, 0, 0, 0, 0};   // H_Y H_U H_V L_Y L_U L_V dH
   const int e0 = p.cnt[0], e1 = p.cnt[0] + p.cnt[1];
-  for (int b = t; b < p.per_frame; b += kReduceThreads) {
-    const int P = b < e0 ? 0 : (b < e1 ? 1 : 2);
+  // The thread's blocks b = t, t + N, ... (N = kReduceThreads), plane by
+  // plane: each sum sees its blocks in the same order as one loop over all
+  // of them would, without selecting the plane per block.
+  auto first_at = [&](int e) { return e + ((t - e) & (kReduceThreads - 1)); };
+  for (int b = t; b < e0; b += kReduceThreads) {
     const double hb = H[b];
-    s[P] += hb;
-    s[3 + P] += sqrt((double)DC[b]);
-    if (P == 0 && prev) s[6] += fabs(hb - prev[b]);
+    s[0] += hb;
+    s[3] += sqrt((double)DC[b]);
+    if (prev) s[6] += fabs(hb - prev[b]);
+  }
+  for (int b = first_at(e0); b < e1; b += kReduceThreads) {
+    s[1] += H[b];
+    s[4] += sqrt((double)DC[b]);
+  }
+  for (int b = first_at(e1); b < p.per_frame; b += kReduceThreads) {
+    s[2] += H[b];
+    s[5] += sqrt((double)DC[b]);
   }
 #pragma unroll
   for (int q = 0; q < 7; q++) red[q][t] = s[q];
