@@ -56,7 +56,8 @@ typedef enum {
 
 /* vca_config.flags */
 #define VCA_F_KEEP_COEFFS 0x1u /* keep the K x K int16 coefficients of the last call (tests) */
-#define VCA_F_VALIDATE 0x2u    /* 10-bit: count samples above 1023; vca_features then fails  */
+#define VCA_F_VALIDATE 0x2u    /* 10-bit: mark each frame holding a sample above 1023;        \
+                                  vca_features fails for a range that includes such a frame */
 #define VCA_F_TIMING 0x4u      /* record HIP events around every kernel launch (vca_timing)  */
 #define VCA_F_DOWNSAMPLE 0x8u  /* the paper's own low-pass option (Section 2, (3)): every     \
                                   plane is downsampled by two -- each sample the mean of a    \
@@ -79,7 +80,8 @@ typedef struct {
   int32_t device;        /* HIP device ordinal                                             */
   uint32_t flags;        /* VCA_F_*                                                        */
   int32_t max_batch;     /* frames per internal launch (scratch sizing); 0 = 256           */
-  int32_t feature_capacity; /* frames of features kept on the device (ring); 0 = 65536     */
+  int32_t feature_capacity; /* frames of features kept in the ring; 0 = 65536; must be    \
+                               >= max_batch (after defaults), else VCA_ERR_INVALID_ARG    */
 } vca_config;
 
 /* A run of consecutive frames of one video.
@@ -158,7 +160,9 @@ vca_status vca_read_yuv(const char* path, int32_t width, int32_t height, int32_t
  * copies the features of frames [first_frame, first_frame + count) into
  * out_host (count records).
  * VCA_ERR_STATE if a frame was not yet submitted or has left the ring, or if
- * VCA_F_VALIDATE found an out-of-range sample. */
+ * VCA_F_VALIDATE found a sample above 1023 in one of the requested frames
+ * (each frame carries its own mark, so frames of other calls do not
+ * matter). */
 vca_status vca_features(vca_ctx* ctx, int64_t first_frame, int32_t count,
                         vca_frame_features* out_host);
 
@@ -166,6 +170,9 @@ vca_status vca_features(vca_ctx* ctx, int64_t first_frame, int32_t count,
  * copies the coefficients of frame `frame` of the most recent
  * vca_analyze_frames call: blocks of Y, then U, then V, each in raster order;
  * per block K x K int16, row-major (row = vertical frequency), DC included.
+ * All three planes of the frame come in one call (the frame's block list is
+ * one array, as for vca_block_stats; vca_block_counts gives the plane
+ * boundaries), so there is no plane argument.
  * capacity is the number of int16 elements out_host can hold. */
 vca_status vca_block_coeffs(vca_ctx* ctx, int64_t frame, int16_t* out_host, size_t capacity);
 
@@ -209,7 +216,9 @@ vca_status vca_get_timing(vca_ctx* ctx, vca_timing* out, int32_t reset);
  * the environment variable VCA_TUNE_CACHE, if set) under the key (device,
  * bit depth, w, K, resolution); later vca_open calls with the same key use
  * it.  Features, h state and frame numbering are unchanged; the per-block
- * exports of the previous call are overwritten.  Not available with
+ * results of the previous call are overwritten, so vca_block_stats and
+ * vca_block_maps return VCA_ERR_STATE until the next analysis.  The tuning
+ * launches do not validate samples.  Not available with
  * VCA_F_KEEP_COEFFS (VCA_ERR_STATE).  Launches too small to fill the device
  * (about two 2160p frames or fewer) take runs of one strip at the untuned
  * depth instead; the tuned shape applies to all others. */
@@ -256,8 +265,10 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
 
 /* Features of frames [first, first + count) of stream `stream`; waits for
  * the round that produced frame first + count - 1 (not for later rounds).
- * VCA_ERR_STATE if that stream was opened with VCA_F_VALIDATE and a 10-bit
- * sample above 1023 was submitted to it (other streams are unaffected). */
+ * VCA_ERR_STATE if that stream was opened with VCA_F_VALIDATE and one of
+ * the requested frames holds a 10-bit sample above 1023 (other frames and
+ * streams are unaffected).  The stream's feature_capacity must be at least
+ * its max_batch (vca_open_batch returns VCA_ERR_INVALID_ARG otherwise). */
 vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32_t count,
                               vca_frame_features* out_host);
 
@@ -267,9 +278,9 @@ vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32
  * (sum of count[r] records, caller-owned).  Waits once, for the latest round
  * any request needs.  Every request is checked before anything is copied
  * (VCA_ERR_INVALID_ARG for a bad stream or range, VCA_ERR_STATE for frames
- * not submitted or out of the ring); a stream whose validation flag is set
- * gives VCA_ERR_STATE after the records of the requests before it are
- * written. */
+ * not submitted or out of the ring); a stream with a validation mark on a requested frame
+ * gives VCA_ERR_STATE (a requested frame of it holds a 10-bit sample above
+ * 1023) after the records of the requests before it are written. */
 vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32_t* streams,
                                    const int64_t* first, const int32_t* count,
                                    vca_frame_features* out_host);

@@ -6,9 +6,10 @@
 // definitions implemented are stated in include/vca.h.
 //
 // Kernels:
-//   fwd_kernel     persistent grid over all 32 x 32 tiles of all frames of a
-//                  launch; one wavefront per tile (vca_tile.h) with a
-//                  register ring of tiles in flight; per-block H and DC out.
+//   strip_kernel   persistent grid over the strips of 32 x 32 tiles of all
+//                  frames of a launch (vca_strip.h): wavefronts walk runs of
+//                  strips with a register ring of tiles in flight; per-block
+//                  H and DC out (and, for tests, the K x K coefficients).
 //   reduce_kernel  one workgroup per frame (vca_reduce.h).
 // Launch shape (ring depth, workgroups per CU) comes from vca_tune's
 // measurements when the context was tuned, else from fixed defaults.
@@ -39,97 +40,27 @@ namespace {
 constexpr int kWavesPerGroup = 4;   // wavefronts per workgroup
 constexpr int kGroupThreads = 64 * kWavesPerGroup;
 constexpr int kDefaultDepth = 2;    // tiles in flight per wavefront when untuned
+constexpr int kDefaultMaxBatch = 256;     // vca_config.max_batch = 0
+constexpr int kDefaultCapacity = 65536;   // vca_config.feature_capacity = 0
+
+int effective(int32_t v, int32_t dflt) { return v == 0 ? dflt : v; }
 
 struct FwdParams {
-  const uint8_t* plane[3];
-  int32_t pitch[3];        // bytes between rows
-  int64_t fstride[3];      // bytes between frames
-  int32_t nbx[3], nby[3];  // blocks per row / column of each plane
-  int32_t ntx[3];          // tiles per row
-  int32_t tcnt[3];         // tiles per plane
-  int32_t boff[3];         // index of the plane's first block within a frame
-  int32_t tiles_per_frame;
-  int32_t per_frame;       // blocks per frame
-  FastDiv div_tpf;         // / tiles_per_frame
-  FastDiv div_ntx[3];      // / ntx[P]
   int32_t n_frames;
-  StripGeom geom;          // the same frames as strips (strip kernel)
-  const v4i* tab_b1;
-  const v4i* tab_a2;
-  const double* tab_w;
-  const v4i* tab_b1p;      // packed layout (K < w): w / K stage-1 operands per lane
-  const double* tab_wp;    // packed layout weights
+  StripGeom geom;          // the launch's frames as strips
+  const v4i* tab_a2;       // stage-2 operand per lane
+  const v4i* tab_b1p;      // w / K stage-1 operands per lane (packed layout; K = w: one)
+  const double* tab_wp;    // weights of the packed layout
   TileOut out;
 };
-
-// Tile `id` of a launch (frame-major, then Y, U, V, then raster order).
-template <int kBits, int kW>
-__device__ inline TileWork decode_tile(const FwdParams& p, int id) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  constexpr int kBpt = kTile / kW;
-  const int f = (int)fastdiv((uint32_t)id, p.div_tpf);
-  int t = id - f * p.tiles_per_frame;
-  int P = 0;
-  if (t >= p.tcnt[0]) {
-    t -= p.tcnt[0];
-    P = 1;
-    if (t >= p.tcnt[1]) {
-      t -= p.tcnt[1];
-      P = 2;
-    }
-  }
-  const int ty = (int)fastdiv((uint32_t)t, p.div_ntx[P]);
-  const int tx = t - ty * p.ntx[P];
-  const int by0 = ty * kBpt, bx0 = tx * kBpt;
-  TileWork w;
-  w.pitch = p.pitch[P];
-  w.base = p.plane[P] + f * p.fstride[P] + (int64_t)by0 * kW * w.pitch + bx0 * kW * kBps;
-  w.vr = min(kBpt, p.nby[P] - by0);
-  w.vc = min(kBpt, p.nbx[P] - bx0);
-  w.out0 = f * p.per_frame + p.boff[P] + by0 * p.nbx[P] + bx0;
-  w.out_row = p.nbx[P];
-  return w;
-}
-
-// Persistent forward kernel: each wavefront walks tiles id, id + S, ...
-// (S = all wavefronts of the grid), keeping kDepth tiles in flight in a
-// register ring (the loop body is unrolled over the ring, so no registers
-// move).
-template <int kBits, int kW, int kK, bool kKeep, int kDepth>
-__global__ __launch_bounds__(kGroupThreads) void fwd_kernel(FwdParams p) {
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  TileConsts<kW, kK> tc;
-  tc.load(p.tab_b1, p.tab_a2, p.tab_w, lane);
-
-  const int total = p.n_frames * p.tiles_per_frame;
-  const int stride = gridDim.x * kWavesPerGroup;
-  int id = blockIdx.x * kWavesPerGroup + wave;
-  TileData ring[kDepth];
-#pragma unroll
-  for (int s = 0; s < kDepth; s++) {
-    const int nid = id + s * stride;
-    if (nid < total) ring[s] = load_tile<kBits, kW>(decode_tile<kBits, kW>(p, nid), lane);
-  }
-  while (id < total) {
-#pragma unroll
-    for (int s = 0; s < kDepth; s++) {
-      if (id < total) {
-        const TileData d = ring[s];
-        const int nid = id + kDepth * stride;
-        if (nid < total) ring[s] = load_tile<kBits, kW>(decode_tile<kBits, kW>(p, nid), lane);
-        fwd_tile<kBits, kW, kK, kKeep>(p.out, tc, d, decode_tile<kBits, kW>(p, id), lane);
-        id += stride;
-      }
-    }
-  }
-}
 
 // Persistent forward kernel over strips (vca_strip.h): wavefront i of S
 // takes the runs of kRunLen strips i, i + S, ...
 // kDs: the planes are downsampled by two on the fly (VCA_F_DOWNSAMPLE);
-// kValidate (10-bit): samples above 1023 set the error flag.
-template <int kBits, int kW, int kK, int kDepth, bool kDs, bool kValidate, int kRunLen = kRun>
+// kValidate (10-bit): samples above 1023 mark their frame; kKeep: the K x K
+// coefficients of every block are exported as well (VCA_F_KEEP_COEFFS).
+template <int kBits, int kW, int kK, int kDepth, bool kDs, bool kValidate, int kRunLen = kRun,
+          bool kKeep = false>
 __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -137,10 +68,9 @@ __global__ __launch_bounds__(kGroupThreads) void strip_kernel(FwdParams p) {
   __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerGroup][kStage];
   PackConsts<kW, kK> pc;
   pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
-  run_strips<kBits, kW, kK, kDepth, kDs, kValidate, kRunLen>(p.geom, p.out, pc,
-                                                     blockIdx.x * kWavesPerGroup + wave,
-                                         gridDim.x * kWavesPerGroup,
-                                         p.n_frames * p.geom.strips_per_frame, lane, stage[wave]);
+  run_strips<kBits, kW, kK, kDepth, kDs, kValidate, kRunLen, kKeep>(
+      p.geom, p.out, pc, blockIdx.x * kWavesPerGroup + wave, gridDim.x * kWavesPerGroup,
+      p.n_frames * p.geom.strips_per_frame, lane, stage[wave]);
 }
 
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceParams p) {
@@ -179,15 +109,24 @@ __global__ __launch_bounds__(kMapsThreads) void block_maps_kernel(MapsParams p) 
   }
 }
 
-// Kernel for (bit depth, w, K, coefficient export, ring depth).  Coefficient
-// export (tests only) always uses depth 1.
+// Kernel for (bit depth, w, K, downsampling, ring depth, validation, run
+// length, coefficient export).
 using FwdKernel = void (*)(FwdParams);
 
 // validate (10-bit only): the validating kernel, one depth.  short_runs:
 // runs of one strip for launches too small to fill the device with runs of
-// kRun (one depth, the untuned default; one for validation).
+// kRun (one depth, the untuned default; one for validation).  keep: the
+// exporting variant of the same walk (runs as the launch size picks them,
+// ring depth 4 or the untuned default, validation decided at run time).
 template <int B, int W, int K, bool kDs>
-FwdKernel pick_depth(int depth, bool validate, bool short_runs) {
+FwdKernel pick_depth(int depth, bool validate, bool short_runs, bool keep) {
+  if constexpr (!kDs) {
+    if (keep)
+      return short_runs ? strip_kernel<B, W, K, kDefaultDepth, false, (B != 8), 1, true>
+                        : strip_kernel<B, W, K, 4, false, (B != 8), kRun, true>;
+  } else {
+    if (keep) return nullptr;
+  }
   if constexpr (B != 8) {
     if (validate) return short_runs ? strip_kernel<B, W, K, 1, kDs, true, 1> : strip_kernel<B, W, K, 1, kDs, true>;
   }
@@ -199,10 +138,10 @@ FwdKernel pick_depth(int depth, bool validate, bool short_runs) {
 
 template <int B, int W>
 FwdKernel pick_k(int K, bool keep, bool ds, int depth, bool v, bool sr) {
-  if (ds) return K == W ? pick_depth<B, W, W, true>(depth, v, sr) : nullptr;
-  if (K == W) return keep ? fwd_kernel<B, W, W, true, 1> : pick_depth<B, W, W, false>(depth, v, sr);
-  if (K == W / 2) return keep ? fwd_kernel<B, W, W / 2, true, 1> : pick_depth<B, W, W / 2, false>(depth, v, sr);
-  if (K == W / 4) return keep ? fwd_kernel<B, W, W / 4, true, 1> : pick_depth<B, W, W / 4, false>(depth, v, sr);
+  if (ds) return K == W ? pick_depth<B, W, W, true>(depth, v, sr, keep) : nullptr;
+  if (K == W) return pick_depth<B, W, W, false>(depth, v, sr, keep);
+  if (K == W / 2) return pick_depth<B, W, W / 2, false>(depth, v, sr, keep);
+  if (K == W / 4) return pick_depth<B, W, W / 4, false>(depth, v, sr, keep);
   return nullptr;
 }
 
@@ -233,16 +172,15 @@ struct vca_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   // device tables and state
-  v4i* tab_b1 = nullptr;
   v4i* tab_a2 = nullptr;
-  double* tab_w = nullptr;
   v4i* tab_b1p = nullptr;
   double* tab_wp = nullptr;
   double* blk_h = nullptr;
   int32_t* blk_dc = nullptr;
   int16_t* coeffs = nullptr;
-  int32_t* err_flag = nullptr;     // device view of err_host
-  int32_t* err_host = nullptr;     // pinned, mapped
+  int32_t* frame_err = nullptr;    // per frame of a launch: validation marks (device)
+  int32_t* err_ring = nullptr;     // device view of err_ring_host
+  int32_t* err_ring_host = nullptr;   // pinned, mapped: [feature_capacity] marks
   double* state[2] = {nullptr, nullptr};
   float* ring = nullptr;           // device view of ring_host
   float* ring_host = nullptr;      // pinned, mapped: [feature_capacity][7]
@@ -301,37 +239,22 @@ vca_status dev_alloc(vca_ctx* c, T** p, size_t count) {
 
 // Forward-launch parameters for frames [done, done + n) of a call.
 FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done, int32_t n) {
-  const Geometry& g = ctx->geo;
   FwdParams fp{};
   const uint8_t* base[3] = {static_cast<const uint8_t*>(fr->y), static_cast<const uint8_t*>(fr->u),
                             static_cast<const uint8_t*>(fr->v)};
   const int64_t fs[3] = {fr->fstride_y, fr->fstride_uv, fr->fstride_uv};
   const int64_t pt[3] = {fr->pitch_y, fr->pitch_uv, fr->pitch_uv};
-  for (int P = 0; P < 3; P++) {
-    fp.plane[P] = base[P] + fs[P] * done;
-    fp.pitch[P] = (int32_t)pt[P];
-    fp.fstride[P] = fs[P];
-    fp.nbx[P] = g.nbx[P];
-    fp.nby[P] = g.nby[P];
-    fp.ntx[P] = g.ntx[P];
-    fp.tcnt[P] = g.tcnt[P];
-    fp.boff[P] = g.boff[P];
-    fp.div_ntx[P] = make_fastdiv((uint32_t)g.ntx[P]);
-  }
-  fp.geom = make_strip_geom(g, fp.plane, fs, pt, 0);
-  fp.tiles_per_frame = g.tiles_per_frame;
-  fp.per_frame = g.per_frame;
-  fp.div_tpf = make_fastdiv((uint32_t)g.tiles_per_frame);
+  const uint8_t* first[3];
+  for (int P = 0; P < 3; P++) first[P] = base[P] + fs[P] * done;
+  fp.geom = make_strip_geom(ctx->geo, first, fs, pt, 0);
   fp.n_frames = n;
-  fp.tab_b1 = ctx->tab_b1;
   fp.tab_a2 = ctx->tab_a2;
-  fp.tab_w = ctx->tab_w;
   fp.tab_b1p = ctx->tab_b1p;
   fp.tab_wp = ctx->tab_wp;
   fp.out.blk_h = ctx->blk_h;
   fp.out.blk_dc = ctx->blk_dc;
   fp.out.coeffs = ctx->coeffs;
-  fp.out.err_flag = ctx->err_flag;
+  fp.out.err_flag = ctx->frame_err;
   fp.out.validate = (ctx->cfg.flags & VCA_F_VALIDATE) && ctx->cfg.bit_depth == 10 ? 1 : 0;
   return fp;
 }
@@ -340,17 +263,17 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
 // allow_short = false: always runs of kRun (the autotuner times those; the
 // tuned depth applies to them only).
 vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu,
-                      bool allow_short = true) {
+                      bool allow_short = true, bool validate = true) {
   const bool keep = ctx->coeffs != nullptr;
   // A launch whose runs of kRun strips would give fewer than four
   // wavefronts per CU (a frame or two at 2160p) takes runs of one strip, so
   // that a single frame spreads over the device instead of 47 workgroups.
+  // The coefficient export follows the same rule, so it shows both walks.
   const int64_t strips = (int64_t)fp.n_frames * fp.geom.strips_per_frame;
-  const bool short_runs =
-      allow_short && !keep && (strips + kRun - 1) / kRun < 4 * (int64_t)ctx->num_cus;
+  const bool short_runs = allow_short && (strips + kRun - 1) / kRun < 4 * (int64_t)ctx->num_cus;
   FwdKernel kern =
       select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth,
-                        (ctx->cfg.flags & VCA_F_VALIDATE) != 0, short_runs);
+                        validate && (ctx->cfg.flags & VCA_F_VALIDATE) != 0, short_runs);
   if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
   // Persistent grid: at most as many workgroups as can be resident at once,
   // so no workgroup waits for another to drain before it starts its loop.
@@ -358,8 +281,7 @@ vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_p
   HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0));
   resident = std::max(1, resident);
   if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
-  const int64_t waves = keep ? (int64_t)fp.n_frames * fp.tiles_per_frame
-                             : short_runs ? strips : (strips + kRun - 1) / kRun;
+  const int64_t waves = short_runs ? strips : (strips + kRun - 1) / kRun;
   const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
   const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);
@@ -410,13 +332,12 @@ void vca_close(vca_ctx* ctx) {
   {
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    void* bufs[] = {ctx->tab_b1,   ctx->tab_a2,   ctx->tab_w,    ctx->tab_b1p,
-                    ctx->tab_wp,   ctx->blk_h,    ctx->blk_dc,   ctx->coeffs,
-                    ctx->state[0], ctx->state[1]};
+    void* bufs[] = {ctx->tab_a2,   ctx->tab_b1p,  ctx->tab_wp,   ctx->blk_h,    ctx->blk_dc,
+                    ctx->coeffs,   ctx->state[0], ctx->state[1], ctx->frame_err};
     for (void* b : bufs)
       if (b) (void)hipFree(b);
     if (ctx->ring_host) (void)hipHostFree(ctx->ring_host);
-    if (ctx->err_host) (void)hipHostFree(ctx->err_host);
+    if (ctx->err_ring_host) (void)hipHostFree(ctx->err_ring_host);
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     ctx->done.destroy();
     if (ctx->copy_stream) (void)hipStreamSynchronize(ctx->copy_stream);
@@ -437,6 +358,9 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   *out = nullptr;
   vca_status s = check_config(cfg);
   if (s != VCA_OK) return s;
+  // one launch's frames must not share ring slots
+  if (effective(cfg->feature_capacity, kDefaultCapacity) < effective(cfg->max_batch, kDefaultMaxBatch))
+    return VCA_ERR_INVALID_ARG;
 
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return VCA_ERR_DEVICE;
@@ -445,8 +369,8 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   vca_ctx* c = new (std::nothrow) vca_ctx();
   if (!c) return VCA_ERR_OOM;
   c->cfg = *cfg;
-  if (c->cfg.max_batch == 0) c->cfg.max_batch = 256;
-  if (c->cfg.feature_capacity == 0) c->cfg.feature_capacity = 65536;
+  c->cfg.max_batch = effective(c->cfg.max_batch, kDefaultMaxBatch);
+  c->cfg.feature_capacity = effective(c->cfg.feature_capacity, kDefaultCapacity);
   c->geo.init(*cfg);
   if ((int64_t)c->cfg.max_batch * c->geo.per_frame > (int64_t)INT32_MAX / 2) {
     delete c;
@@ -473,20 +397,21 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   if (c->done.init(1) != hipSuccess) return bail(VCA_ERR_DEVICE);
   const size_t mb = (size_t)c->cfg.max_batch;
   const int K = c->geo.K;
-  if ((s = dev_alloc(c, &c->tab_b1, 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_a2, 64)) != VCA_OK) return bail(s);
-  if ((s = dev_alloc(c, &c->tab_w, 16 * 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_b1p, (size_t)(cfg->block_size / K) * 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->tab_wp, 16 * 64)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->blk_h, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->blk_dc, mb * c->geo.per_frame)) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->state[0], c->geo.cnt[0])) != VCA_OK) return bail(s);
   if ((s = dev_alloc(c, &c->state[1], c->geo.cnt[0])) != VCA_OK) return bail(s);
+  if ((s = dev_alloc(c, &c->frame_err, mb)) != VCA_OK) return bail(s);
+  if (hipMemset(c->frame_err, 0, mb * sizeof(int32_t)) != hipSuccess) return bail(VCA_ERR_DEVICE);
   if (host_mapped_alloc((size_t)c->cfg.feature_capacity * 7 * sizeof(float),
                         reinterpret_cast<void**>(&c->ring_host),
                         reinterpret_cast<void**>(&c->ring)) != hipSuccess ||
-      host_mapped_alloc(sizeof(int32_t), reinterpret_cast<void**>(&c->err_host),
-                        reinterpret_cast<void**>(&c->err_flag)) != hipSuccess)
+      host_mapped_alloc((size_t)c->cfg.feature_capacity * sizeof(int32_t),
+                        reinterpret_cast<void**>(&c->err_ring_host),
+                        reinterpret_cast<void**>(&c->err_ring)) != hipSuccess)
     return bail(VCA_ERR_OOM);
   if (cfg->flags & VCA_F_KEEP_COEFFS)
     if ((s = dev_alloc(c, &c->coeffs, mb * c->geo.per_frame * K * K)) != VCA_OK) return bail(s);
@@ -497,10 +422,7 @@ vca_status vca_open(const vca_config* cfg, void* hip_stream, vca_ctx** out) {
   std::vector<int8_t> b1p;
   std::vector<double> wtp;
   build_packed_tables(cfg->block_size, K, b1p, wtp);
-  if (hipMemcpy(c->tab_b1, b1.data(), b1.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->tab_a2, a2.data(), a2.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->tab_w, wt.data(), wt.size() * sizeof(double), hipMemcpyHostToDevice) !=
-          hipSuccess ||
+  if (hipMemcpy(c->tab_a2, a2.data(), a2.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_b1p, b1p.data(), b1p.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->tab_wp, wtp.data(), wtp.size() * sizeof(double), hipMemcpyHostToDevice) !=
           hipSuccess)
@@ -553,6 +475,8 @@ vca_status analyze_device(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames) 
     rp.state_in = ctx->has_prev ? ctx->state[ctx->cur_state] : nullptr;
     rp.state_out = ctx->state[ctx->cur_state ^ 1];
     rp.ring = ctx->ring;
+    rp.frame_err = (cfg.flags & VCA_F_VALIDATE) ? ctx->frame_err : nullptr;
+    rp.err_ring = ctx->err_ring;
     rp.first_frame = ctx->submitted;
     rp.capacity = cfg.feature_capacity;
     for (int P = 0; P < 3; P++) {
@@ -767,21 +691,24 @@ vca_status vca_tune(vca_ctx* ctx, const vca_frames* fr, int32_t n_frames, int32_
   LaunchChoice best;
   best.ms = 1e30;
   vca_status st = VCA_OK;
+  // the tuning launches overwrite the per-block results of the last call
+  ctx->last_chunk_len = 0;
   for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
     int resident = 0;
     FwdKernel kern =
         select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, false, ctx->geo.ds, depth,
-                          (ctx->cfg.flags & VCA_F_VALIDATE) != 0);
+                          false);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0) != hipSuccess)
       resident = 1;
     for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
-      st = launch_fwd(ctx, fp, depth, gpc, false);   // warm-up
+      // the non-validating kernel: tuning frames leave no validation marks
+      st = launch_fwd(ctx, fp, depth, gpc, false, false);   // warm-up
       if (st != VCA_OK) break;
       if (hipEventRecord(a, ctx->stream) != hipSuccess) {
         st = fail(ctx, VCA_ERR_DEVICE, "hipEventRecord");
         break;
       }
-      for (int r = 0; r < reps && st == VCA_OK; r++) st = launch_fwd(ctx, fp, depth, gpc, false);
+      for (int r = 0; r < reps && st == VCA_OK; r++) st = launch_fwd(ctx, fp, depth, gpc, false, false);
       if (st != VCA_OK) break;
       if (hipEventRecord(b, ctx->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess) {
         st = fail(ctx, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
@@ -817,11 +744,16 @@ vca_status vca_features(vca_ctx* ctx, int64_t first, int32_t count, vca_frame_fe
   if (first < ctx->submitted - cap) return fail(ctx, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(ctx->device);
   HIP_TRY(ctx, ctx->done.wait(0, first + count, ctx->stream));
-  // the ring and the flag are host memory the kernels wrote before the launch
-  // that produced the last frame asked for completed (later launches may
-  // still run: they write other ring slots)
-  if ((ctx->cfg.flags & VCA_F_VALIDATE) && *static_cast<volatile int32_t*>(ctx->err_host))
-    return fail(ctx, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted");
+  // the rings are host memory the kernels wrote before the launch that
+  // produced the last frame asked for completed (later launches may still
+  // run: they write other ring slots)
+  if (ctx->cfg.flags & VCA_F_VALIDATE) {
+    const volatile int32_t* marks = ctx->err_ring_host;
+    for (int64_t f = first; f < first + count; f++)
+      if (marks[f % cap])
+        return fail(ctx, VCA_ERR_STATE,
+                    "frame " + std::to_string(f) + " holds a 10-bit sample above 1023");
+  }
   int64_t done = 0;
   while (done < count) {
     const int64_t slot = (first + done) % cap;

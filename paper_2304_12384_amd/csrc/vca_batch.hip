@@ -37,6 +37,8 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kKinds = 18;          // bit depth {8, 10} x w {32, 16, 8} x K {w, w/2, w/4}
+constexpr int32_t kDefaultMaxBatch = 300;    // frames per stream and round (max_batch = 0)
+constexpr int32_t kDefaultCapacity = 4096;   // feature ring per stream (feature_capacity = 0)
 
 inline int kind_of(int bits, int w, int K) {
   const int wi = w == 32 ? 0 : (w == 16 ? 1 : 2);
@@ -51,7 +53,7 @@ struct StreamDesc {
   int32_t strips;                  // strips of the stream in this launch
   int32_t chunk_begin, chunk_end;  // the stream's chunks in the launch's flat list
   int32_t validate;
-  int32_t stream;                  // index of the stream (its error flag)
+  int32_t stream;                  // index of the stream
 };
 
 // Consecutive strips of one stream handed to a wavefront at a time.
@@ -75,7 +77,8 @@ struct BatchParams {
   const double* tab_wp;  // [kKinds][16][64] packed-layout weights
   double* blk_h;
   int32_t* blk_dc;
-  int32_t* err_flag;      // [n_streams]: a validated 10-bit sample above 1023
+  int32_t* err_flag;      // per frame of the round (StripGeom::frame_base + frame):
+                          // a validated 10-bit sample above 1023
   int32_t* queue;         // next chunk to hand out; zero at launch
 };
 
@@ -109,7 +112,6 @@ __device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int& c,
     while (d < kr.desc_end - 1 && c >= p.streams[d].chunk_end) d++;
     const StreamDesc& sd = p.streams[d];
     o.validate = sd.validate;
-    o.err_flag = p.err_flag + sd.stream;
     const int s0 = (c - sd.chunk_begin) * kChunkStrips;
     const int s1 = min(s0 + kChunkStrips, sd.strips);
     run_strips<kBits, kW, kK, kDepth, false, (kBits != 8)>(sd.geom, o, pc, s0 / kRun, 1, s1, lane, stage);
@@ -224,8 +226,9 @@ struct vca_batch {
   float* rings = nullptr;          // device view of rings_host
   float* rings_host = nullptr;     // pinned, mapped
   std::vector<int64_t> ring_off;   // per stream, in floats
-  int32_t* err_flag = nullptr;     // device view of err_host
-  int32_t* err_host = nullptr;     // pinned, mapped: [n_streams]
+  int32_t* frame_err = nullptr;    // per frame of a round: validation marks (device)
+  int32_t* err_rings = nullptr;    // device view of err_rings_host
+  int32_t* err_rings_host = nullptr;   // pinned, mapped: per stream [feature_capacity] marks
   int32_t* queue = nullptr;        // chunk counter of the forward launch
   std::vector<int> cur_state;
   std::vector<char> has_prev;
@@ -290,6 +293,13 @@ void drop_graph(vca_batch* b) {
 void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, const int32_t* cnt,
                       int32_t* total_chunks, int32_t* total_frames) {
   int32_t chunks = 0, frames = 0, i = 0;
+  // each stream's frames are numbered from its first reduction workgroup on
+  std::vector<int32_t> frame_begin(b->n);
+  for (int s = 0; s < b->n; s++) {
+    frame_begin[s] = frames;
+    frames += cnt[s];
+  }
+  frames = 0;
   for (int k = 0; k < kKinds; k++) {
     KindRange& kr = b->kinds[k];
     kr.desc_begin = i;
@@ -306,7 +316,7 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
       const int64_t pt[3] = {fr[s].pitch_y, fr[s].pitch_uv, fr[s].pitch_uv};
       const uint8_t* first[3];
       for (int P = 0; P < 3; P++) first[P] = cnt[s] > 0 ? base[P] + fs[P] * off[s] : nullptr;
-      sd.geom = make_strip_geom(g, first, fs, pt, (int32_t)b->blk_base[s]);
+      sd.geom = make_strip_geom(g, first, fs, pt, (int32_t)b->blk_base[s], frame_begin[s]);
       sd.kind = k;
       sd.strips = cnt[s] * sd.geom.strips_per_frame;
       sd.chunk_begin = chunks;
@@ -330,6 +340,8 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
     rp.state_in = b->has_prev[s] ? st + (int64_t)b->cur_state[s] * g.cnt[0] : nullptr;
     rp.state_out = st + (int64_t)(b->cur_state[s] ^ 1) * g.cnt[0];
     rp.ring = b->rings + b->ring_off[s];
+    rp.frame_err = (c.flags & VCA_F_VALIDATE) ? b->frame_err + frames : nullptr;
+    rp.err_ring = b->err_rings + b->ring_off[s] / 7;
     rp.first_frame = b->submitted[s];
     rp.capacity = c.feature_capacity;
     for (int P = 0; P < 3; P++) {
@@ -363,7 +375,7 @@ vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_chunks, 
   bp.tab_wp = b->tab_wp;
   bp.blk_h = b->blk_h;
   bp.blk_dc = b->blk_dc;
-  bp.err_flag = b->err_flag;
+  bp.err_flag = b->frame_err;
   bp.queue = b->queue;
   hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, b->queue);
   BHIP_TRY(b, hipGetLastError());
@@ -412,6 +424,17 @@ std::string batch_tune_key(const vca_batch* b) {
   return buf;
 }
 
+// Validation marks of frames [first, first + count) of a stream (whose round
+// has completed): a message if one of them held a 10-bit sample above 1023.
+const char* invalid_frames(const vca_batch* b, int32_t s, int64_t first, int32_t count) {
+  if (!(b->cfgs[s].flags & VCA_F_VALIDATE)) return nullptr;
+  const int64_t cap = b->cfgs[s].feature_capacity;
+  const volatile int32_t* marks = b->err_rings_host + b->ring_off[s] / 7;
+  for (int64_t f = first; f < first + count; f++)
+    if (marks[f % cap]) return "a requested frame holds a 10-bit sample above 1023";
+  return nullptr;
+}
+
 vca_status check_batch_frames(vca_batch* b, const vca_frames* fr, const int32_t* n_frames) {
   if (!fr || !n_frames) return bfail(b, VCA_ERR_INVALID_ARG, "null argument");
   for (int s = 0; s < b->n; s++) {
@@ -434,12 +457,12 @@ void vca_close_batch(vca_batch* b) {
     DeviceGuard g(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
-    void* bufs[] = {b->tab_b1p, b->tab_a2, b->tab_wp,     b->blk_h,
-                    b->blk_dc,  b->state,  b->d_streams, b->d_red, b->queue};
+    void* bufs[] = {b->tab_b1p, b->tab_a2,    b->tab_wp, b->blk_h,  b->blk_dc,
+                    b->state,   b->d_streams, b->d_red,  b->queue, b->frame_err};
     for (void* p : bufs)
       if (p) (void)hipFree(p);
     if (b->rings_host) (void)hipHostFree(b->rings_host);
-    if (b->err_host) (void)hipHostFree(b->err_host);
+    if (b->err_rings_host) (void)hipHostFree(b->err_rings_host);
     if (b->h_streams) (void)hipHostFree(b->h_streams);
     if (b->h_red) (void)hipHostFree(b->h_red);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
@@ -460,6 +483,10 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
     vca_status st = check_config(&cfgs[s]);
     if (st == VCA_OK && (cfgs[s].flags & VCA_F_DOWNSAMPLE)) st = VCA_ERR_UNSUPPORTED;
     if (st != VCA_OK) return st;
+    // one round's frames of a stream must not share ring slots
+    const int32_t mb = cfgs[s].max_batch ? cfgs[s].max_batch : kDefaultMaxBatch;
+    const int32_t cap = cfgs[s].feature_capacity ? cfgs[s].feature_capacity : kDefaultCapacity;
+    if (cap < mb) return VCA_ERR_INVALID_ARG;
     if (cfgs[s].flags & VCA_F_KEEP_COEFFS) return VCA_ERR_UNSUPPORTED;
     if (cfgs[s].device != cfgs[0].device) return VCA_ERR_INVALID_ARG;
   }
@@ -479,11 +506,12 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   b->cur_state.assign(n_streams, 0);
   b->has_prev.assign(n_streams, 0);
   b->submitted.assign(n_streams, 0);
-  int64_t blk = 0, st_total = 0, ring_total = 0;
+  int64_t blk = 0, st_total = 0, ring_total = 0, round_frames = 0;
   for (int s = 0; s < n_streams; s++) {
     vca_config& c = b->cfgs[s];
-    if (c.max_batch == 0) c.max_batch = 300;
-    if (c.feature_capacity == 0) c.feature_capacity = 4096;
+    if (c.max_batch == 0) c.max_batch = kDefaultMaxBatch;
+    if (c.feature_capacity == 0) c.feature_capacity = kDefaultCapacity;
+    round_frames += c.max_batch;
     b->geos[s].init(c);
     if (c.flags & VCA_F_TIMING) b->timing = true;
     if (c.bit_depth != 8) b->only8 = false;
@@ -524,9 +552,13 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
   if ((s = balloc(b, &b->state, (size_t)st_total)) != VCA_OK) return bail(s);
   if (host_mapped_alloc((size_t)ring_total * sizeof(float), reinterpret_cast<void**>(&b->rings_host),
                         reinterpret_cast<void**>(&b->rings)) != hipSuccess ||
-      host_mapped_alloc((size_t)n_streams * sizeof(int32_t), reinterpret_cast<void**>(&b->err_host),
-                        reinterpret_cast<void**>(&b->err_flag)) != hipSuccess)
+      host_mapped_alloc((size_t)(ring_total / 7) * sizeof(int32_t),
+                        reinterpret_cast<void**>(&b->err_rings_host),
+                        reinterpret_cast<void**>(&b->err_rings)) != hipSuccess)
     return bail(VCA_ERR_OOM);
+  if ((s = balloc(b, &b->frame_err, (size_t)round_frames)) != VCA_OK) return bail(s);
+  if (hipMemset(b->frame_err, 0, (size_t)round_frames * sizeof(int32_t)) != hipSuccess)
+    return bail(VCA_ERR_DEVICE);
   if ((s = balloc(b, &b->d_streams, n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->d_red, n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->queue, 1)) != VCA_OK) return bail(s);
@@ -638,6 +670,8 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
   if ((st = wait_staging(b)) != VCA_OK) return st;
   int32_t chunks = 0, nfr = 0;
   fill_descriptors(b, frames, off.data(), cnt.data(), &chunks, &nfr);
+  // no validation while tuning: no reduction follows to collect the marks
+  for (int i = 0; i < b->n; i++) b->h_streams[i].validate = 0;
   if ((st = upload_descriptors(b)) != VCA_OK) return st;
   hipEvent_t e0, e1;
   BHIP_TRY(b, hipEventCreate(&e0));
@@ -693,10 +727,9 @@ vca_status vca_batch_features(vca_batch* b, int32_t stream, int64_t first, int32
   if (first < b->submitted[stream] - cap) return bfail(b, VCA_ERR_STATE, "frame left the feature ring");
   DeviceGuard guard(b->device);
   BHIP_TRY(b, b->done.wait(stream, first + count, b->stream));
-  // the rings and flags are host memory the kernels wrote before the round
-  // that produced the last frame asked for completed
-  if (static_cast<volatile int32_t*>(b->err_host)[stream])
-    return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to this stream");
+  // the rings are host memory the kernels wrote before the round that
+  // produced the last frame asked for completed
+  if (const char* bad = invalid_frames(b, stream, first, count)) return bfail(b, VCA_ERR_STATE, bad);
   const float* ring = b->rings_host + b->ring_off[stream];
   int64_t done = 0;
   while (done < count) {
@@ -729,8 +762,8 @@ vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32
   float* dst = reinterpret_cast<float*>(out);
   for (int32_t r = 0; r < n_requests; r++) {
     const int32_t s = streams[r];
-    if (static_cast<volatile int32_t*>(b->err_host)[s])
-      return bfail(b, VCA_ERR_STATE, "a 10-bit sample above 1023 was submitted to stream " + std::to_string(s));
+    if (const char* bad = invalid_frames(b, s, first[r], count[r]))
+      return bfail(b, VCA_ERR_STATE, "stream " + std::to_string(s) + ": " + bad);
     const int64_t cap = b->cfgs[s].feature_capacity;
     const float* ring = b->rings_host + b->ring_off[s];
     for (int64_t done = 0; done < count[r];) {

@@ -22,6 +22,9 @@ struct ReduceParams {
   const double* state_in;  // luma H of the frame before frame 0, or null (h = 0)
   double* state_out;       // receives luma H of the last frame
   float* ring;             // [capacity][7] feature ring
+  int32_t* frame_err;      // per frame of the launch: validation mark of the forward
+                           // kernel (moved to err_ring and cleared), or null
+  int32_t* err_ring;       // [capacity] validation marks beside the feature ring
   int64_t first_frame;     // global index of frame 0 of this launch
   int64_t capacity;
   int32_t cnt[3];          // blocks per plane
@@ -69,7 +72,12 @@ __device__ inline void reduce_frame(const ReduceParams& p, int f) {
     __syncthreads();
   }
   if (t == 0) {
-    float* o = p.ring + ((p.first_frame + f) % p.capacity) * 7;
+    const int64_t slot = (p.first_frame + f) % p.capacity;
+    if (p.frame_err) {
+      p.err_ring[slot] = p.frame_err[f];
+      p.frame_err[f] = 0;   // clean for the next launch on this stream
+    }
+    float* o = p.ring + slot * 7;
     o[0] = (float)(red[0][0] * p.inv_norm[0]);
     o[1] = (float)(red[6][0] * p.inv_norm[0]);
     o[2] = (float)(red[3][0] * p.inv_norm[0]);

@@ -36,13 +36,14 @@ struct StripGeom {
   FastDiv div_spf;         // / strips_per_frame
   int32_t per_frame;       // blocks per frame
   int32_t blk_base;        // output index of block 0 of the run's frame 0
+  int32_t frame_base;      // index of the run's frame 0 in the launch's frame flags
 };
 
 // Host: strips of frames starting at base[P] (Y, U, V) with the given frame
 // strides and pitches, outputs from block blk_base on.
 inline StripGeom make_strip_geom(const Geometry& g, const uint8_t* const base[3],
                                  const int64_t fstride[3], const int64_t pitch[3],
-                                 int32_t blk_base) {
+                                 int32_t blk_base, int32_t frame_base = 0) {
   StripGeom G{};
   for (int P = 0; P < 3; P++) {
     StripPlane& sp = G.sp[P];
@@ -61,6 +62,7 @@ inline StripGeom make_strip_geom(const Geometry& g, const uint8_t* const base[3]
   G.div_spf = make_fastdiv((uint32_t)G.strips_per_frame);
   G.per_frame = g.per_frame;
   G.blk_base = blk_base;
+  G.frame_base = frame_base;
   return G;
 }
 
@@ -73,6 +75,7 @@ struct StripWork {
   int32_t vr;           // block rows of the strip inside the grid
   int32_t vc_last;      // block columns of the last tile inside the grid
   int32_t row0;         // output index of block (0, 0) of the strip's tile row
+  int32_t frame;        // the strip's frame in the launch's frame flags
 };
 
 // Strip `id` (frame-major, then Y, U, V, then tile rows, then strips along a
@@ -106,6 +109,7 @@ __device__ inline StripWork decode_strip(const StripGeom& G, int id) {
   w.out0 = G.blk_base + f * G.per_frame + pl.boff + by0 * pl.nbx + bx0;
   w.row0 = w.out0 - bx0;
   w.out_row = pl.nbx;
+  w.frame = G.frame_base + f;
   return w;
 }
 
@@ -258,8 +262,36 @@ constexpr int kSegCols = 128;   // block columns of a staged segment (w = 16, 8)
 // LDS bytes of one wavefront's staging area (FP64 H, then int32 DC).
 constexpr int stage_bytes(int w) { return w == 32 ? 0 : (kTile / w) * kSegCols * 12; }
 
+// Coefficient export (VCA_F_KEEP_COEFFS, tests): the K x K coefficients of
+// the blocks of unit u of strip S, DC corrected, at ((block * K + i) * K + k)
+// of out.coeffs -- the same registers coeff_energy weighs, so the export shows
+// exactly what the production walk computed.
+template <int kBits, int kW, int kK, class PC>
+__device__ inline void store_unit_coeffs(const TileOut& o, const StripWork& S, int u, const PC& pc,
+                                         const v16i& dh, const v16i& dl, int lane) {
+  constexpr int kS2 = ilog2c(kW) + 6;
+  constexpr int kBpt = kTile / kW;
+  constexpr int kPack = kW / kK;
+  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;
+  const int c = lane & 31, g = lane >> 5;
+  const int bc = c / kW, cc = c % kW, kk = cc % kK;
+  const int t = u * kPack + cc / kK;   // the lane's sample tile within the strip
+  const int vc = t == S.n - 1 ? S.vc_last : kBpt;
+  if (t >= S.n || bc >= vc) return;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    if (!reg_used(j, kW, kK)) continue;
+    const int m = reg_row(j, g), br = m / kW, ii = m % kW;
+    if (ii >= kK || br >= S.vr) continue;
+    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
+    if (reg_block_row0(j, kW)) yv += pc.row0_fix;
+    const int64_t blk = S.out0 + br * S.out_row + t * kBpt + bc;
+    o.coeffs[(blk * kK + ii) * kK + kk] = (int16_t)(yv + (ii == 0 && kk == 0 ? kDcAdd : 0));
+  }
+}
+
 template <int kBits, int kW, int kK, int kDepthMax, bool kDs = false, bool kValidate = false,
-          int kRunLen = kRun>
+          int kRunLen = kRun, bool kKeep = false>
 __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& out,
                                            const PackConsts<kW, kK>& pc, int run0, int run_stride,
                                            int end, int lane, uint8_t* stage) {
@@ -300,7 +332,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   double hrun = 0.0;
   int dcrun = 0;
   int run_out0 = S.out0;
-  uint32_t seen = 0;   // kValidate: OR of every sample walked
+  uint32_t seen = 0;   // kValidate: OR of every sample of the current strip
   double* st_h = reinterpret_cast<double*>(stage);            // [kBpt][kSegCols]
   int* st_dc = reinterpret_cast<int*>(st_h + kBpt * kSegCols);  // [kBpt][kSegCols]
 
@@ -320,6 +352,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
       double h[kBpt];
       int dc[kBpt];
       coeff_energy<kBits, kW, kK>(pc, dh, dl, h, dc);
+      if constexpr (kKeep) store_unit_coeffs<kBits, kW, kK>(out, S, u, pc, dh, dl, lane);
       if constexpr (kW == 32) {
         hs[u] = h[0];
         dcs[u] = dc[0];
@@ -400,13 +433,17 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
         run_out0 = S2.out0;
       }
     }
+    // kValidate: a flagged sample of the strip marks its frame (the
+    // reduction moves the mark into the frame's slot of the feature ring)
+    if constexpr (kValidate) {
+      if (out.validate && (seen & kOver10Bits)) out.err_flag[S.frame] = 1;
+      seen = 0;
+    }
     if (!more) break;
     id = id2;
     S = S2;
     O = O2;
   }
-  // kValidate: one test per call, a flagged sample of any strip sets the error
-  if (kValidate && out.validate && (seen & kOver10Bits)) *out.err_flag = 1;
 }
 
 }  // namespace vca

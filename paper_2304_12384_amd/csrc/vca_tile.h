@@ -11,8 +11,7 @@
 //     vertical pass once its 16-bit values are split into int8 bytes;
 //   * vertical pass Y = Cd T on two int8 MFMAs (hi and lo bytes of T);
 //   * per lane, FP64 sums of W |Y| per block row, reduced over the lanes of
-//     a block (a shuffle butterfly in the one-tile kernel, permlane swaps
-//     and DPP in the strip kernels) to the block energy H; DC is read in
+//     a block (permlane swaps and DPP) to the block energy H; DC is read in
 //     place.
 // Transform definition (Section 2 of the paper names the block-DCT features;
 // the integer transform is the H.265 core transform): per block
@@ -145,15 +144,6 @@ __device__ inline uint32_t perm_b32(uint32_t hi_src, uint32_t lo_src, uint32_t s
   return __builtin_amdgcn_perm(hi_src, lo_src, sel);
 }
 
-// Wave-uniform description of one tile.
-struct TileWork {
-  const uint8_t* base;  // row 0, column 0 of the tile
-  int32_t pitch;        // bytes between rows (< 2^23)
-  int32_t vr, vc;       // complete blocks of the tile inside the plane's block grid
-  int32_t out0;         // output index of the tile's block (0, 0)
-  int32_t out_row;      // output index step between block rows
-};
-
 // Raw samples of one lane: 8-bit uses a (16 samples), 10-bit a and b
 // (8 uint16 samples each).
 struct TileData {
@@ -161,58 +151,13 @@ struct TileData {
   v4i b;
 };
 
-// Per-wavefront constants.
-template <int kW, int kK>
-struct TileConsts {
-  v4i b1;             // stage-1 B operand
-  v4i a2;             // stage-2 A operand
-  double wt[16];      // weights (only registers in use are loaded)
-  int row0_fix;       // +128 on each block's first coefficient row (lanes g = 0)
-
-  __device__ void load(const v4i* tab_b1, const v4i* tab_a2, const double* tab_w, int lane) {
-    b1 = tab_b1[lane];
-    a2 = tab_a2[lane];
-#pragma unroll
-    for (int j = 0; j < 16; j++)
-      if (reg_used(j, kW, kK)) wt[j] = tab_w[j * 64 + lane];
-    row0_fix = lane < 32 ? 128 : 0;
-  }
-};
-
-// Loads a lane's samples.  Rows and 16-byte pieces outside the tile's valid
-// blocks are redirected to row 0 / the lane's first valid piece: a 16-byte
-// piece that starts inside the block grid lies inside the row's pitch (a
-// multiple of 16 bytes), so every access stays in bounds; the redirected
-// data only feeds blocks that are discarded.
-template <int kBits, int kW>
-__device__ __forceinline__ TileData load_tile(const TileWork& t, int lane) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
-  constexpr int kBpt = kTile / kW;
-  const int r = lane & 31, g = lane >> 5;
-  TileData d;
-  if (t.vr == kBpt && t.vc == kBpt) {
-    const uint32_t off = __umul24((uint32_t)r, (uint32_t)t.pitch) + 16 * g * kBps;
-    d.a = *reinterpret_cast<const v4i*>(t.base + off);
-    if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(t.base + off + 16);
-  } else {
-    const int rows = t.vr * kW, cols = t.vc * kW;
-    const uint32_t roff = __umul24((uint32_t)(r < rows ? r : 0), (uint32_t)t.pitch);
-    const int c0 = 16 * g < cols ? 16 * g : 0;
-    d.a = *reinterpret_cast<const v4i*>(t.base + roff + c0 * kBps);
-    if (kBits != 8) {
-      const int c1 = 16 * g + 8 < cols ? 16 * g + 8 : c0;
-      d.b = *reinterpret_cast<const v4i*>(t.base + roff + c1 * kBps);
-    }
-  }
-  return d;
-}
-
-// Outputs of the forward tile.
+// Outputs of the forward kernels.
 struct TileOut {
   double* blk_h;      // block energies
   int32_t* blk_dc;    // block DC coefficients
   int16_t* coeffs;    // optional K x K coefficients per block
-  int32_t* err_flag;  // set to 1 when a 10-bit sample exceeds 1023 (validation on)
+  int32_t* err_flag;  // per frame of the launch: set to 1 when a 10-bit sample of
+                      // the frame exceeds 1023 (validation on)
   int32_t validate;
 };
 
@@ -304,13 +249,6 @@ __device__ __forceinline__ v16i stage1_sum(const Acc1& a) {
   return d1;
 }
 
-template <int kBits, int kW, int kPack>
-__device__ __forceinline__ v16i stage1(const v4i (&b1)[kPack],
-                                       const TileData (&d)[kPack]) {
-  uint32_t seen = 0;   // validated by the caller
-  return stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(b1, d, stage1_bias<ilog2c(kW) + kBits - 9>(), seen));
-}
-
 // Split of the horizontal-pass result and the vertical pass.  Exact split of
 // T (-2^14 <= T < 2^15 for every w and B):
 //   T = 256 T_hi + u,  T_hi = T >> 8 in [-64, 127],  u = T & 255,
@@ -356,94 +294,6 @@ __device__ __forceinline__ void mfma2(const v4i& a2, const Split& sp, const v16i
   const v16i zero = {};
   dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.hi, c2, 0, 0, 0);
   dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.lo, zero, 0, 0, 0);
-}
-
-template <int kBits, int kW>
-__device__ __forceinline__ void stage2(const v4i& a2, const v16i& d1, v16i& dh, v16i& dl) {
-  mfma2(a2, split2<kBits, kW>(d1), stage2_bias<kW>(), dh, dl);
-}
-
-// Both passes of one tile.
-template <int kBits, int kW, class Consts>
-__device__ __forceinline__ void tile_transform(const Consts& tc, const TileData& d,
-                                               v16i& dh, v16i& dl) {
-  const v4i b1[1] = {tc.b1};
-  const TileData dd[1] = {d};
-  stage2<kBits, kW>(tc.a2, stage1<kBits, kW, 1>(b1, dd), dh, dl);
-}
-
-// Transform, energies and DC of one tile, reduced and stored per block.
-// Consts: TileConsts<kW, kK>, or TileConsts<8, 8> (all registers loaded)
-// when one wavefront serves tiles of several block sizes.
-template <int kBits, int kW, int kK, bool kKeep, class Consts>
-__device__ __forceinline__ void fwd_tile(const TileOut& o, const Consts& tc, const TileData& d,
-                                         const TileWork& t, int lane) {
-  constexpr int kS2 = ilog2c(kW) + 6;
-  constexpr int kBpt = kTile / kW;
-  constexpr int kDcAdd = kBits == 8 ? kDcOffset : 0;   // 8-bit samples are offset by -128
-  const int g = lane >> 5, r = lane & 31;
-  v16i dh, dl;
-  if (kBits != 8 && o.validate && (samples_or(d) & kOver10Bits)) *o.err_flag = 1;
-  tile_transform<kBits, kW>(tc, d, dh, dl);
-
-  // FP64 energy per block row (two partial sums when the tile is one block).
-  constexpr int kAcc = kBpt == 1 ? 2 : kBpt;
-  double h[kAcc];
-  int dcv[kBpt];
-#pragma unroll
-  for (int a = 0; a < kAcc; a++) h[a] = 0.0;
-#pragma unroll
-  for (int b = 0; b < kBpt; b++) dcv[b] = 0;
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    if (!reg_used(j, kW, kK)) continue;
-    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
-    const int br = (8 * (j / 4)) / kW;
-    if (reg_block_row0(j, kW)) {
-      yv += tc.row0_fix;
-      dcv[br] = yv;
-    }
-    const int a = kBpt == 1 ? (j & 1) : br;
-    h[a] = fma(tc.wt[j], fabs((double)yv), h[a]);
-    if (kKeep) {
-      const int i = reg_row(j, g);
-      const int ii = i % kW, kk = r % kW, bc = r / kW;
-      if (ii < kK && kk < kK && br < t.vr && bc < t.vc) {
-        const int out = yv + ((ii == 0 && kk == 0) ? kDcAdd : 0);
-        o.coeffs[((int64_t)(t.out0 + br * t.out_row + bc) * kK + ii) * kK + kk] = (int16_t)out;
-      }
-    }
-  }
-  double hb[kBpt];
-  if (kBpt == 1) {
-    hb[0] = h[0] + h[1];
-  } else {
-#pragma unroll
-    for (int b = 0; b < kBpt; b++) hb[b] = h[b];
-  }
-  // Butterfly over the lanes of one block column: offsets 1 .. w/2 inside the
-  // 32-lane half, then 32 across the halves.
-#pragma unroll
-  for (int off = 1; off < kW; off <<= 1) {
-#pragma unroll
-    for (int b = 0; b < kBpt; b++) hb[b] += __shfl_xor(hb[b], off);
-  }
-#pragma unroll
-  for (int b = 0; b < kBpt; b++) hb[b] += __shfl_xor(hb[b], 32);
-  // Lane bc * w (g = 0) holds the DC of block (br, bc) in dcv[br].
-  if (g == 0 && (r % kW) == 0) {
-    const int bc = r / kW;
-    if (bc < t.vc) {
-#pragma unroll
-      for (int b = 0; b < kBpt; b++) {
-        if (b < t.vr) {
-          const int idx = t.out0 + b * t.out_row + bc;
-          o.blk_h[idx] = hb[b];
-          o.blk_dc[idx] = dcv[b] + kDcAdd;
-        }
-      }
-    }
-  }
 }
 
 // ------------------------------------------------------- w = 32 strips

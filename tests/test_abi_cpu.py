@@ -74,6 +74,21 @@ def test_bad_config_rejected_before_device(bad):
     assert not ctx.value
 
 
+@pytest.mark.parametrize("mb,cap", [(8, 4), (0, 255), (300, 299)])
+def test_feature_ring_smaller_than_a_launch_rejected(mb, cap):
+    """A ring that cannot hold one launch's frames (after the defaults:
+    max_batch 256 plain, 300 batched) is refused before the device is
+    touched."""
+    c = cfg(max_batch=mb, feature_capacity=cap)
+    ctx = ctypes.c_void_p(1234)
+    assert _lib.lib().vca_open(ctypes.byref(c), None, ctypes.byref(ctx)) == _lib.VCA_ERR_INVALID_ARG
+    assert not ctx.value
+    b = ctypes.c_void_p(1234)
+    assert _lib.lib().vca_open_batch(ctypes.byref(c), 1, None, ctypes.byref(b)) == \
+        _lib.VCA_ERR_INVALID_ARG
+    assert not b.value
+
+
 def test_null_arguments():
     L = _lib.lib()
     assert L.vca_open(None, None, None) == _lib.VCA_ERR_INVALID_ARG

@@ -223,4 +223,9 @@ def test_batch_10bit_validation(vca):
     assert b.features(1, 0, 2).shape == (2, 7)
     with pytest.raises(VcaError):
         b.features(0, 0, 2)
+    # the mark is frame 1's: frame 0 of the same stream still reads, and so
+    # does the next round's clean frame
+    assert b.features(0, 0, 1).shape == (1, 7)
+    b.submit([(dev10[0][:1], dev10[1][:1], dev10[2][:1]), tuple(dev8)])
+    assert b.features(0, 2, 1).shape == (1, 7)
     b.close()

@@ -170,6 +170,43 @@ def test_10bit_validation(vca, w, k, plane, pos):
     an.submit(*[torch.from_numpy(a.view(np.int16)).cuda() for a in planes])
     with pytest.raises(VcaError):
         an.features(2, 2)
+    with pytest.raises(VcaError):
+        an.features(3, 1)
+    # each frame carries its own mark: the clean frames of both calls still read
+    assert an.features(2, 1).shape == (1, 7)
+    assert an.features(0, 2).shape == (2, 7)
+    an.close()
+
+
+def test_10bit_validation_marks_per_frame(vca):
+    """Good frames submitted, then a call with an out-of-range sample, then
+    the good frames read: they succeed (a mark belongs to its frame, not to
+    the context); later clean frames that reuse the ring slots of the bad
+    one read too."""
+    from paper_2304_12384_amd import VcaError
+    print_case(test="10bit_validation_marks_per_frame")
+    rng = np.random.default_rng(19)
+    width, height = 256, 128
+    y = rng.integers(0, 1024, size=(2, height, width)).astype(np.uint16)
+    u = rng.integers(0, 1024, size=(2, height // 2, width // 2)).astype(np.uint16)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int16)).cuda()
+    good = (dev(y), dev(u), dev(u))
+    bad_y = y.copy()
+    bad_y[1, 70, 9] = 2000                                   # second frame of the call
+    an = vca.Analyzer(width, height, bit_depth=10, block_size=16, validate=True, max_batch=2,
+                      feature_capacity=4)
+    an.submit(*good)                                         # frames 0, 1
+    an.submit(dev(bad_y), good[1], good[2])                  # frames 2, 3 (3 is bad)
+    assert an.features(0, 2).shape == (2, 7)
+    assert an.features(2, 1).shape == (1, 7)
+    for first, count in ((3, 1), (2, 2), (0, 4)):
+        with pytest.raises(VcaError):
+            an.features(first, count)
+    an.submit(*good)                                         # frames 4, 5: slots 0, 1
+    assert an.features(4, 2).shape == (2, 7)
+    an.submit(*good)                                         # frames 6, 7: slots 2, 3
+    assert an.features(6, 2).shape == (2, 7)
+    assert an.features(4, 4).shape == (4, 7)
     an.close()
 
 
