@@ -239,6 +239,36 @@ int64_t vca_frames_submitted(const vca_ctx* ctx);
 /* Waits for outstanding work and frees the context.  NULL-safe. */
 void vca_close(vca_ctx* ctx);
 
+/* Allocation-free analysis, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Analyses n_frames device-resident frames (frames->on_device
+ * = 1, the alignment rules above) of a video with configuration cfg as one
+ * fresh sequence -- h = 0 for its first frame, chained over the rest -- and
+ * enqueues the plain path's kernels on hip_stream (a hipStream_t; NULL = the
+ * null stream) without waiting.  The features (7 floats per frame, in
+ * vca_frame_features order) are written to features_dev, caller-owned DEVICE
+ * memory of n_frames records, 4-byte aligned; they are identical to those of
+ * a freshly opened context fed the same frames.  No context, no allocation:
+ * every intermediate (tables, per-block energies and DC, the previous
+ * frame's luma energies) lives in one fixed 32 MiB device array of the
+ * library, which every device the call runs on holds until the process ends.
+ * The call cuts the frames into launches of as many frames as fit there.
+ *   - The first call on each device finds the array's address and uploads
+ *     the transform tables with synchronous copies; make that call outside
+ *     stream capture.
+ *   - Calls share their device's array: two calls that may run at the same
+ *     time on one device (different streams) race and corrupt each other's
+ *     results.  Calls on one stream are ordered and safe.
+ *   - cfg->max_batch and feature_capacity are ignored; VCA_F_KEEP_COEFFS,
+ *     VCA_F_VALIDATE and VCA_F_TIMING give VCA_ERR_UNSUPPORTED, as does a
+ *     frame too large for the array: one frame needs 12 bytes per block (all
+ *     planes) plus 16 bytes per luma block, and the array leaves
+ *     32 MiB - 144 KiB for that (every size up to 8192 x 4096 at w = 8).
+ *   - VCA_ERR_INVALID_ARG for a bad cfg, frames or output pointer;
+ *     VCA_ERR_DEVICE if a HIP call fails.  No error detail is kept. */
+vca_status vca_analyze_noalloc(const vca_config* cfg, const vca_frames* frames, int32_t n_frames,
+                               float* features_dev, void* hip_stream);
+
 /* ------------------------------------------------------------ batched form
  * Many independent streams -- each with its own resolution, block size,
  * low-pass size, bit depth and frame count -- analysed by ONE persistent

@@ -6,9 +6,11 @@ Adaptive Video Streaming", Section 2, computed by hand-written HIP kernels
 behind the C ABI in include/vca.h.
 """
 from ._lib import VcaError, EXPORTS, LIB_PATH
-from .analyzer import Analyzer, Batch, PreparedFrames, FEATURE_NAMES, block_counts, read_yuv, write_yuv
+from .analyzer import (Analyzer, Batch, PreparedFrames, FEATURE_NAMES, analyze_noalloc, block_counts,
+                       read_yuv, write_yuv)
 from .grad import VCAEnergyFn, energy_features
 
-__all__ = ["Analyzer", "Batch", "PreparedFrames", "FEATURE_NAMES", "block_counts", "read_yuv", "write_yuv",
+__all__ = ["Analyzer", "Batch", "PreparedFrames", "FEATURE_NAMES", "analyze_noalloc", "block_counts",
+           "read_yuv", "write_yuv",
            "VcaError", "EXPORTS", "LIB_PATH",
            "VCAEnergyFn", "energy_features"]

@@ -34,6 +34,7 @@ EXPORTS = (
     "vca_batch_tuned_launch", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
     "vca_batch_last_error", "vca_close_batch",
     "vca_grad_workspace", "vca_energy_forward", "vca_energy_backward",
+    "vca_analyze_noalloc",
 )
 
 
@@ -124,6 +125,8 @@ def lib() -> ctypes.CDLL:
             "vca_grad_workspace": (ctypes.c_int64, [ctypes.POINTER(VcaGradConfig)]),
             "vca_energy_forward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P]),
             "vca_energy_backward": (St, [ctypes.POINTER(VcaGradConfig), P, P, P, P, P]),
+            "vca_analyze_noalloc": (St, [ctypes.POINTER(VcaConfig), ctypes.POINTER(VcaFrames),
+                                         ctypes.c_int32, P, P]),
             "vca_status_str": (ctypes.c_char_p, [ctypes.c_int]),
             "vca_last_error": (ctypes.c_char_p, [P]),
         }

@@ -243,6 +243,37 @@ class Analyzer:
         return {"depth": d.value, "groups_per_cu": g.value, "ms": ms.value}
 
 
+def analyze_noalloc(y: torch.Tensor, u: torch.Tensor, v: torch.Tensor, out: torch.Tensor, *,
+                    bit_depth: int = 8, block_size: int = 32, lowpass_k: int = 0,
+                    downsample: bool = False, stream: torch.cuda.Stream | None = None) -> None:
+    """``vca_analyze_noalloc``: features of device frames y, u, v ([n, H, W],
+    [n, H/2, W/2]) as one fresh sequence into ``out`` (float32 device tensor
+    [n, 7], contiguous), enqueued on ``stream`` (default: the current one) with
+    no device allocation by the library."""
+    bps = 1 if bit_depth == 8 else 2
+    y, py, fy = _plane_geometry(y, bps)
+    u, pu, fu = _plane_geometry(u, bps)
+    v, pv, fv = _plane_geometry(v, bps)
+    if pu != pv or fu != fv:
+        raise ValueError("U and V must share pitch and frame stride")
+    n = y.shape[0]
+    if u.shape[0] != n or v.shape[0] != n:
+        raise ValueError("planes hold different frame counts")
+    if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+            and tuple(out.shape) == (n, 7)):
+        raise ValueError("out must be a contiguous float32 device tensor [n, 7]")
+    height, width = y.shape[1], y.shape[2]
+    cfg = _config(width, height, bit_depth, block_size, lowpass_k, y.device.index,
+                  _lib.VCA_F_DOWNSAMPLE if downsample else 0, 0, 0)
+    fr = VcaFrames(y.data_ptr(), u.data_ptr(), v.data_ptr(), py, pu, fy, fu, 1)
+    if stream is None:
+        stream = torch.cuda.current_stream(y.device)
+    check(_lib.lib().vca_analyze_noalloc(ctypes.byref(cfg), ctypes.byref(fr), n,
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(stream.cuda_stream)),
+          "vca_analyze_noalloc")
+
+
 def _host_plane(p, bit_depth):
     """(contiguous-row numpy array, pitch, frame stride) of a host plane."""
     if hasattr(p, "is_cuda"):

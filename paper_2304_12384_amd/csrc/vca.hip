@@ -259,43 +259,60 @@ FwdParams make_fwd_params(const vca_ctx* ctx, const vca_frames* fr, int32_t done
   return fp;
 }
 
-// Enqueues one forward launch with the given ring depth and workgroup cap.
-// allow_short = false: always runs of kRun (the autotuner times those; the
-// tuned depth applies to them only).
-vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu,
-                      bool allow_short = true, bool validate = true) {
-  const bool keep = ctx->coeffs != nullptr;
+// Enqueues one forward launch of the strip kernel for (bits, w, K, ds) with
+// the given ring depth and workgroup cap on `stream`.  allow_short = false:
+// always runs of kRun (the autotuner times those; the tuned depth applies to
+// them only).  On failure `err` receives the message.
+vca_status enqueue_fwd(const Geometry& geo, int num_cus, hipStream_t stream, const FwdParams& fp,
+                       int depth, int groups_per_cu, bool keep, bool validate, bool allow_short,
+                       std::string& err) {
   // A launch whose runs of kRun strips would give fewer than four
   // wavefronts per CU (a frame or two at 2160p) takes runs of one strip, so
   // that a single frame spreads over the device instead of 47 workgroups.
   // The coefficient export follows the same rule, so it shows both walks.
   const int64_t strips = (int64_t)fp.n_frames * fp.geom.strips_per_frame;
-  const bool short_runs = allow_short && (strips + kRun - 1) / kRun < 4 * (int64_t)ctx->num_cus;
-  FwdKernel kern =
-      select_fwd_kernel(ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, keep, ctx->geo.ds, depth,
-                        validate && (ctx->cfg.flags & VCA_F_VALIDATE) != 0, short_runs);
-  if (!kern) return fail(ctx, VCA_ERR_UNSUPPORTED, "no kernel for this configuration");
+  const bool short_runs = allow_short && (strips + kRun - 1) / kRun < 4 * (int64_t)num_cus;
+  FwdKernel kern = select_fwd_kernel(geo.bits, geo.w, geo.K, keep, geo.ds, depth, validate, short_runs);
+  if (!kern) {
+    err = "no kernel for this configuration";
+    return VCA_ERR_UNSUPPORTED;
+  }
   // Persistent grid: at most as many workgroups as can be resident at once,
   // so no workgroup waits for another to drain before it starts its loop.
   int resident = 0;
-  HIP_TRY(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0));
-  resident = std::max(1, resident);
-  if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
-  const int64_t waves = short_runs ? strips : (strips + kRun - 1) / kRun;
-  const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
-  const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)ctx->num_cus * resident);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, ctx->stream, fp);
-  HIP_TRY(ctx, hipGetLastError());
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kGroupThreads, 0);
+  if (e == hipSuccess) {
+    resident = std::max(1, resident);
+    if (groups_per_cu > 0) resident = std::min(resident, groups_per_cu);
+    const int64_t waves = short_runs ? strips : (strips + kRun - 1) / kRun;
+    const int64_t groups_needed = (waves + kWavesPerGroup - 1) / kWavesPerGroup;
+    const int grid = (int)std::min<int64_t>(groups_needed, (int64_t)num_cus * resident);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kGroupThreads), 0, stream, fp);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    err = std::string("forward launch: ") + hipGetErrorString(e);
+    return VCA_ERR_DEVICE;
+  }
   return VCA_OK;
 }
 
-std::string tune_key(const vca_ctx* ctx) {
+// The same for a context's configuration and stream.
+vca_status launch_fwd(vca_ctx* ctx, const FwdParams& fp, int depth, int groups_per_cu,
+                      bool allow_short = true, bool validate = true) {
+  return enqueue_fwd(ctx->geo, ctx->num_cus, ctx->stream, fp, depth, groups_per_cu,
+                     ctx->coeffs != nullptr, validate && (ctx->cfg.flags & VCA_F_VALIDATE) != 0,
+                     allow_short, ctx->err);
+}
+
+std::string tune_key(int num_cus, const vca_config& cfg, const Geometry& geo) {
   char key[160];
-  std::snprintf(key, sizeof(key), "gfx950/cu%d/plain/b%d/w%d/k%d%s/%dx%d", ctx->num_cus,
-                ctx->cfg.bit_depth, ctx->cfg.block_size, ctx->geo.K, ctx->geo.ds ? "/ds" : "",
-                ctx->cfg.width, ctx->cfg.height);
+  std::snprintf(key, sizeof(key), "gfx950/cu%d/plain/b%d/w%d/k%d%s/%dx%d", num_cus, cfg.bit_depth,
+                cfg.block_size, geo.K, geo.ds ? "/ds" : "", cfg.width, cfg.height);
   return key;
 }
+
+std::string tune_key(const vca_ctx* ctx) { return tune_key(ctx->num_cus, ctx->cfg, ctx->geo); }
 
 }  // namespace
 
@@ -846,6 +863,166 @@ vca_status vca_block_stats(vca_ctx* ctx, int64_t frame, double* h_out, int32_t* 
     HIP_TRY(ctx, hipMemcpy(h_out, ctx->blk_h + off, per * sizeof(double), hipMemcpyDeviceToHost));
   if (dc_out)
     HIP_TRY(ctx, hipMemcpy(dc_out, ctx->blk_dc + off, per * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return VCA_OK;
+}
+
+}  // extern "C"
+
+// ====================================================== allocation-free form
+// vca_analyze_noalloc runs the plain path's kernels with every buffer they
+// need beyond the caller's frames and feature output placed in `scratch`, a
+// fixed array each device holds while the process runs:
+//   [0, kNaTablesBytes)  operand and weight tables of the nine (w, K)
+//                        classes, kNaClassBytes apart, uploaded once per
+//                        device on its first call;
+//   then                 per-launch block energies (FP64) and DC (int32) of
+//                        up to n_max frames, and two luma-H state buffers
+//                        (the previous launch's last frame for h).
+// Host code reaches the array only through the address hipGetSymbolAddress
+// returned for the current device.
+namespace {
+
+constexpr size_t kNaScratchBytes = 32ull << 20;
+constexpr size_t kNaClassBytes = 16 << 10;           // a2 1 KiB + b1p <= 4 KiB + weights 8 KiB
+constexpr size_t kNaTablesBytes = 9 * kNaClassBytes;
+constexpr int kNaMaxDevices = 64;
+
+__device__ __align__(256) uint8_t scratch[kNaScratchBytes];
+
+struct NaDevice {
+  uint8_t* ptr = nullptr;   // this device's copy of `scratch`
+  int num_cus = 0;
+};
+
+std::mutex na_mu;
+NaDevice na_dev[kNaMaxDevices];
+
+int na_class(int w, int K) { return 3 * (w == 8 ? 0 : (w == 16 ? 1 : 2)) + (K == w ? 0 : (K == w / 2 ? 1 : 2)); }
+
+// Once per device, with that device current: the array's device address,
+// then the tables of every class (synchronous copies; nothing is allocated).
+vca_status na_setup(int device, NaDevice* out, std::string& err) {
+  std::lock_guard<std::mutex> lk(na_mu);
+  NaDevice& d = na_dev[device];
+  if (!d.ptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return VCA_ERR_DEVICE;
+    }
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    for (int w = 8; w <= 32 && e == hipSuccess; w *= 2) {
+      for (int K = w; K >= w / 4 && e == hipSuccess; K /= 2) {
+        std::vector<int8_t> b1, a2, b1p;
+        std::vector<double> wt, wtp;
+        build_tile_tables(w, K, b1, a2, wt);
+        build_packed_tables(w, K, b1p, wtp);
+        uint8_t* base = static_cast<uint8_t*>(ptr) + na_class(w, K) * kNaClassBytes;
+        e = hipMemcpy(base, a2.data(), a2.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(base + 1024, b1p.data(), b1p.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+          e = hipMemcpy(base + 5120, wtp.data(), wtp.size() * sizeof(double), hipMemcpyHostToDevice);
+      }
+    }
+    if (e != hipSuccess) {
+      err = std::string("scratch set-up: ") + hipGetErrorString(e);
+      return VCA_ERR_DEVICE;
+    }
+    d.num_cus = cus;
+    d.ptr = static_cast<uint8_t*>(ptr);
+  }
+  *out = d;
+  return VCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vca_status vca_analyze_noalloc(const vca_config* cfg, const vca_frames* fr, int32_t n_frames,
+                               float* features_dev, void* hip_stream) {
+  vca_status s = check_config(cfg);
+  if (s != VCA_OK) return s;
+  if (!fr || n_frames < 0 || (n_frames > 0 && !features_dev) || ((uintptr_t)features_dev & 3))
+    return VCA_ERR_INVALID_ARG;
+  if (cfg->flags & (VCA_F_KEEP_COEFFS | VCA_F_VALIDATE | VCA_F_TIMING)) return VCA_ERR_UNSUPPORTED;
+  if (cfg->device >= kNaMaxDevices) return VCA_ERR_UNSUPPORTED;
+  Geometry geo;
+  geo.init(*cfg);
+  // frames per launch that fit beside the tables and the two state buffers
+  const size_t state_bytes = (size_t)geo.cnt[0] * sizeof(double);
+  const size_t per_frame_bytes = (size_t)geo.per_frame * (sizeof(double) + sizeof(int32_t));
+  const size_t avail = kNaScratchBytes - kNaTablesBytes - 2 * ((state_bytes + 255) / 256 * 256);
+  const int64_t n_max = (int64_t)(avail / (per_frame_bytes + 256));
+  if (n_max < 1) return VCA_ERR_UNSUPPORTED;   // one frame's block results exceed the array
+  if (n_frames == 0) return VCA_OK;
+  if (fr->on_device != 1) return VCA_ERR_INVALID_ARG;
+  if (check_frames(*cfg, fr, n_frames)) return VCA_ERR_INVALID_ARG;
+
+  DeviceGuard guard(cfg->device);
+  std::string na_err;   // stays empty (no allocation) unless a HIP call fails
+  NaDevice dev;
+  if ((s = na_setup(cfg->device, &dev, na_err)) != VCA_OK) return s;
+  uint8_t* tab = dev.ptr + na_class(geo.w, geo.K) * kNaClassBytes;
+  uint8_t* cur = dev.ptr + kNaTablesBytes;
+  double* state[2];
+  state[0] = reinterpret_cast<double*>(cur);
+  cur += (state_bytes + 255) / 256 * 256;
+  state[1] = reinterpret_cast<double*>(cur);
+  cur += (state_bytes + 255) / 256 * 256;
+  const int32_t n_launch = (int32_t)std::min<int64_t>(n_max, n_frames);
+  double* blk_h = reinterpret_cast<double*>(cur);
+  int32_t* blk_dc = reinterpret_cast<int32_t*>(cur + ((size_t)n_launch * geo.per_frame * sizeof(double) + 255) / 256 * 256);
+
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  LaunchChoice tuned;
+  TuneCache::get().find(tune_key(dev.num_cus, *cfg, geo), &tuned);
+  const int depth = tuned.depth > 0 ? tuned.depth : kDefaultDepth;
+  const double ww = (double)cfg->block_size * cfg->block_size;
+  int cur_state = 0;
+  for (int32_t done = 0; done < n_frames;) {
+    const int32_t n = std::min<int32_t>(n_launch, n_frames - done);
+    FwdParams fp{};
+    const uint8_t* first[3] = {static_cast<const uint8_t*>(fr->y) + fr->fstride_y * done,
+                               static_cast<const uint8_t*>(fr->u) + fr->fstride_uv * done,
+                               static_cast<const uint8_t*>(fr->v) + fr->fstride_uv * done};
+    const int64_t fs[3] = {fr->fstride_y, fr->fstride_uv, fr->fstride_uv};
+    const int64_t pt[3] = {fr->pitch_y, fr->pitch_uv, fr->pitch_uv};
+    fp.geom = make_strip_geom(geo, first, fs, pt, 0);
+    fp.n_frames = n;
+    fp.tab_a2 = reinterpret_cast<const v4i*>(tab);
+    fp.tab_b1p = reinterpret_cast<const v4i*>(tab + 1024);
+    fp.tab_wp = reinterpret_cast<const double*>(tab + 5120);
+    fp.out.blk_h = blk_h;
+    fp.out.blk_dc = blk_dc;
+    if ((s = enqueue_fwd(geo, dev.num_cus, stream, fp, depth, tuned.groups_per_cu, false, false, true,
+                         na_err)) != VCA_OK)
+      return s;
+    ReduceParams rp{};
+    rp.blk_h = blk_h;
+    rp.blk_dc = blk_dc;
+    rp.state_in = done > 0 ? state[cur_state] : nullptr;   // h = 0 for the call's first frame
+    rp.state_out = state[cur_state ^ 1];
+    rp.ring = features_dev;
+    rp.first_frame = done;
+    rp.capacity = n_frames;
+    for (int P = 0; P < 3; P++) {
+      rp.cnt[P] = geo.cnt[P];
+      rp.inv_norm[P] = 1.0 / ((double)geo.cnt[P] * ww);
+    }
+    rp.per_frame = geo.per_frame;
+    rp.n_frames = n;
+    hipLaunchKernelGGL(reduce_kernel, dim3(n), dim3(kReduceThreads), 0, stream, rp);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      na_err = std::string("reduce launch: ") + hipGetErrorString(e);
+      return VCA_ERR_DEVICE;
+    }
+    cur_state ^= 1;
+    done += n;
+  }
   return VCA_OK;
 }
 

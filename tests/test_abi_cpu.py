@@ -175,3 +175,27 @@ def test_downsample_flag_block_counts_and_rejections():
     ctx = ctypes.c_void_p(1234)
     assert L.vca_open(ctypes.byref(c), None, ctypes.byref(ctx)) == _lib.VCA_ERR_UNSUPPORTED
     assert not ctx.value
+
+
+def test_noalloc_rejects_before_touching_a_device():
+    """vca_analyze_noalloc refuses, without a device, what its fixed array cannot
+    hold (one 8192 x 8192 frame at w = 8 needs more than the 32 MiB) and the
+    flags it does not support; a bad config is an invalid argument."""
+    L = _lib.lib()
+    fr = _lib.VcaFrames(16, 16, 16, 8192, 4096, 8192 * 8192, 4096 * 4096, 1)
+    out = ctypes.c_void_p(256)
+    big = cfg(width=8192, height=8192, block_size=8)
+    assert L.vca_analyze_noalloc(ctypes.byref(big), ctypes.byref(fr), 1, out, None) == \
+        _lib.VCA_ERR_UNSUPPORTED
+    for flags in (_lib.VCA_F_KEEP_COEFFS, _lib.VCA_F_VALIDATE, _lib.VCA_F_TIMING):
+        c = cfg(flags=flags)
+        assert L.vca_analyze_noalloc(ctypes.byref(c), ctypes.byref(fr), 1, out, None) == \
+            _lib.VCA_ERR_UNSUPPORTED
+    bad = cfg(block_size=12)
+    assert L.vca_analyze_noalloc(ctypes.byref(bad), ctypes.byref(fr), 1, out, None) == \
+        _lib.VCA_ERR_INVALID_ARG
+    ok = cfg(width=8192, height=4096, block_size=8)
+    # zero frames: nothing to do, no device needed
+    assert L.vca_analyze_noalloc(ctypes.byref(ok), ctypes.byref(fr), 0, None, None) == _lib.VCA_OK
+    assert L.vca_analyze_noalloc(ctypes.byref(ok), ctypes.byref(fr), 1, None, None) == \
+        _lib.VCA_ERR_INVALID_ARG
