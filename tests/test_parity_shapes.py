@@ -65,27 +65,117 @@ def test_10bit_stress_bit_exact(vca, w, res):
     check_bit_exact(vca, video, w, 0)
 
 
+def strips_per_frame(width, height, w):
+    """Strips (runs of up to 8 tiles of 32 x 32 along a tile row) of one frame."""
+    total = 0
+    for pw, ph in ((width, height), (width // 2, height // 2), (width // 2, height // 2)):
+        bpt = 32 // w
+        ntx = -(-(pw // w) // bpt)
+        rows = -(-(ph // w) // bpt)
+        total += -(-ntx // 8) * rows
+    return total
+
+
+def frames_for_long_runs(width, height, w):
+    """Frames one launch needs so that the library walks runs of 8 strips (the
+    kernels of every large launch): at least 4 runs per compute unit."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return -(-(8 * 4 * cus) // strips_per_frame(width, height, w)) + 1
+
+
+def as_int16(coeffs):
+    """The oracle's coefficients as int16 (every value fits: |AC| <= 16384,
+    DC <= 32736), so a frame compares with one array_equal."""
+    c = np.asarray(coeffs)
+    assert c.min() >= -32768 and c.max() <= 32767
+    return c.astype(np.int16)
+
+
+def cyclic_reference(base, w, k):
+    """Oracle of the cycle 0, 1, .., m-1, 0 of the m base frames: per-frame
+    coefficients, DC and H of the base frames, and a function giving the
+    features of frame t of the device sequence t % m."""
+    m = base.n_frames
+    idx = list(range(m)) + [0]
+    cfg = oracle.Config(base.width, base.height, base.bit_depth, w, k)
+    ref = oracle.analyze(cfg, base.y[idx], base.u[idx], base.v[idx], threads=8,
+                         want_blocks=True, want_coeffs=True)
+
+    def features(t):
+        return ref.features[0 if t == 0 else (m if t % m == 0 else t % m)]
+    return ref, features
+
+
+def repeat_on_device(base, n):
+    """Device planes of n frames, frame t = base frame t % m."""
+    out = []
+    for p in (base.y, base.u, base.v):
+        a = np.ascontiguousarray(p)
+        src = torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).cuda()
+        out.append(src[torch.arange(n, device="cuda") % base.n_frames].contiguous())
+    return out
+
+
+def check_long_launch(vca, base, w, k, n, validate=False):
+    """n frames (base frames repeated) in one launch of the run-of-8 kernels:
+    the production kernel's features, DC and H of every frame, and the
+    exporting variant of the same walk's every coefficient, against the
+    oracle."""
+    m = base.n_frames
+    ref, ref_features = cyclic_reference(base, w, k)
+    planes = repeat_on_device(base, n)
+    # production kernels (no export): features, DC and H of every frame
+    an = vca.Analyzer(base.width, base.height, bit_depth=base.bit_depth, block_size=w,
+                      lowpass_k=k, max_batch=n, validate=validate)
+    an.submit(*planes)
+    feats = an.features(0, n)
+    maps = an.block_maps(0, n)
+    torch.cuda.synchronize()
+    an.close()
+    dc = maps["dc"].cpu().numpy()
+    hh = maps["h"].cpu().numpy()
+    for t in range(n):
+        assert (dc[t] == ref.block_dc[t % m]).all(), f"frame {t}: DC"
+        np.testing.assert_allclose(hh[t], ref.block_h[t % m], rtol=1e-12, atol=0)
+    assert_features_close(feats, np.stack([ref_features(t) for t in range(n)]))
+    # the exporting variant of the same walk: every coefficient of every frame
+    an = vca.Analyzer(base.width, base.height, bit_depth=base.bit_depth, block_size=w,
+                      lowpass_k=k, max_batch=n, keep_coeffs=True, validate=validate)
+    an.submit(*planes)
+    ref16 = as_int16(ref.coeffs)
+    for t in range(n):
+        co = an.block_coeffs(t)
+        if not np.array_equal(co, ref16[t % m]):
+            bad = co != ref16[t % m]
+            raise AssertionError(f"frame {t}: {int(bad.sum())} coefficients differ "
+                                 f"(first {np.argwhere(bad)[0]})")
+    an.close()
+    del planes
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("w,k", [(32, 0), (16, 0), (8, 0), (32, 16), (16, 8), (8, 2)])
 @pytest.mark.parametrize("res", [(1920, 1080), (3840, 2160)])
 def test_10bit_stress_strip_path(vca, w, k, res):
-    """The production strip kernels (no coefficient export): every block's DC
-    bit-exact and H to 1e-12 -- a wrong |coefficient| anywhere in a block
-    moves H by at least its weight (>= 1) -- on the 10-bit worst cases."""
+    """The 10-bit worst cases through the run-of-8 kernels every large launch
+    uses (three stress frames repeated past the single-strip threshold):
+    every frame's DC bit-exact and H to 1e-12 from the production kernel,
+    every coefficient bit-exact from the exporting variant of its walk."""
     width, height = res
-    print_case(test="10bit_stress_strip", w=w, k=k, width=width, height=height)
-    video = synth.stress_video(width, height, 3, cell=w, stream=200 + w + k)
-    an = vca.Analyzer(width, height, bit_depth=10, block_size=w, lowpass_k=k, validate=True)
-    y, u, v = to_device(video)
-    an.submit(y, u, v)
-    feats = an.features(0, 3)
-    maps = an.block_maps(0, 3)
-    torch.cuda.synchronize()
-    an.close()
-    cfg = oracle.Config(width, height, 10, w, k)
-    ref = oracle.analyze(cfg, video.y, video.u, video.v, threads=8, want_blocks=True)
-    assert (maps["dc"].cpu().numpy() == ref.block_dc).all()
-    np.testing.assert_allclose(maps["h"].cpu().numpy(), ref.block_h, rtol=1e-12, atol=0)
-    assert_features_close(feats, ref.features)
+    n = frames_for_long_runs(width, height, w)
+    print_case(test="10bit_stress_strip", w=w, k=k, width=width, height=height, frames=n)
+    base = synth.stress_video(width, height, 3, cell=w, stream=200 + w + k)
+    check_long_launch(vca, base, w, k, n, validate=True)
+
+
+@pytest.mark.parametrize("w", [32, 16, 8])
+@pytest.mark.parametrize("kdiv", [1, 2, 4])
+def test_8bit_long_launch(vca, patches, w, kdiv):
+    """8-bit moving content through the run-of-8 kernels for every (w, K)."""
+    k = 0 if kdiv == 1 else w // kdiv
+    n = frames_for_long_runs(patches.width, patches.height, w)
+    print_case(test="8bit_long_launch", w=w, k=k, frames=n)
+    check_long_launch(vca, patches, w, k, n)
 
 
 @pytest.mark.parametrize("w,k", [(32, 16), (32, 8), (16, 8), (8, 4), (8, 2)])
@@ -218,7 +308,9 @@ def test_10bit_300_frames_one_launch(vca, w, res):
     frames -- full-range noise, saturated edges and sign-matched worst-case
     blocks -- repeat on the device as frames t % 3; sampled frames (with the
     frame before them, for h) are checked against the oracle: every block's
-    DC bit-exact, H to 1e-12, the features to 1e-5."""
+    DC bit-exact, H to 1e-12, the features to 1e-5; then the exporting
+    variant of the same walk, over the same 300 frames in one launch, gives
+    every coefficient of every frame bit-exact."""
     width, height = res
     n = 300
     print_case(test="10bit_300_frames", w=w, width=width, height=height, frames=n)
@@ -243,3 +335,16 @@ def test_10bit_300_frames_one_launch(vca, w, res):
         assert_features_close(feats[t:t + 1], ref.features[-1][None])
         assert (maps[t]["dc"].cpu().numpy()[0] == ref.block_dc[-1]).all(), f"frame {t}"
         np.testing.assert_allclose(maps[t]["h"].cpu().numpy()[0], ref.block_h[-1], rtol=1e-12, atol=0)
+    # every coefficient of all 300 frames, from the exporting variant of the
+    # same walk in one launch
+    ref = oracle.analyze(cfg, base.y, base.u, base.v, threads=8, want_coeffs=True)
+    planes = repeat_on_device(base, n)
+    an = vca.Analyzer(width, height, bit_depth=10, block_size=w, max_batch=n, keep_coeffs=True,
+                      validate=True)
+    an.submit(*planes)
+    ref16 = as_int16(ref.coeffs)
+    for t in range(n):
+        assert np.array_equal(an.block_coeffs(t), ref16[t % 3]), f"frame {t}: coefficients differ"
+    an.close()
+    del planes
+    torch.cuda.empty_cache()
