@@ -357,9 +357,10 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
     tiles = (W // w) * (H // w) * n                # w = 32: one 32 x 32 tile per block
     bytes_fwd = tiles * (w * w * 4 + 256)          # samples read, coefficient signs written
     bytes_bwd = tiles * (256 + w * w * 4)          # signs read, dL/dx written
-    # fp16 matrix-core work as issued: forward 12, backward 10 products of
-    # 32x32x16 per tile (exact fp16 splits of the FP32 operands)
-    f16_fwd = tiles * 12 * 2 * 32 * 32 * 16
+    # fp16 matrix-core work as issued: forward 6 (integer-valued samples: one
+    # digit, 2 horizontal + 4 vertical products), backward 10 products of
+    # 32x32x16 per tile
+    f16_fwd = tiles * 6 * 2 * 32 * 32 * 16
     f16_bwd = tiles * 10 * 2 * 32 * 32 * 16
     bw_gbs = bytes_bwd / (bwd_ms * 1e-3) / 1e9
     fw_gbs = bytes_fwd / (fwd_ms * 1e-3) / 1e9

@@ -354,9 +354,15 @@ void vca_close_batch(vca_batch* b);
  *   E_t = sum_blocks H_t / (C_Y w^2),
  *   h_t = sum_blocks |H_t - H_{t-1}| / (C_Y w^2), h = 0 at a sequence start,
  * and dH/dX = 2^-(2 log2 w + B - 3) C_w^T (W o sign(Y)) C_w, sign(0) = 0.
- * The transforms run on fp16 matrix cores with FP32 accumulation over exact
- * fp16 splits of the FP32 operands; block energies and the per-frame sums
- * are FP64.  Input: n_seq sequences of seq_len consecutive float32 frames. */
+ * The transforms run on fp16 matrix cores with FP32 accumulation over
+ * operands split into fp16 integers, so every accumulation is exact: each
+ * sample is taken as a + 2^-11 b + 2^-22 c (three integer digits), which is
+ * the sample itself for |x| in [2, 2^11) and for every sample on the 2^-22
+ * grid, and within 2^-23 of it for |x| < 2; the coefficients Y are then
+ * exact (assembled in FP64), so E and h carry only FP64 rounding.  Samples
+ * of magnitude 2^11 or more are outside this domain (results approximate).
+ * Block energies and the per-frame sums are FP64.  Input: n_seq sequences of
+ * seq_len consecutive float32 frames. */
 typedef struct {
   uint32_t struct_size; /* = sizeof(vca_grad_config)                                   */
   int32_t width;        /* luma width; >= block_size                                   */
@@ -379,8 +385,8 @@ int64_t vca_grad_workspace(const vca_grad_config* cfg);
 /* Forward: reads x (device, 16-byte aligned, cfg's layout), writes E[f] and
  * h[f] (device, n_seq * seq_len floats each, frame f = s * seq_len + t) and
  * the workspace (device, vca_grad_workspace bytes, 256-byte aligned; keep it
- * unchanged for vca_energy_backward).  For integer-valued samples below 2^11
- * the signs of all coefficients, zeros included, are exact.  Enqueued on
+ * unchanged for vca_energy_backward).  Within the domain above, the signs
+ * of all coefficients, zeros included, are exact.  Enqueued on
  * hip_stream (NULL: the default stream); returns without waiting. */
 vca_status vca_energy_forward(const vca_grad_config* cfg, const float* x, float* E, float* h,
                               void* workspace, void* hip_stream);

@@ -8,14 +8,18 @@
 // d/dX of H is 2^-(s1+s2) C^T (W o sign(Y)) C, with sign(0) = 0.
 //
 // One wavefront per 32 x 32 tile (block-diagonal Cd for w < 32), on fp16
-// matrix cores (v_mfma_f32_32x32x16_f16, FP32 accumulation) with exact
-// splits of the FP32 operands:
-//   forward  T = X Cd^T with X = x0 + x1 + x2 (three fp16 parts: every FP32
-//            sample exactly), Y = Cd T with T = 4096 hi + lo, lo = lo0 + lo1.
-//            For integer samples below 2^11 every product and partial sum
-//            is exact and Y = 4096 Yh + Yl rounds once: sign(Y), and Y = 0,
-//            are exact.  Block energies in FP64; per tile the signs of the
-//            coefficients go to the workspace as two 16-bit masks per lane.
+// matrix cores (v_mfma_f32_32x32x16_f16, FP32 accumulation) with operands
+// split into fp16 integers, so that every product and partial sum is an
+// integer below 2^24 and the accumulators are exact:
+//   forward  the samples as fixed-point digits x = a + 2^-11 b + 2^-22 c + r
+//            (a = rint(x), |b|, |c| <= 1024, |r| <= 2^-23 and r = 0 for
+//            |x| >= 2 or x on the 2^-22 grid); per digit T = X Cd^T, split
+//            as T = 4096 t_h + t_l; Y assembled in FP64 from four exact
+//            accumulators (see tile_acc), so Y, sign(Y) and Y = 0 are
+//            exact for such samples (|x| < 2^11).  Tiles of integer samples
+//            have b = c = 0 and skip their products.  Block energies in
+//            FP64; per tile the signs of the coefficients go to the
+//            workspace as two 16-bit masks per lane.
 //   backward S = W o sign(Y) from the masks (W = w0 + w1, two fp16 parts),
 //            U = S^T Cd, G^T = Cd^T U (U in three fp16 parts), both chained
 //            in registers, then each block of G times its upstream factor
@@ -34,6 +38,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/vca.h"
@@ -60,10 +65,12 @@ struct H8 {
 // Per-lane operand tables and weights.  Slot s of MFMA h of lane (c + 32 g):
 //   b1: Cd[c][16 g + 8 h + s]        (stage 1 B; the lane's samples 16 g..)
 //   a2: Cd[c][m_{8h+s}(g)]           (stage 2 A; T rows held in registers)
+//   a2x2: 2 a2                        (stage 2 A of the 2 t_h digit products)
 //   ct: Cd[m_{8h+s}(g)][c]           (backward: B of S^T Cd and A of Cd^T U)
 struct alignas(16) GradTables {
   H8 b1[2][64];
   H8 a2[2][64];
+  H8 a2x2[2][64];
   H8 ct[2][64];
   double wd[16][64];   // weight * 2^-(s1+s2) of coefficient register j (energy)
   float w0[16][64];    // weight = w0 + w1, both fp16 values (backward)
@@ -164,39 +171,125 @@ __device__ inline H8 ld8(const H8 (&t)[64], int lane) {
   return h;
 }
 
-// Y of a tile in the accumulator layout (lane = column, register j = row
-// m_j), without the 2^-(s1+s2) scale.
-__device__ inline v16f tile_y(const H8 (&b1)[2], const H8 (&a2)[2], const float x[16]) {
-  v16f t = {};
+// Fixed-point digits of a lane's 16 samples: x = a + 2^-11 b + 2^-22 c + r
+// with a = rint(x), b = rint((x - a) 2^11), c = rint((x - a - 2^-11 b) 2^22),
+// each an integer of magnitude <= 2048 (exact in fp16; |x| < 2^11), and
+// |r| <= 2^-23 (r = 0 unless x is off the 2^-22 grid, i.e. |x| < 2).
+// digit(x, 0, ..) gives a (and whether some sample is not an integer),
+// digit(x, 1, ..) gives b and digit(x, 2, ..) c, each in two halves of 8.
+__device__ inline bool digit(const float (&x)[16], int which, H8 (&d)[2]) {
+  bool frac = false;
 #pragma unroll
   for (int h = 0; h < 2; h++) {
-    H8 x0, x1, x2;
-    split3(x + 8 * h, x0, x1, x2);
-    t = mma(x0, b1[h], t);
-    t = mma(x1, b1[h], t);
-    t = mma(x2, b1[h], t);
-  }
-  v16f yh = {}, yl = {};
-#pragma unroll
-  for (int h = 0; h < 2; h++) {
-    H8 hi, l0, l1;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const int j = 8 * h + 2 * q;
-      const float ha = rintf(t[j] * (1.f / 4096.f)), hb = rintf(t[j + 1] * (1.f / 4096.f));
-      const float la = fmaf(-4096.f, ha, t[j]), lb = fmaf(-4096.f, hb, t[j + 1]);
-      hi.w[q] = pk(ha, hb);
-      l0.w[q] = pk(la, lb);
-      l1.w[q] = pk(la - lo_of(l0.w[q]), lb - hi_of(l0.w[q]));
-    }
-    yh = mma(a2[h], hi, yh);
-    yl = mma(a2[h], l0, yl);
-    yl = mma(a2[h], l1, yl);
-  }
-  v16f y;
+      float v[2];
 #pragma unroll
-  for (int j = 0; j < 16; j++) y[j] = fmaf(4096.f, yh[j], yl[j]);
+      for (int e = 0; e < 2; e++) {
+        const float xv = x[8 * h + 2 * q + e];
+        const float ia = rintf(xv);
+        float r = xv - ia;                                   // exact, |r| <= 1/2
+        if (which == 0) {
+          frac |= r != 0.f;
+          v[e] = ia;
+        } else {
+          const float ib = rintf(r * 2048.f);
+          if (which == 1) {
+            v[e] = ib;
+          } else {
+            r = fmaf(-ib, 1.f / 2048.f, r);                  // exact, |r| <= 2^-12
+            v[e] = rintf(r * 4194304.f);
+          }
+        }
+      }
+      d[h].w[q] = pk(v[0], v[1]);
+    }
+  }
+  return frac;
+}
+
+// Horizontal pass of one digit: T = X Cd^T (|T| <= 2048 * 2048 = 2^22).
+__device__ inline v16f stage1(const H8 (&b1)[2], const H8 (&xd)[2]) {
+  v16f t = {};
+  t = mma(xd[0], b1[0], t);
+  t = mma(xd[1], b1[1], t);
+  return t;
+}
+
+// Vertical-pass operands of T's registers 8h..8h+7: T = 4096 th + tl with
+// th = rint(T / 4096) (|th| <= 1024) and |tl| <= 2048.
+__device__ inline void split_t(const v16f& t, int h, H8& th, H8& tl) {
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int j = 8 * h + 2 * q;
+    const float ha = rintf(t[j] * (1.f / 4096.f)), hb = rintf(t[j + 1] * (1.f / 4096.f));
+    th.w[q] = pk(ha, hb);
+    tl.w[q] = pk(fmaf(-4096.f, ha, t[j]), fmaf(-4096.f, hb, t[j + 1]));
+  }
+}
+
+// Y (without the 2^-(s1+s2) scale) of a tile in the accumulator layout
+// (lane = column, register j = row m_j) as
+//   Y = 4096 A1 + A2 + 2^-11 A3 + 2^-22 A4,
+//   A1 = Cd t_h(a),  A2 = Cd t_l(a) + 2Cd t_h(b),
+//   A3 = Cd t_l(b) + 2Cd t_h(c),  A4 = Cd t_l(c),
+// where t(d) is the horizontal pass of digit d.  |t_h(b)|, |t_h(c)| <= 512,
+// so A2 and A3 stay below 2^23 and every accumulator is an exact integer.
+// kFrac = false: integer samples (b = c = 0), A1 and A2 only.
+struct YAcc {
+  v16f a1, a2, a3, a4;
+};
+
+template <bool kFrac>
+__device__ inline YAcc tile_acc(const H8 (&b1)[2], const H8 (&a2)[2], const H8 (&a2x2)[2],
+                                const float (&x)[16], const H8 (&xa)[2]) {
+  YAcc y;
+  y.a1 = v16f{};
+  y.a2 = v16f{};
+  v16f t = stage1(b1, xa);
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    H8 th, tl;
+    split_t(t, h, th, tl);
+    y.a1 = mma(a2[h], th, y.a1);
+    y.a2 = mma(a2[h], tl, y.a2);
+  }
+  if constexpr (kFrac) {
+    H8 xd[2];
+    y.a3 = v16f{};
+    y.a4 = v16f{};
+    digit(x, 1, xd);
+    t = stage1(b1, xd);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      H8 th, tl;
+      split_t(t, h, th, tl);
+      y.a2 = mma(a2x2[h], th, y.a2);
+      y.a3 = mma(a2[h], tl, y.a3);
+    }
+    digit(x, 2, xd);
+    t = stage1(b1, xd);
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+      H8 th, tl;
+      split_t(t, h, th, tl);
+      y.a3 = mma(a2x2[h], th, y.a3);
+      y.a4 = mma(a2[h], tl, y.a4);
+    }
+  }
   return y;
+}
+
+// Coefficient j of the tile from its accumulators, exactly (up to one FP64
+// rounding in the last term).
+template <bool kFrac>
+__device__ inline double coeff(const YAcc& y, int j) {
+  double v = fma(4096.0, (double)y.a1[j], (double)y.a2[j]);
+  if constexpr (kFrac) {
+    v = fma(0x1p-11, (double)y.a3[j], v);
+    v = fma(0x1p-22, (double)y.a4[j], v);
+  }
+  return v;
 }
 
 template <int kW, int kK>
@@ -208,28 +301,42 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
   double wd[16];
 #pragma unroll
   for (int j = 0; j < 16; j++) wd[j] = reg_used(j, kW, kK) ? p.tab->wd[j][lane] : 0.0;
-  H8 b1[2], a2[2];
+  H8 b1[2], a2[2], a2x2[2];
 #pragma unroll
   for (int h = 0; h < 2; h++) {
     b1[h] = ld8(p.tab->b1[h], lane);
     a2[h] = ld8(p.tab->a2[h], lane);
+    a2x2[h] = ld8(p.tab->a2x2[h], lane);
   }
   const int total = p.n_frames * p.tiles_per_frame;
   const int stride = gridDim.x * kGWaves;
   int id = blockIdx.x * kGWaves + wave;
   if (id >= total) return;
   // Energies and coefficient signs of tile `id` (samples x).
+  // energies and sign masks from the exact coefficients
+  auto energy = [&](const YAcc& y, double (&h)[kBpt], uint32_t& mask, auto frac) {
+    constexpr bool kFrac = decltype(frac)::value;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      if (!reg_used(j, kW, kK)) continue;
+      const double v = coeff<kFrac>(y, j);
+      h[(8 * (j / 4)) / kW] = fma(wd[j], fabs(v), h[(8 * (j / 4)) / kW]);
+      mask |= (v > 0.0 ? 1u << j : 0u) | (v < 0.0 ? 1u << (16 + j) : 0u);
+    }
+  };
   auto tile = [&](const FTile<kW>& t, const float (&x)[16], int id) {
-    const v16f y = tile_y(b1, a2, x);
+    H8 xa[2];
+    const bool frac_lane = digit(x, 0, xa);
     double h[kBpt];
 #pragma unroll
     for (int b = 0; b < kBpt; b++) h[b] = 0.0;
     uint32_t mask = 0;
-#pragma unroll
-    for (int j = 0; j < 16; j++) {
-      if (!reg_used(j, kW, kK)) continue;
-      h[(8 * (j / 4)) / kW] = fma(wd[j], (double)fabsf(y[j]), h[(8 * (j / 4)) / kW]);
-      mask |= (y[j] > 0.f ? 1u << j : 0u) | (y[j] < 0.f ? 1u << (16 + j) : 0u);
+    // one branch per tile for the whole wavefront: integer samples skip the
+    // products of the fraction digits
+    if (__builtin_amdgcn_ballot_w64(frac_lane) != 0) {
+      energy(tile_acc<true>(b1, a2, a2x2, x, xa), h, mask, std::true_type{});
+    } else {
+      energy(tile_acc<false>(b1, a2, a2x2, x, xa), h, mask, std::false_type{});
     }
     p.masks[(int64_t)id * 64 + lane] = mask;
     // Each block's shares lie in the kW lanes of its block column in both
@@ -478,15 +585,17 @@ void build_grad_tables(int w, int K, int bit_depth, GradTables& t) {
   for (int lane = 0; lane < 64; lane++) {
     const int c = lane & 31, g = lane >> 5;
     for (int h = 0; h < 2; h++) {
-      float vb1[8], va2[8], vct[8];
+      float vb1[8], va2[8], va2x2[8], vct[8];
       for (int s = 0; s < 8; s++) {
         const int m = reg_row(8 * h + s, g);
         vb1[s] = (float)matd(w, c, 16 * g + 8 * h + s);
         va2[s] = (float)matd(w, c, m);
+        va2x2[s] = 2.f * va2[s];
         vct[s] = (float)matd(w, m, c);
       }
       put8(t.b1[h][lane], vb1);
       put8(t.a2[h][lane], va2);
+      put8(t.a2x2[h][lane], va2x2);
       put8(t.ct[h][lane], vct);
     }
     for (int j = 0; j < 16; j++) {

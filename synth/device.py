@@ -1,7 +1,8 @@
 """Builds synthetic frames in device memory from ``SceneVideo`` canvases.
 
-Only data movement (uploads and slicing copies with torch); no analysis
-arithmetic.  Frame t of the result equals ``SceneVideo.frame(t)``.
+Only data movement (uploads and slicing copies with torch) and input
+filtering; no analysis arithmetic.  Frame t of the result equals
+``SceneVideo.frame(t)``.
 """
 from __future__ import annotations
 
@@ -105,3 +106,24 @@ def generated_scene_video(width: int, height: int, n_frames: int, *, seed: int,
             v[s0 + t].copy_(canv_c[1][oy // 2:oy // 2 + H // 2, ox // 2:ox // 2 + W // 2])
         del canvas_y, canv_c
     return DeviceVideo(y, u, v, 8)
+
+
+def soft_device_frames(x, seed: int):
+    """Device analogue of ``video.soft_frames``: float32 frames [..., H, W]
+    blurred along rows and columns with a 3-tap kernel whose side weight is
+    drawn per frame from torch's generator seeded by ``seed``."""
+    import torch
+    g = torch.Generator(device=x.device)
+    g.manual_seed(seed)
+    shape = x.shape
+    f = x.reshape(-1, 1, *shape[-2:]).float()
+    a = 0.1 + 0.3 * torch.rand((f.shape[0], 2), generator=g, device=x.device)
+    out = torch.empty_like(f)
+    for i in range(f.shape[0]):
+        ay, ax = float(a[i, 0]), float(a[i, 1])
+        ky = torch.tensor([ay, 1.0, ay], device=x.device) / (1.0 + 2 * ay)
+        kx = torch.tensor([ax, 1.0, ax], device=x.device) / (1.0 + 2 * ax)
+        p = torch.nn.functional.pad(f[i:i + 1], (1, 1, 1, 1), mode="replicate")
+        p = torch.nn.functional.conv2d(p, ky.view(1, 1, 3, 1))
+        out[i:i + 1] = torch.nn.functional.conv2d(p, kx.view(1, 1, 1, 3))
+    return out.reshape(shape).contiguous()

@@ -15,6 +15,9 @@ stand in for them with the same shapes and sample ranges):
     rebuild them cheaply from the canvases and the offsets (``SceneVideo``).
   * ``stress_video``: 10-bit blocks of full-range noise, saturated edges and
     cosine-sign patterns that drive transform intermediates to their extremes.
+  * ``soft_frames``: float frames with fractional values, as a pre-processing
+    filter would produce them: a separable binomial blur of given frames with
+    seeded per-frame sub-sample weights.
 """
 from __future__ import annotations
 
@@ -240,3 +243,23 @@ def batch_streams(n_streams: int = 64, *, recipe: int = 3, min_frames: int = 30,
         out.append(dict(width=W, height=H, block_size=int(rng.choice(block_sizes)),
                         n_frames=int(rng.integers(min_frames, max_frames + 1)), stream=s + 1))
     return out
+
+
+def soft_frames(x: np.ndarray, *, recipe: int = 5, stream: int = 0) -> np.ndarray:
+    """Non-integer frames from frames x [..., H, W]: each frame blurred along
+    columns and rows with a seeded 3-tap kernel [a, 1, a] / (1 + 2a),
+    a ~ U(0.1, 0.4) per frame and direction (edges replicated), so values
+    stay in the input range and almost none is an integer.  Returned as
+    float64 holding float32 values (what a float32 filter output is)."""
+    rng = make_rng(recipe, stream)
+    x = np.asarray(x, np.float64)
+    flat = x.reshape(-1, *x.shape[-2:])
+    out = np.empty_like(flat)
+    for i, f in enumerate(flat):
+        ay, ax = rng.uniform(0.1, 0.4, size=2)
+        ky = np.array([ay, 1.0, ay]) / (1.0 + 2 * ay)
+        kx = np.array([ax, 1.0, ax]) / (1.0 + 2 * ax)
+        p = np.pad(f, 1, mode="edge")
+        g = ky[0] * p[:-2, :] + ky[1] * p[1:-1, :] + ky[2] * p[2:, :]
+        out[i] = kx[0] * g[:, :-2] + kx[1] * g[:, 1:-1] + kx[2] * g[:, 2:]
+    return out.reshape(x.shape).astype(np.float32).astype(np.float64)
