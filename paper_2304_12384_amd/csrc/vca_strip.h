@@ -1,13 +1,16 @@
 // vca_strip.h -- strips of 32 x 32 tiles, the work unit of the plain and the
 // batched forward kernels.
 //
-// A strip is a run of up to kStrip consecutive tiles of one tile row of one
-// plane of one frame.  A wavefront decodes a strip once (scalar loads of one
-// plane record), addresses every tile as scalar base + a 32-bit lane offset
-// computed once per strip, and transforms the strip in units of
-// kPack = w / K tiles that share one MFMA tile (vca_tile.h, packed layout).
-// For w = 32 the FP64 energy shares of the strip's tiles are reduced together
-// at the end of the strip.
+// A strip is a run of up to kStrip consecutive tiles of one plane of one
+// frame: for w = 32 (a tile is one block) on planes at least kStrip blocks
+// wide, kStrip consecutive blocks in raster order, wrapping at most once
+// from one block row to the next, so that only the plane's last strip can be
+// short; otherwise up to kStrip tiles of one tile row.  A wavefront decodes a strip once (scalar loads of one plane record),
+// addresses every tile as a scalar base + a 32-bit lane offset computed once
+// per strip, and transforms the strip in units of kPack = w / K tiles that
+// share one MFMA tile (vca_tile.h, packed layout).  For w = 32 the FP64
+// energy shares of the strip's tiles are reduced together at the end of the
+// strip.
 #pragma once
 
 #include "vca_host.h"
@@ -18,16 +21,22 @@ namespace vca {
 constexpr int kStrip = 8;   // tiles per strip
 
 // One plane as the strip decoder sees it.
-struct StripPlane {
+// 64 bytes, so that the strip decoder reads a record with one wide scalar
+// load.
+struct alignas(16) StripPlane {
   const uint8_t* plane;    // first sample of frame 0
   int64_t fstride;         // bytes between frames
   int32_t pitch;           // bytes between rows
   int32_t nbx, nby, ntx;   // blocks per row / column, tiles per row
-  int32_t spr;             // strips per tile row
+  int32_t spr;             // strips per tile row; 0: the strips follow the raster
+                           // order of blocks (w = 32 and nbx >= kStrip)
   int32_t scnt;            // strips per plane
   int32_t boff;            // index of the plane's first block within a frame
-  FastDiv div_spr;         // / spr
+  int32_t cnt;             // blocks of the plane
+  FastDiv div_spr;         // / spr (row strips)
+  FastDiv div_nbx;         // / nbx (raster-order strips)
 };
+static_assert(sizeof(StripPlane) == 64, "one 64-byte record per plane");
 
 // The strips of a run of frames of one video.
 struct StripGeom {
@@ -53,10 +62,16 @@ inline StripGeom make_strip_geom(const Geometry& g, const uint8_t* const base[3]
     sp.nbx = g.nbx[P];
     sp.nby = g.nby[P];
     sp.ntx = g.ntx[P];
-    sp.spr = (g.ntx[P] + kStrip - 1) / kStrip;
-    sp.scnt = sp.spr * (g.tcnt[P] / g.ntx[P]);
+    sp.cnt = g.cnt[P];
+    // w = 32 on planes at least kStrip blocks wide: strips of kStrip
+    // consecutive blocks along the raster order (at most one row wrap each)
+    const bool linear = g.w == kTile && sp.nbx >= kStrip;
+    const int32_t spr = (g.ntx[P] + kStrip - 1) / kStrip;
+    sp.spr = linear ? 0 : spr;
+    sp.scnt = linear ? (sp.cnt + kStrip - 1) / kStrip : spr * (g.tcnt[P] / g.ntx[P]);
     sp.boff = g.boff[P];
-    sp.div_spr = make_fastdiv((uint32_t)sp.spr);
+    sp.div_spr = make_fastdiv((uint32_t)spr);
+    sp.div_nbx = make_fastdiv((uint32_t)sp.nbx);
   }
   G.strips_per_frame = G.sp[0].scnt + G.sp[1].scnt + G.sp[2].scnt;
   G.div_spf = make_fastdiv((uint32_t)G.strips_per_frame);
@@ -68,6 +83,8 @@ inline StripGeom make_strip_geom(const Geometry& g, const uint8_t* const base[3]
 
 struct StripWork {
   const uint8_t* base;  // first sample of the strip's first tile
+  int64_t wrap_delta;   // w = 32: bytes from the end of a block row to the next row's start
+  int32_t wrap_t;       // w = 32: tiles t >= wrap_t lie on the next block row
   int32_t pitch;
   int32_t n;            // tiles in the strip, 1..kStrip
   int32_t out0;         // output index of block (0, 0) of the first tile
@@ -97,10 +114,41 @@ __device__ inline StripWork decode_strip(const StripGeom& G, int id) {
     }
   }
   const StripPlane& pl = G.sp[P];
+  if constexpr (kW == kTile) {
+    // blocks i0 .. i0 + n - 1 in raster order: linear strips of kStrip
+    // blocks, else the strips of each block row
+    int i0, by, c0, n;
+    if (pl.spr == 0) {
+      i0 = r * kStrip;
+      by = (int)fastdiv((uint32_t)i0, pl.div_nbx);
+      c0 = i0 - by * pl.nbx;
+      n = min(kStrip, pl.cnt - i0);
+    } else {
+      by = (int)fastdiv((uint32_t)r, pl.div_spr);
+      c0 = (r - by * pl.spr) * kStrip;
+      i0 = by * pl.nbx + c0;
+      n = min(kStrip, pl.nbx - c0);
+    }
+    StripWork w;
+    w.pitch = pl.pitch;
+    w.n = n;
+    w.base = pl.plane + f * pl.fstride + (int64_t)by * kTile * kScale * w.pitch + c0 * kTile * kBps * kScale;
+    w.wrap_t = pl.nbx - c0;
+    w.wrap_delta = (int64_t)kTile * kScale * w.pitch - (int64_t)pl.nbx * kTile * kBps * kScale;
+    w.vr = 1;
+    w.vc_last = 1;
+    w.out0 = G.blk_base + f * G.per_frame + pl.boff + i0;
+    w.row0 = w.out0;
+    w.out_row = pl.nbx;
+    w.frame = G.frame_base + f;
+    return w;
+  }
   const int ty = (int)fastdiv((uint32_t)r, pl.div_spr);
   const int tx0 = (r - ty * pl.spr) * kStrip;
   StripWork w;
   w.pitch = pl.pitch;
+  w.wrap_t = kStrip;
+  w.wrap_delta = 0;
   w.n = min(kStrip, pl.ntx - tx0);
   const int by0 = ty * kBpt, bx0 = tx0 * kBpt;
   w.base = pl.plane + f * pl.fstride + (int64_t)by0 * kW * kScale * w.pitch + bx0 * kW * kBps * kScale;
@@ -220,15 +268,25 @@ __device__ inline TileData downsample_tile(const uint8_t* row0, uint32_t oa, uin
   return d;
 }
 
+// First sample of tile t of a strip (scalar): w = 32 tiles follow the raster
+// order of blocks and may continue on the next block row (once).
+template <int kBits, int kW, bool kDs = false>
+__device__ inline const uint8_t* tile_base(const StripWork& s, int t) {
+  constexpr int kBps = kBits == 8 ? 1 : 2;
+  constexpr int kScale = kDs ? 2 : 1;
+  const uint8_t* b = s.base + t * (kTile * kBps * kScale);
+  if constexpr (kW == kTile) b += t >= s.wrap_t ? s.wrap_delta : 0;
+  return b;
+}
+
 template <int kBits, int kW, bool kDs = false>
 __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, int t) {
-  constexpr int kBps = kBits == 8 ? 1 : 2;
   const bool last = kW != 32 && t == s.n - 1;
   if constexpr (kDs) {
-    return downsample_tile<kBits>(s.base + t * kTile * kBps * 2, last ? o.last_a : o.a,
+    return downsample_tile<kBits>(tile_base<kBits, kW, true>(s, t), last ? o.last_a : o.a,
                                   last ? o.last_b : o.b, s.pitch);
   }
-  const uint8_t* base = s.base + t * kTile * kBps;
+  const uint8_t* base = tile_base<kBits, kW>(s, t);
   TileData d;
   d.a = *reinterpret_cast<const v4i*>(base + (last ? o.last_a : o.a));
   if (kBits != 8) d.b = *reinterpret_cast<const v4i*>(base + (last ? o.last_b : o.b));
@@ -259,8 +317,9 @@ __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, 
 constexpr int kRun = 8;   // strips per run (w = 32: at most 64 blocks, one per lane)
 constexpr int kSegCols = 128;   // block columns of a staged segment (w = 16, 8)
 
-// LDS bytes of one wavefront's staging area (FP64 H, then int32 DC).
-constexpr int stage_bytes(int w) { return w == 32 ? 0 : (kTile / w) * kSegCols * 12; }
+// LDS bytes of one wavefront's staging area: w = 32, the DC of the run's 64
+// blocks; else the segment's FP64 H, then int32 DC.
+constexpr int stage_bytes(int w) { return w == 32 ? 64 * 4 : (kTile / w) * kSegCols * 12; }
 
 // Coefficient export (VCA_F_KEEP_COEFFS, tests): the K x K coefficients of
 // the blocks of unit u of strip S, DC corrected, at ((block * K + i) * K + k)
@@ -283,8 +342,7 @@ __device__ inline void store_unit_coeffs(const TileOut& o, const StripWork& S, i
     if (!reg_used(j, kW, kK)) continue;
     const int m = reg_row(j, g), br = m / kW, ii = m % kW;
     if (ii >= kK || br >= S.vr) continue;
-    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
-    if (reg_block_row0(j, kW)) yv += pc.row0_fix;
+    const int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
     const int64_t blk = S.out0 + br * S.out_row + t * kBpt + bc;
     o.coeffs[(blk * kK + ii) * kK + kk] = (int16_t)(yv + (ii == 0 && kk == 0 ? kDcAdd : 0));
   }
@@ -325,16 +383,15 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   Unit ring[kDepth];
 #pragma unroll
   for (int u = 0; u < kDepth; u++) ring[u] = load_unit(S, O, u);
-  const v16i c1 = stage1_bias<ilog2c(kW) + kBits - 9>();
-  const v16i c2 = stage2_bias<kW>();
+  const v16i c2 = stage2_bias<kW>(lane);
   // w = 32: the current run's blocks, lane i holding block run_out0 + i;
   // w < 32: the staged segment starts at block run_out0 (row 0 of its tile row)
   double hrun = 0.0;
-  int dcrun = 0;
   int run_out0 = S.out0;
   uint32_t seen = 0;   // kValidate: OR of every sample of the current strip
   double* st_h = reinterpret_cast<double*>(stage);            // [kBpt][kSegCols]
   int* st_dc = reinterpret_cast<int*>(st_h + kBpt * kSegCols);  // [kBpt][kSegCols]
+  int* st_run_dc = reinterpret_cast<int*>(stage);              // w = 32: [64] DC of the run
 
   while (true) {
     const int id2 = next_id(id);
@@ -379,7 +436,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
       const int v = u + kDepth;   // the unit whose loads go out now
       ring[u % kDepth] = v < kUnits ? load_unit(S, O, v) : load_unit(S2, O2, v - kUnits);
       v16i dh, dl;
-      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(pc.b1, d.t, c1, seen))),
+      mfma2(pc.a2, split2<kBits, kW>(stage1_sum<kBits>(stage1_acc<kBits, kW, kPack>(pc.b1, d.t, seen))),
             c2, dh, dl);
       finish(u, dh, dl);
     }
@@ -398,19 +455,19 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
       const bool in_strip = t >= 0 && t < S.n;
       const double ht = __shfl(h, in_strip ? tile_lane(t) : lane);
       if (in_strip) hrun = ht;
-      // DC of tile u * kPack + q': register dcs[u] of lane q' * K (g = 0)
+      // DC of tile u * kPack + q (register dcs[u] of the lane with c = q K,
+      // g = 0) into the wavefront's LDS row at run position + tile, read back
+      // by lane = position at the run's end; positions past the strip's last
+      // tile are rewritten by the next strip of the run or not stored
+      const int pos0 = S.out0 - run_out0;
+      if (g == 0 && cc % kK == 0) {
 #pragma unroll
-      for (int u = 0; u < kUnits; u++) {
-#pragma unroll
-        for (int qq = 0; qq < kPack; qq++) {
-          const int dcv = __builtin_amdgcn_readlane(dcs[u], qq * kK);
-          if (t == u * kPack + qq) dcrun = dcv;
-        }
+        for (int u = 0; u < kUnits; u++) st_run_dc[pos0 + u * kPack + q] = dcs[u];
       }
       if (!more || id2 % kRunLen == 0) {   // the run ends with this strip
         if (lane < S.out0 - run_out0 + S.n) {
           out.blk_h[run_out0 + lane] = hrun;
-          out.blk_dc[run_out0 + lane] = dcrun + kDcAdd;
+          out.blk_dc[run_out0 + lane] = st_run_dc[lane] + kDcAdd;
         }
         run_out0 = S2.out0;
       }

@@ -161,13 +161,15 @@ struct TileOut {
   int32_t validate;
 };
 
-// Rounding of the horizontal pass, 2^(s1-1), as the initial accumulator.
-template <int kS1>
-__device__ __forceinline__ v16i stage1_bias() {
-  v16i c1;
+// A v16i with every element v, built at the matrix-core call that takes it
+// as the accumulator input (zero is encoded in the instruction; other values
+// the compiler copies into registers once per strip).
+template <int kV>
+__device__ __forceinline__ v16i splat16() {
+  v16i c;
 #pragma unroll
-  for (int j = 0; j < 16; j++) c1[j] = 1 << (kS1 - 1);   // rounding of the horizontal pass
-  return c1;
+  for (int j = 0; j < 16; j++) c[j] = kV;
+  return c;
 }
 
 // 10-bit samples need no offset: x = 256 t + lo with lo the sign-extended low
@@ -214,26 +216,31 @@ struct Acc1 {
 
 // Horizontal pass of kPack sample tiles into one accumulator: tile p's
 // B operand b1[p] puts its coefficients in its own lanes (kPack = 1: the
-// plain tile).  c1 holds the rounding 2^(s1-1) in every element.
+// plain tile).  The first product adds the rounding 2^(s1-1).
 template <int kBits, int kW, int kPack>
 __device__ __forceinline__ Acc1 stage1_acc(const v4i (&b1)[kPack],
-                                           const TileData (&d)[kPack], const v16i& c1,
-                                           uint32_t& seen) {
+                                           const TileData (&d)[kPack], uint32_t& seen) {
+  constexpr int kS1 = ilog2c(kW) + kBits - 9;
   Acc1 r;
-  r.lo = c1;
   if (kBits == 8) {
+    r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(d[0].a ^ (int)0x80808080, b1[0],
+                                                 splat16<1 << (kS1 - 1)>(), 0, 0, 0);   // x - 128
 #pragma unroll
-    for (int p = 0; p < kPack; p++)
-      r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(d[p].a ^ (int)0x80808080, b1[p], r.lo, 0, 0, 0);   // x - 128
+    for (int p = 1; p < kPack; p++)
+      r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(d[p].a ^ (int)0x80808080, b1[p], r.lo, 0, 0, 0);
   } else {
-    r.hi = v16i{};
 #pragma unroll
     for (int p = 0; p < kPack; p++) {
       v4i hi, lo;
       operands10(d[p], hi, lo);
       seen |= samples_or(d[p]);
-      r.hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], r.hi, 0, 0, 0);
-      r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], r.lo, 0, 0, 0);
+      if (p == 0) {
+        r.hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], splat16<0>(), 0, 0, 0);
+        r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], splat16<1 << (kS1 - 1)>(), 0, 0, 0);
+      } else {
+        r.hi = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, b1[p], r.hi, 0, 0, 0);
+        r.lo = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, b1[p], r.lo, 0, 0, 0);
+      }
     }
   }
   return r;
@@ -254,9 +261,9 @@ __device__ __forceinline__ v16i stage1_sum(const Acc1& a) {
 //   T = 256 T_hi + u,  T_hi = T >> 8 in [-64, 127],  u = T & 255,
 // C T = 256 C T_hi + C (u - 128) + 128 C 1, the last term being 128 * 64 w
 // on each block's row 0 and 0 elsewhere: exactly +128 after the 2^s2
-// scaling.  The vertical pass's rounding 2^(s2-1) rides in the hi
-// accumulator as 2^(s2-9).  Y = (256 dh + dl) >> s2 (+128 on each block's
-// row 0).
+// scaling.  Both the vertical pass's rounding 2^(s2-1) and that +128 ride in
+// the hi accumulator's initial value (2^(s2-9), plus 2^(s2-1) on each
+// block's row 0), so Y = (256 dh + dl) >> s2.
 struct Split {
   v4i hi;   // T >> 8 bytes
   v4i lo;   // (T & 255) - 128 bytes
@@ -268,32 +275,50 @@ __device__ __forceinline__ Split split2(const v16i& d1) {
   Split sp;
 #pragma unroll
   for (int q = 0; q < 4; q++) {
-    const uint32_t s0 = (uint32_t)(d1[4 * q + 0] >> kS1);
-    const uint32_t s1 = (uint32_t)(d1[4 * q + 1] >> kS1);
-    const uint32_t s2 = (uint32_t)(d1[4 * q + 2] >> kS1);
-    const uint32_t s3 = (uint32_t)(d1[4 * q + 3] >> kS1);
-    const uint32_t p01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
-    const uint32_t p23 = perm_b32(s3, s2, 0x05010400u);
-    sp.lo[q] = (int)(perm_b32(p23, p01, 0x05040100u) ^ 0x80808080u);   // u - 128
-    sp.hi[q] = (int)perm_b32(p23, p01, 0x07060302u);                     // T >> 8
+    // T of registers 4q..4q+3 in the low 16 bits of s0..s3: a 64-bit shift
+    // of a register pair moves both (the upper word's low bits land above
+    // bit 16 of the lower word, which the byte selection below ignores)
+    uint64_t p01 = (((uint64_t)(uint32_t)d1[4 * q + 1] << 32) | (uint32_t)d1[4 * q + 0]) >> kS1;
+    uint64_t p23 = (((uint64_t)(uint32_t)d1[4 * q + 3] << 32) | (uint32_t)d1[4 * q + 2]) >> kS1;
+    // (empty asm, no instruction: keeps the compiler from splitting each
+    // shift into two 32-bit ones; not volatile, so it does not pin the
+    // schedule)
+    asm("" : "+v"(p01), "+v"(p23));
+    const uint32_t s0 = (uint32_t)p01, s1 = (uint32_t)(p01 >> 32);
+    const uint32_t s2 = (uint32_t)p23, s3 = (uint32_t)(p23 >> 32);
+    const uint32_t b01 = perm_b32(s1, s0, 0x05010400u);   // s0.b0 s1.b0 s0.b1 s1.b1
+    const uint32_t b23 = perm_b32(s3, s2, 0x05010400u);
+    sp.lo[q] = (int)(perm_b32(b23, b01, 0x05040100u) ^ 0x80808080u);   // u - 128
+    sp.hi[q] = (int)perm_b32(b23, b01, 0x07060302u);                     // T >> 8
   }
   return sp;
 }
 
-template <int kW>
-__device__ __forceinline__ v16i stage2_bias() {
-  constexpr int kS2 = ilog2c(kW) + 6;
-  v16i c2;
-#pragma unroll
-  for (int j = 0; j < 16; j++) c2[j] = 1 << (kS2 - 9);   // 256 * 2^(s2-9) = 2^(s2-1)
-  return c2;
-}
-
+// Vertical pass: dh = Cd T_hi + c2 (stage2_bias: the rounding and the +128
+// of each block's row 0) and dl = Cd (u - 128).
 __device__ __forceinline__ void mfma2(const v4i& a2, const Split& sp, const v16i& c2, v16i& dh,
                                       v16i& dl) {
-  const v16i zero = {};
   dh = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.hi, c2, 0, 0, 0);
-  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.lo, zero, 0, 0, 0);
+  dl = __builtin_amdgcn_mfma_i32_32x32x32_i8(a2, sp.lo, splat16<0>(), 0, 0, 0);
+}
+
+// Initial value of the vertical pass's hi accumulator: the rounding
+// 2^(s2-1) / 256 in every element, plus the +128 of each block's row 0
+// (128 * 2^s2 / 256 in the registers holding a row 0, lanes g = 0).  Kept in
+// registers for the whole strip walk (the empty asm makes it an opaque
+// register value, so the compiler neither rebuilds it for every product nor
+// copies it in).
+template <int kW>
+__device__ __forceinline__ v16i stage2_bias(int lane) {
+  constexpr int kS2 = ilog2c(kW) + 6;
+  v16i c2 = splat16<1 << (kS2 - 9)>();
+  if (lane < 32) {
+#pragma unroll
+    for (int j = 0; j < 16; j++)
+      if (reg_block_row0(j, kW)) c2[j] += 1 << (kS2 - 1);
+  }
+  asm volatile("" : "+v"(c2));
+  return c2;
 }
 
 // ------------------------------------------------------- w = 32 strips
@@ -322,11 +347,12 @@ __device__ inline double fold16(double a, double b) {
   return mk64(h[0], l[0]) + mk64(h[1], l[1]);
 }
 
-// v read from another lane of the same 16-lane row through DPP.
+// v read from another lane of the same 16-lane row through DPP (every
+// pattern used reads a lane of the same row, so no lane keeps an old value).
 template <int kCtrl>
 __device__ inline double dpp64(double v) {
-  const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo32(v), kCtrl, 0xf, 0xf, false);
-  const uint32_t h = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)hi32(v), kCtrl, 0xf, 0xf, false);
+  const uint32_t l = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo32(v), kCtrl, 0xf, 0xf, true);
+  const uint32_t h = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi32(v), kCtrl, 0xf, 0xf, true);
   return mk64(h, l);
 }
 
@@ -386,7 +412,6 @@ struct PackConsts {
   v4i b1[kPack];      // stage-1 B operand of each sample tile
   v4i a2;             // stage-2 A operand
   double wt[16];      // weights (only registers in use are loaded)
-  int row0_fix;       // +128 on each block's first coefficient row (lanes g = 0)
 
   __device__ void load(const v4i* tab_b1p, const v4i* tab_a2, const double* tab_w, int lane) {
 #pragma unroll
@@ -395,7 +420,6 @@ struct PackConsts {
 #pragma unroll
     for (int j = 0; j < 16; j++)
       if (reg_used(j, kW, kK)) wt[j] = tab_w[j * 64 + lane];
-    row0_fix = lane < 32 ? 128 : 0;
   }
 };
 
@@ -408,30 +432,22 @@ __device__ __forceinline__ void coeff_energy(const PC& pc, const v16i& dh, const
                                              double (&h)[kTile / kW], int (&dc)[kTile / kW]) {
   constexpr int kS2 = ilog2c(kW) + 6;
   constexpr int kBpt = kTile / kW;
-  constexpr int kAcc = kBpt == 1 ? 2 : kBpt;   // two chains when one block row
-  double acc[kAcc];
+  double acc[kBpt];
 #pragma unroll
-  for (int a = 0; a < kAcc; a++) acc[a] = 0.0;
-#pragma unroll
-  for (int b = 0; b < kBpt; b++) dc[b] = 0;
+  for (int b = 0; b < kBpt; b++) {
+    acc[b] = 0.0;
+    dc[b] = 0;
+  }
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     if (!reg_used(j, kW, kK)) continue;
-    int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
+    const int yv = (int)((uint32_t)dh[j] * 256u + (uint32_t)dl[j]) >> kS2;
     const int br = (8 * (j / 4)) / kW;
-    if (reg_block_row0(j, kW)) {
-      yv += pc.row0_fix;
-      dc[br] = yv;
-    }
-    const int a = kBpt == 1 ? (j & 1) : br;
-    acc[a] = fma(pc.wt[j], fabs((double)yv), acc[a]);
+    if (reg_block_row0(j, kW)) dc[br] = yv;
+    acc[br] = fma(pc.wt[j], fabs((double)yv), acc[br]);
   }
-  if (kBpt == 1) {
-    h[0] = acc[0] + acc[1];
-  } else {
 #pragma unroll
-    for (int b = 0; b < kBpt; b++) h[b] = acc[b];
-  }
+  for (int b = 0; b < kBpt; b++) h[b] = acc[b];
 }
 
 // ----------------------------------------------------- w = 16, 8 blocks

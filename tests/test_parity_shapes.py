@@ -66,9 +66,14 @@ def test_10bit_stress_bit_exact(vca, w, res):
 
 
 def strips_per_frame(width, height, w):
-    """Strips (runs of up to 8 tiles of 32 x 32 along a tile row) of one frame."""
+    """Strips of one frame: w = 32, runs of up to 8 consecutive blocks of a
+    plane in raster order; w = 16, 8, runs of up to 8 tiles of 32 x 32 along
+    a tile row."""
     total = 0
     for pw, ph in ((width, height), (width // 2, height // 2), (width // 2, height // 2)):
+        if w == 32:
+            total += -(-((pw // w) * (ph // w)) // 8)
+            continue
         bpt = 32 // w
         ntx = -(-(pw // w) // bpt)
         rows = -(-(ph // w) // bpt)
