@@ -36,63 +36,93 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes_per_frame(width: int, height: int, w: int) -> int:
-    """Samples inside complete w x w blocks of Y, U and V: each is read once."""
-    yb = (width // w) * w * (height // w) * w
-    cb = ((width // 2) // w) * w * ((height // 2) // w) * w
-    return yb + 2 * cb
+def frame_bytes(width: int, height: int, bit_depth: int = 8) -> int:
+    """Algorithmic bytes of one 4:2:0 frame: every sample of Y, U and V once
+    (3840x2160 8-bit: 12,441,600 B; 10-bit, uint16 samples: 24,883,200 B)."""
+    return (width * height + 2 * (width // 2) * (height // 2)) * (1 if bit_depth == 8 else 2)
 
 
-def mfma_ops_per_frame(width: int, height: int, w: int, k: int = 0) -> int:
+def block_count(width: int, height: int, w: int) -> int:
+    return (width // w) * (height // w) + 2 * ((width // 2) // w) * ((height // 2) // w)
+
+
+def int8_ops_per_frame(width: int, height: int, w: int, k: int = 0) -> int:
+    """Algorithmic int8 ops (2 per multiply-add) of the two transform passes
+    per frame: per block the horizontal pass w x K x w and the vertical pass
+    K x K x w multiply-adds (3840x2160, w = 32: 1.573 G full, 0.590 G K = 16)."""
+    K = k or w
+    return block_count(width, height, w) * 2 * (w * K * w + K * K * w)
+
+
+def mfma_issued_ops_per_frame(width: int, height: int, w: int, k: int = 0, bit_depth: int = 8) -> int:
     """int8 ops the forward kernel issues on MFMA per frame.  A unit of
     w / K sample tiles of 32 x 32 (one tile for the full transform) takes one
-    32x32x32 horizontal-pass product per sample tile and two vertical-pass
-    products (hi and lo) shared by the unit."""
+    32x32x32 horizontal-pass product per sample tile (two for 10-bit) and two
+    vertical-pass products (hi and lo) shared by the unit."""
     pack = w // (k or w)
-    tiles = (width // w) * (height // w) + 2 * ((width // 2) // w) * ((height // 2) // w)
-    tiles = tiles * (w * w) / (32 * 32)
-    return int(tiles * (pack + 2) / pack * 2 * 32 * 32 * 32)
+    tiles = block_count(width, height, w) * (w * w) / (32 * 32)
+    per_tile = (1 if bit_depth == 8 else 2) + 2 / pack
+    return int(tiles * per_tile * 2 * 32 * 32 * 32)
 
 
-def cpu_baseline(sv, frames: int, lowpass_k: int = 0) -> dict:
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(sv, frames: int) -> dict:
+    """The CPU oracle (plain C, int64 transform, FP64 features, OpenMP over
+    frames) timed on this host: the 10 frames of the 720p patches workload in
+    full, and the first `frames` frames of the 600-frame 2160p workload at
+    full DCT and K = 16, each on every core this process may use and on one
+    thread.  A reported baseline, not a target."""
     import oracle
-    threads = min(16, len(os.sched_getaffinity(0)))
+    import synth
+    cores = len(os.sched_getaffinity(0))
     video = sv.frames(0, frames)
-    cfg = oracle.Config(WIDTH, HEIGHT, 8, BLOCK, lowpass_k)
-    t0 = time.perf_counter()
-    oracle.analyze(cfg, video.y, video.u, video.v, threads=threads)
-    dt = time.perf_counter() - t0
-    # beside it: K = 16 on a quarter of the sample, and one thread on 8 frames
-    nk = max(1, frames // 4)
-    t0 = time.perf_counter()
-    oracle.analyze(oracle.Config(WIDTH, HEIGHT, 8, BLOCK, 16), video.y[:nk], video.u[:nk],
-                   video.v[:nk], threads=threads)
-    dt_k16 = time.perf_counter() - t0
-    n1 = min(8, frames)
-    t0 = time.perf_counter()
-    oracle.analyze(cfg, video.y[:n1], video.u[:n1], video.v[:n1], threads=1)
-    dt_1 = time.perf_counter() - t0
-    return {"value": frames / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {frames} frames of the 600-frame 2160p workload, "
-                      f"{'full DCT' if lowpass_k == 0 else f'K={lowpass_k}'}, "
-                      f"{threads} OpenMP threads, {dt:.1f} s wall",
-            "lowpass_k16_value": nk / dt_k16,
-            "lowpass_k16_sample": f"first {nk} frames, K=16, {threads} threads, {dt_k16:.1f} s",
-            "single_thread_value": n1 / dt_1,
-            "single_thread_sample": f"first {n1} frames, full DCT, 1 thread, {dt_1:.1f} s",
-            "cpu": platform.processor() or platform.machine()}
+    small = synth.patches_video()
 
+    def timed(cfg, v, threads):
+        t0 = time.perf_counter()
+        oracle.analyze(cfg, v.y, v.u, v.v, threads=threads)
+        return time.perf_counter() - t0
 
-def downsampled_bytes_per_frame(width: int, height: int, w: int) -> int:
-    """Input samples under the complete w x w blocks of the half-size planes
-    (each analysed sample is the mean of a 2 x 2 input block)."""
-    return 4 * algorithmic_bytes_per_frame(width // 2, height // 2, w)
+    full = oracle.Config(WIDTH, HEIGHT, 8, BLOCK, 0)
+    k16 = oracle.Config(WIDTH, HEIGHT, 8, BLOCK, 16)
+    c720 = oracle.Config(small.width, small.height, 8, BLOCK, 0)
+    t_all = timed(full, video, cores)
+    t_k16_all = timed(k16, video, cores)
+    t_one = timed(full, video, 1)
+    t_k16_one = timed(k16, video, 1)
+    t720_all = timed(c720, small, cores)
+    t720_one = timed(c720, small, 1)
+    n720 = small.n_frames
+    return {"value": frames / t_all, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {frames} frames of the 600-frame 3840x2160 8-bit workload, w=32, "
+                      f"full DCT, {cores} OpenMP threads (every core of this process's affinity), "
+                      f"{t_all:.1f} s wall",
+            "cpu": cpu_model(),
+            "full_single_thread": frames / t_one,
+            "lowpass_k16_all_cores": frames / t_k16_all,
+            "lowpass_k16_single_thread": frames / t_k16_one,
+            "patches_720p_all_cores": n720 / t720_all,
+            "patches_720p_single_thread": n720 / t720_one,
+            "detail": f"2160p: full {t_all:.2f} s ({cores} threads) / {t_one:.2f} s (1 thread), "
+                      f"K=16 {t_k16_all:.2f} s / {t_k16_one:.2f} s for {frames} frames; "
+                      f"720p patches workload ({n720} frames, full DCT) {t720_all:.3f} s / "
+                      f"{t720_one:.3f} s"}
 
 
 def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool,
-             downsample: bool = False) -> dict:
+             downsample: bool = False, block_size: int = BLOCK) -> dict:
     import torch
-    an = vca.Analyzer(WIDTH, HEIGHT, block_size=BLOCK, lowpass_k=lowpass_k, timing=True,
+    an = vca.Analyzer(WIDTH, HEIGHT, block_size=block_size, lowpass_k=lowpass_k, timing=True,
                       max_batch=MAX_BATCH, downsample=downsample)
     planes = dev.planes()
     launch = an.tune(*planes, reps=2) if tune else an.tuned_launch()
@@ -109,34 +139,87 @@ def run_mode(vca, dev, lowpass_k: int, steps: int, warmup: int, tune: bool,
     dt = time.perf_counter() - t0
     tm = an.timing(reset=True)
     an.close()
+    return launch_record(tm, steps * FRAMES / dt, dt * 1e3 / steps, WIDTH, HEIGHT, block_size,
+                         lowpass_k, 8, downsample, launch, feats)
+
+
+def launch_record(tm: dict, fps: float, ms_per_step: float, width: int, height: int, w: int,
+                  k: int, bit_depth: int, downsample: bool, launch: dict, feats) -> dict:
+    """Rates of the forward kernel from the library's HIP-event times: HBM
+    against the frame's algorithmic bytes (every sample once), int8 matrix
+    cores against the transform's algorithmic ops and against the ops issued
+    (hi/lo split included)."""
     fwd_ms = tm["forward_ms"] / max(1, tm["forward_launches"])
     red_ms = tm["reduce_ms"] / max(1, tm["reduce_launches"])
     frames_per_launch = tm["frames"] / max(1, tm["forward_launches"])
-    per_frame = (downsampled_bytes_per_frame if downsample else algorithmic_bytes_per_frame)(
-        WIDTH, HEIGHT, BLOCK)
-    alg_bytes = per_frame * frames_per_launch
+    alg_bytes = frame_bytes(width, height, bit_depth) * frames_per_launch
     gbs = alg_bytes / (fwd_ms * 1e-3) / 1e9
-    mfma_frame = (mfma_ops_per_frame(WIDTH // 2, HEIGHT // 2, BLOCK) if downsample
-                  else mfma_ops_per_frame(WIDTH, HEIGHT, BLOCK, lowpass_k))
-    tops = mfma_frame * frames_per_launch / (fwd_ms * 1e-3) / 1e12
+    aw, ah = (width // 2, height // 2) if downsample else (width, height)
+    alg_tops = int8_ops_per_frame(aw, ah, w, k) * frames_per_launch / (fwd_ms * 1e-3) / 1e12
+    iss_tops = (mfma_issued_ops_per_frame(aw, ah, w, k, bit_depth) * frames_per_launch
+                / (fwd_ms * 1e-3) / 1e12)
     return {
-        "fps": steps * FRAMES / dt,
-        "ms_per_step": dt * 1e3 / steps,
+        "fps": fps,
+        "ms_per_step": ms_per_step,
         "forward_kernel_ms": fwd_ms,
         "reduce_kernel_ms": red_ms,
         "frames_per_launch": frames_per_launch,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
-        "mfma": {"achieved": tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
-                 "frac": tops / INT8_PEAK_TOPS},
+        "mfma": {"achieved": alg_tops, "peak": INT8_PEAK_TOPS, "unit": "TOP/s",
+                 "frac": alg_tops / INT8_PEAK_TOPS, "ops": "algorithmic (transform multiply-adds x 2)",
+                 "issued_achieved": iss_tops, "issued_frac": iss_tops / INT8_PEAK_TOPS},
         "last_features": [float(x) for x in feats[-1]],
         "launch": launch,
     }
 
 
+TENBIT_FRAMES = 300
+
+
+def run_tenbit(vca, steps: int, warmup: int, tune: bool) -> dict:
+    """The 10-bit precision-stress workload: 300 frames of 3840x2160 and of
+    1920x1080 10-bit 4:2:0 (uint16 samples), w = 32 and 16, full DCT, one
+    launch per step.  Three stress frames (full-range noise, saturated edges
+    and sign-matched worst-case blocks) repeat on the device as frames t % 3."""
+    import numpy as np
+    import torch
+    import synth
+    out = {}
+    for width, height in ((3840, 2160), (1920, 1080)):
+        for w in (32, 16):
+            base = synth.stress_video(width, height, 3, cell=w, stream=300 + w)
+            idx = torch.arange(TENBIT_FRAMES, device="cuda") % 3
+            planes = [torch.from_numpy(p.view(np.int16)).cuda()[idx].contiguous()
+                      for p in (base.y, base.u, base.v)]
+            an = vca.Analyzer(width, height, bit_depth=10, block_size=w, timing=True,
+                              max_batch=TENBIT_FRAMES)
+            launch = an.tune(*planes, reps=2) if tune else an.tuned_launch()
+            for _ in range(warmup):
+                an.features(an.submit(*planes), TENBIT_FRAMES)
+            an.timing(reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                feats = an.features(an.submit(*planes), TENBIT_FRAMES)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rec = launch_record(an.timing(reset=True), steps * TENBIT_FRAMES / dt, dt * 1e3 / steps,
+                                width, height, w, 0, 10, False, launch, feats)
+            an.close()
+            del planes
+            torch.cuda.empty_cache()
+            rec.pop("last_features")
+            rec["frame_bytes"] = frame_bytes(width, height, 10)
+            out[f"{width}x{height}_w{w}"] = rec
+            log(f"10-bit {width}x{height} w={w}: {rec['fps']:.0f} frames/s, forward "
+                f"{rec['forward_kernel_ms']:.3f} ms, HBM {rec['roofline']['frac']:.3f}")
+    return out
+
+
 def plane_bytes(d: dict) -> int:
-    """Samples inside complete blocks of one frame of a stream (8-bit)."""
-    return algorithmic_bytes_per_frame(d["width"], d["height"], d["block_size"])
+    """Algorithmic bytes of one frame of a stream (8-bit)."""
+    return frame_bytes(d["width"], d["height"])
 
 
 def small_streams(n: int = 256, frames: int = 8) -> list:
@@ -443,12 +526,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-frames", type=int, default=512,
-                    help="frames of the oracle's bounded CPU sample (0 skips it)")
-    ap.add_argument("--modes", default="full,lowpass,downsample,ingest,batch,backward",
+    ap.add_argument("--cpu-frames", type=int, default=60,
+                    help="2160p frames of the oracle's bounded CPU sample (0 skips it)")
+    ap.add_argument("--modes",
+                    default="full,lowpass,downsample,blocksizes,tenbit,ingest,batch,backward",
                     help="comma list of full, lowpass (K = 16 crop), downsample (the paper's 2x "
-                         "downsampled low-pass), ingest (frames from host memory and a .yuv "
-                         "file), batch, backward")
+                         "downsampled low-pass), blocksizes (w = 16 and 8, full DCT), tenbit "
+                         "(the 10-bit stress workload), ingest (frames from host memory and a "
+                         ".yuv file), batch, backward")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB from a cold source (the "
@@ -478,7 +563,8 @@ def main() -> int:
     results = {}
     modes = args.modes.split(",")
     sv = dev = None
-    if any(m in modes for m in ("full", "lowpass", "downsample", "ingest")) or args.cpu_frames > 0:
+    if any(m in modes for m in ("full", "lowpass", "downsample", "blocksizes", "ingest")) \
+            or args.cpu_frames > 0:
         log("generating the 600-frame 2160p synthetic workload")
         sv = synth.scene_video(WIDTH, HEIGHT, FRAMES)
         dev = scene_to_device(sv)
@@ -491,11 +577,23 @@ def main() -> int:
                                  downsample=mode == "downsample")
         log(f"mode={mode}: {results[mode]['fps']:.0f} frames/s, forward kernel "
             f"{results[mode]['forward_kernel_ms']:.3f} ms/launch, launch {results[mode]['launch']}")
+    sizes = {}
+    if "blocksizes" in modes:
+        for w in (16, 8):
+            log(f"timing block size w={w} (full DCT)")
+            r = run_mode(vca, dev, 0, args.steps, args.warmup, not args.no_tune, block_size=w)
+            r.pop("last_features")
+            sizes[f"w{w}"] = r
+            log(f"w={w}: {r['fps']:.0f} frames/s, forward kernel {r['forward_kernel_ms']:.3f} ms/launch")
     latency = None
     if "full" in modes:
         latency = run_latency(vca, dev)
         log(f"single-frame latency: median {latency['median_us']:.1f} us, "
             f"p99 {latency['p99_us']:.1f} us")
+    tenbit = None
+    if "tenbit" in modes:
+        log("timing the 10-bit precision-stress workload")
+        tenbit = run_tenbit(vca, args.steps, args.warmup, not args.no_tune)
     ingest = None
     if "ingest" in modes:
         log("timing host-resident ingest")
@@ -584,6 +682,22 @@ def main() -> int:
                 entry["roofline"]["traffic"] = traffic[mode]
     if copy is not None:
         line["calibration_copy"] = copy
+    if sizes:
+        line["block_sizes_8bit"] = {k: {"value": v["fps"], "unit": "frames/s",
+                                        "ms_per_step": v["ms_per_step"], "roofline": v["roofline"],
+                                        "mfma": v["mfma"], "forward_kernel_ms": v["forward_kernel_ms"],
+                                        "launch": v["launch"]} for k, v in sizes.items()}
+        line["block_sizes_8bit"]["workload"] = ("the same 600 frames of 3840x2160 8-bit 4:2:0, "
+                                                "full DCT, one launch per step")
+    if tenbit is not None:
+        line["tenbit_stress"] = {k: {"value": v["fps"], "unit": "frames/s",
+                                     "ms_per_step": v["ms_per_step"], "roofline": v["roofline"],
+                                     "mfma": v["mfma"], "forward_kernel_ms": v["forward_kernel_ms"],
+                                     "frame_bytes": v["frame_bytes"], "launch": v["launch"]}
+                                 for k, v in tenbit.items()}
+        line["tenbit_stress"]["workload"] = (f"{TENBIT_FRAMES} frames of 10-bit 4:2:0 (uint16) per "
+                                             "step, full DCT: full-range noise, saturated edges "
+                                             "and sign-matched worst-case blocks")
     if latency is not None:
         line["single_frame_latency"] = latency
     if ingest is not None:

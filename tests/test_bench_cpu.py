@@ -14,35 +14,38 @@ import bench
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_algorithmic_bytes_per_2160p_frame():
-    # w = 32: 120 x 67 luma blocks and 2 x 60 x 33 chroma blocks of 1024 samples
-    assert bench.algorithmic_bytes_per_frame(3840, 2160, 32) == (120 * 67 + 2 * 60 * 33) * 1024
-    assert bench.algorithmic_bytes_per_frame(3840, 2160, 32) == 12_288_000
-    # w = 16: 240 x 135 and 2 x 120 x 67 blocks of 256 samples
-    assert bench.algorithmic_bytes_per_frame(3840, 2160, 16) == (240 * 135 + 2 * 120 * 67) * 256
-    # w = 8 covers every sample of a 2160p frame
-    assert bench.algorithmic_bytes_per_frame(3840, 2160, 8) == 3840 * 2160 * 3 // 2
+def test_frame_bytes():
+    # every sample of Y (3840 x 2160) and of U and V (1920 x 1080) once
+    assert bench.frame_bytes(3840, 2160) == 12_441_600
+    assert bench.frame_bytes(3840, 2160, 10) == 24_883_200       # uint16 samples
+    assert bench.frame_bytes(1920, 1080, 10) == 6_220_800
+    assert bench.frame_bytes(1280, 720) == 1_382_400
 
 
-def test_downsampled_bytes_per_2160p_frame():
-    # the half-size video's blocks (60 x 33 luma, 2 x 30 x 16 chroma), each
-    # analysed sample the mean of four input samples
-    assert bench.downsampled_bytes_per_frame(3840, 2160, 32) == 4 * (60 * 33 + 2 * 30 * 16) * 1024
-    assert bench.downsampled_bytes_per_frame(3840, 2160, 32) == 12_042_240
+def test_algorithmic_int8_ops_per_2160p_frame():
+    blocks = 120 * 67 + 2 * 60 * 33     # w = 32, complete blocks only
+    assert bench.block_count(3840, 2160, 32) == blocks == 12_000
+    # per block w*K*w + K*K*w multiply-adds, 2 ops each
+    assert bench.int8_ops_per_frame(3840, 2160, 32) == blocks * 2 * 2 * 32 ** 3
+    assert bench.int8_ops_per_frame(3840, 2160, 32) == 1_572_864_000
+    assert bench.int8_ops_per_frame(3840, 2160, 32, 16) == blocks * 2 * (16 * 32 * 32 + 16 * 16 * 32)
+    assert bench.int8_ops_per_frame(3840, 2160, 32, 16) == 589_824_000
 
 
-def test_matrix_core_ops_per_2160p_frame():
+def test_matrix_core_issued_ops_per_2160p_frame():
     product = 2 * 32 * 32 * 32        # int8 ops of one 32x32x32 product
     tiles = 120 * 67 + 2 * 60 * 33     # w = 32: one block per 32 x 32 tile
     # full transform: horizontal pass + hi and lo vertical passes per tile
-    assert bench.mfma_ops_per_frame(3840, 2160, 32) == tiles * 3 * product
+    assert bench.mfma_issued_ops_per_frame(3840, 2160, 32) == tiles * 3 * product
     # K = 16: two sample tiles share one pair of vertical-pass products
-    assert bench.mfma_ops_per_frame(3840, 2160, 32, 16) == tiles * 2 * product
+    assert bench.mfma_issued_ops_per_frame(3840, 2160, 32, 16) == tiles * 2 * product
     # K = 8: four sample tiles share them
-    assert bench.mfma_ops_per_frame(3840, 2160, 32, 8) == tiles * 6 // 4 * product
+    assert bench.mfma_issued_ops_per_frame(3840, 2160, 32, 8) == tiles * 6 // 4 * product
     # w = 16: four blocks per 32 x 32 tile
     tiles16 = (240 * 135 + 2 * 120 * 67) // 4
-    assert bench.mfma_ops_per_frame(3840, 2160, 16) == tiles16 * 3 * product
+    assert bench.mfma_issued_ops_per_frame(3840, 2160, 16) == tiles16 * 3 * product
+    # 10-bit: two horizontal-pass products per tile
+    assert bench.mfma_issued_ops_per_frame(3840, 2160, 32, 0, 10) == tiles * 4 * product
 
 
 def test_small_streams_workload():
