@@ -271,12 +271,14 @@ vca_status vca_analyze_noalloc(const vca_config* cfg, const vca_frames* frames, 
 
 /* ------------------------------------------------------------ batched form
  * Many independent streams -- each with its own resolution, block size,
- * low-pass size, bit depth and frame count -- analysed by ONE persistent
- * kernel launch over all their tiles (its wavefronts draw work from a
- * device counter that a one-thread kernel zeroes first) plus one reduction
- * launch, captured into a hipGraph on the first call with a given
- * frame-count signature and replayed afterwards (only the per-stream
- * descriptor tables are uploaded per call).  Per stream the results are identical to a
+ * low-pass size, bit depth and frame count -- analysed in one round of
+ * launches: per class of streams (bit depth, w, K) ONE persistent kernel
+ * launch over all their tiles (its wavefronts draw work from a device counter
+ * of the class; one small kernel zeroes the counters first), each followed by
+ * the class's reduction launch, the classes on parallel branches; the round
+ * is captured into a hipGraph on the first call with a given frame-count
+ * signature and replayed afterwards (only the per-stream descriptor tables
+ * are uploaded per call).  Per stream the results are identical to a
  * vca_ctx opened with the same configuration and fed the same frames. */
 typedef struct vca_batch vca_batch; /* opaque; owned by the library */
 
@@ -315,15 +317,26 @@ vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32
                                    const int64_t* first, const int32_t* count,
                                    vca_frame_features* out_host);
 
-/* Autotuner of the batched launch shape (as vca_tune, over the first round
- * of the given frames of every stream); cached under the batch's stream
+/* Autotuner of the batched launch shapes: over the first round of the given
+ * frames of every stream, times each class's forward launch alone for every
+ * ring depth (1, 2, 4) and every count of workgroups per compute unit that
+ * fits, and keeps the fastest per class; cached under the batch's stream
  * list.  Features and h state are unchanged. */
 vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames,
                           int32_t reps);
 
-/* Launch shape of the batch (see vca_tuned_launch). */
+/* Launch shape of the batch (see vca_tuned_launch): the shape of its most
+ * expensive class, and the sum of the classes' tuned forward times. */
 vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* groups_per_cu,
                                   double* ms);
+
+/* Per class of streams, the tuned forward launch: ms[k] its device time alone
+ * (0 for a class not tuned), depth[k] and groups_per_cu[k] its shape (0 when
+ * untuned).  Each output may be NULL, else an array of 18 entries indexed by
+ * class k = (B == 10 ? 9 : 0) + 3 * (w == 32 ? 0 : w == 16 ? 1 : 2) +
+ * (K == w ? 0 : K == w / 2 ? 1 : 2).  Host only. */
+vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
+                                 int32_t* groups_per_cu);
 
 /* Device time of the batch's launches (both kernels), measured with HIP
  * events on its stream when any stream was opened with VCA_F_TIMING. */

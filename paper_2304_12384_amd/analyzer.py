@@ -341,8 +341,8 @@ class _StreamGeom:
 
 
 class Batch:
-    """Wraps one ``vca_batch``: many streams analysed by one persistent,
-    graph-replayed launch.
+    """Wraps one ``vca_batch``: many streams analysed by one graph-replayed
+    round (one persistent launch per class of streams).
 
     >>> b = Batch([dict(width=1920, height=1080, block_size=16), dict(width=640, height=360)])
     >>> b.submit([(y0, u0, v0), (y1, u1, v1)])
@@ -458,6 +458,24 @@ class Batch:
                                                 ctypes.byref(ms)), "vca_batch_tuned_launch",
               batch=self._b)
         return {"depth": d.value, "groups_per_cu": g.value, "ms": ms.value}
+
+    def class_times(self) -> dict:
+        """Tuned forward launch of each class present: {"b8_w32_k32": {"ms", "depth",
+        "groups_per_cu"}, ...} (device time of the class's launch alone)."""
+        ms = (ctypes.c_double * 18)()
+        dp = (ctypes.c_int32 * 18)()
+        gp = (ctypes.c_int32 * 18)()
+        check(_lib.lib().vca_batch_class_times(self._b, ms, dp, gp), "vca_batch_class_times",
+              batch=self._b)
+        out = {}
+        for k in range(18):
+            if dp[k] <= 0:
+                continue
+            bits = 10 if k >= 9 else 8
+            w = (32, 16, 8)[(k // 3) % 3]
+            kk = w // (1, 2, 4)[k % 3]
+            out[f"b{bits}_w{w}_k{kk}"] = {"ms": ms[k], "depth": dp[k], "groups_per_cu": gp[k]}
+        return out
 
     def timing(self, reset: bool = False) -> dict:
         ms, n, fr = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()

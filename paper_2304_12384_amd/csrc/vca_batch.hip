@@ -1,18 +1,21 @@
 // vca_batch.hip -- batched form of the VCA forward path (gfx950).
 //
 // Many independent video streams of different resolution, block size, bit
-// depth and frame count are analysed by ONE persistent launch: every
-// wavefront takes chunks of a flat list (runs of kChunkStrips consecutive
-// strips of one stream, vca_strip.h; a stream's chunks are contiguous) from a
-// device-wide counter, so that waves that drew cheap chunks take more and
-// all finish together, copies the chunk's stream descriptor into registers,
-// and runs the strip loop specialised for the stream's (bit depth, w, K)
-// class.  A second launch reduces every (stream, frame) pair to its seven
-// features (vca_reduce.h).  The three kernels of a round (counter reset,
-// forward, reduction) are captured once into a hipGraph per frame-count
-// signature and replayed; per call only the descriptor tables (frame
-// pointers, state buffers) are uploaded.  The ring depth and workgroups per
-// CU come from vca_tune_batch.
+// depth and frame count are analysed in one round of launches: the streams
+// are grouped by class (bit depth, w, K), and each class present gets ONE
+// persistent launch of a kernel specialised for it (its own register budget,
+// ring depth and workgroups per CU, chosen by vca_tune_batch).  Its
+// wavefronts take chunks of the class's flat list (runs of kChunkStrips
+// consecutive strips of one stream, vca_strip.h; a stream's chunks are
+// contiguous) from the class's device counter, so that waves that drew cheap
+// chunks take more and all finish together, and run the plain path's strip
+// loop.  Right after a class's forward launch, a reduction launch turns each
+// of the class's (stream, frame) pairs into its seven features
+// (vca_reduce.h).  Classes run on parallel branches (forked streams), so one
+// class's reduction and tail overlap another's forward work.  A round's
+// launches (counter reset, then the branches) are captured once into a
+// hipGraph per frame-count signature and replayed; per call only the
+// descriptor tables (frame pointers, state buffers) are uploaded.
 
 #include <hip/hip_runtime.h>
 
@@ -56,6 +59,8 @@ struct StreamDesc {
   int32_t stream;                  // index of the stream
 };
 
+using ConstDesc = __attribute__((address_space(4))) const StreamDesc;
+
 // Consecutive strips of one stream handed to a wavefront at a time.
 constexpr int kChunkStrips = 32;
 static_assert(kChunkStrips % kRun == 0, "chunks start on a run boundary");
@@ -70,24 +75,23 @@ struct KindRange {
 
 struct BatchParams {
   const StreamDesc* streams;   // in flat order (by class, then stream)
-  KindRange kinds[kKinds];
-  int32_t total_chunks;
-  const v4i* tab_b1p;    // [kKinds][kMaxPack][64] packed stage-1 operands
-  const v4i* tab_a2;     // [kKinds][64]
-  const double* tab_wp;  // [kKinds][16][64] packed-layout weights
+  KindRange kr;                // the class's descriptors and chunks
+  const v4i* tab_b1p;    // the class's packed stage-1 operands [kMaxPack][64]
+  const v4i* tab_a2;     // [64]
+  const double* tab_wp;  // [16][64] packed-layout weights
   double* blk_h;
   int32_t* blk_dc;
   int32_t* err_flag;      // per frame of the round (StripGeom::frame_base + frame):
                           // a validated 10-bit sample above 1023
-  int32_t* queue;         // next chunk to hand out; zero at launch
+  int32_t* queue;         // the class's next chunk (relative to kr.chunk_begin); zero at launch
 };
 
 struct BatchReduceParams {
-  const ReduceParams* red;    // per stream; red[s].frame_begin = first workgroup of s
+  const ReduceParams* red;    // the class's streams; red[s].frame_begin = first workgroup of s
   int32_t n_streams;
 };
 
-// The next chunk of the launch for the calling wavefront (one atomic per
+// The next chunk of the class for the calling wavefront (one atomic per
 // wavefront, result broadcast).  Chunks are handed out in increasing order.
 __device__ __forceinline__ int next_chunk(int32_t* queue, int lane) {
   int c = 0;
@@ -95,86 +99,45 @@ __device__ __forceinline__ int next_chunk(int32_t* queue, int lane) {
   return __builtin_amdgcn_readfirstlane(c);
 }
 
-// The chunks of one class that the calling wavefront draws: c is its current
-// chunk on entry (at or after the class's first chunk) and its first chunk
-// past the class on return.  The class's descriptors are contiguous and c
-// only grows, so the stream search only moves forward; the class's operand
-// tables are loaded once.
+// Persistent kernel of one class: every wavefront draws the class's chunks
+// until its list is exhausted.  The class's descriptors are contiguous and a
+// wavefront's chunks only grow, so its stream search only moves forward.
 template <int kBits, int kW, int kK, int kDepth>
-__device__ __forceinline__ void run_kind(const BatchParams& p, int kind, int& c, const TileOut& o0,
-                                         int lane, uint8_t* stage) {
-  const KindRange kr = p.kinds[kind];
-  PackConsts<kW, kK> pc;
-  pc.load(p.tab_b1p + kind * kMaxPack * 64, p.tab_a2 + kind * 64, p.tab_wp + kind * 16 * 64, lane);
-  TileOut o = o0;
-  int d = kr.desc_begin;
-  for (; c < kr.chunk_end; c = next_chunk(p.queue, lane)) {
-    while (d < kr.desc_end - 1 && c >= p.streams[d].chunk_end) d++;
-    const StreamDesc& sd = p.streams[d];
-    o.validate = sd.validate;
-    const int s0 = (c - sd.chunk_begin) * kChunkStrips;
-    const int s1 = min(s0 + kChunkStrips, sd.strips);
-    run_strips<kBits, kW, kK, kDepth, false, (kBits != 8)>(sd.geom, o, pc, s0 / kRun, 1, s1, lane, stage);
-  }
-}
-
-// The classes one after the other, each its own loop (a switch inside one
-// loop made the compiler allocate registers for several classes at once).
-template <int kDepth, int kBits, int kW, int kK>
-__device__ __forceinline__ void run_kind_if(const BatchParams& p, int kind, int& c,
-                                            const TileOut& o, int lane, uint8_t* stage) {
-  if (c < p.kinds[kind].chunk_end)
-    run_kind<kBits, kW, kK, kDepth>(p, kind, c, o, lane, stage);
-}
-
-// Persistent batched kernel: every wavefront draws chunks until the list is
-// exhausted, walking the classes in the list's order.
-// kOnly8: every stream of the launch is 8-bit (the 10-bit classes are left
-// out, which lowers the kernel's register allocation).  The register budget
-// is held at three wavefronts per SIMD for the 8-bit kernel and two for the
-// one that serves both bit depths (which then keeps a few values in scratch
-// rather than drop to one wavefront per SIMD).
-template <int kDepth, bool kOnly8>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kOnly8 ? 3 : 2)))
-void batch_fwd_kernel(BatchParams p) {
+__global__ __launch_bounds__(kThreads) void batch_class_kernel(BatchParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr int kStage = stage_bytes(kW);
+  __shared__ __attribute__((aligned(16))) uint8_t stage_mem[kWaves][kStage];
   TileOut o;
   o.blk_h = p.blk_h;
   o.blk_dc = p.blk_dc;
   o.coeffs = nullptr;
   o.err_flag = p.err_flag;
   o.validate = 0;
-  // output staging of the w = 16 and 8 classes (the largest is w = 8's)
-  __shared__ __attribute__((aligned(16))) uint8_t stage_mem[kWaves][stage_bytes(8)];
-  uint8_t* stage = stage_mem[wave];
-  int c = next_chunk(p.queue, lane);
-  run_kind_if<kDepth, 8, 32, 32>(p, 0, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 32, 16>(p, 1, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 32, 8>(p, 2, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 16, 16>(p, 3, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 16, 8>(p, 4, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 16, 4>(p, 5, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 8, 8>(p, 6, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 8, 4>(p, 7, c, o, lane, stage);
-  run_kind_if<kDepth, 8, 8, 2>(p, 8, c, o, lane, stage);
-  if constexpr (!kOnly8) {
-    run_kind_if<kDepth, 10, 32, 32>(p, 9, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 32, 16>(p, 10, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 32, 8>(p, 11, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 16, 16>(p, 12, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 16, 8>(p, 13, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 16, 4>(p, 14, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 8, 8>(p, 15, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 8, 4>(p, 16, c, o, lane, stage);
-    run_kind_if<kDepth, 10, 8, 2>(p, 17, c, o, lane, stage);
+  PackConsts<kW, kK> pc;
+  pc.load(p.tab_b1p, p.tab_a2, p.tab_wp, lane);
+  // The descriptors stay unchanged while the launch runs: reading them
+  // through the constant address space gives scalar loads, as for a kernel
+  // argument, where generic loads would be vector loads whose wait also
+  // drains the tile prefetch ring.
+  const ConstDesc* streams = (const ConstDesc*)p.streams;
+  int d = p.kr.desc_begin;
+  for (int c = p.kr.chunk_begin + next_chunk(p.queue, lane); c < p.kr.chunk_end;
+       c = p.kr.chunk_begin + next_chunk(p.queue, lane)) {
+    while (d < p.kr.desc_end - 1 && c >= streams[d].chunk_end) d++;
+    o.validate = streams[d].validate;
+    const int s0 = (c - streams[d].chunk_begin) * kChunkStrips;
+    const int s1 = min(s0 + kChunkStrips, streams[d].strips);
+    run_strips<kBits, kW, kK, kDepth, false, (kBits != 8)>(
+        *(const StripGeom*)&streams[d].geom, o, pc, s0 / kRun, 1, s1, lane,
+        stage_mem[wave]);
   }
 }
 
-// Zeroes the chunk counter ahead of the forward launch (a kernel node rather
-// than a memset, so the captured graph holds kernels only).
+// Zeroes the classes' chunk counters ahead of the forward launches (a kernel
+// node rather than a memset, so the captured graph holds kernels only).
 __global__ void queue_reset_kernel(int32_t* queue) {
-  if (threadIdx.x == 0) *queue = 0;
+  if (threadIdx.x < kKinds) queue[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(kReduceThreads) void batch_reduce_kernel(BatchReduceParams p) {
@@ -191,15 +154,31 @@ __global__ __launch_bounds__(kReduceThreads) void batch_reduce_kernel(BatchReduc
 
 using BatchKernel = void (*)(BatchParams);
 
-BatchKernel batch_kernel_for(int depth, bool only8) {
-  if (only8) {
-    if (depth == 1) return batch_fwd_kernel<1, true>;
-    if (depth >= 4) return batch_fwd_kernel<4, true>;
-    return batch_fwd_kernel<2, true>;
-  }
-  if (depth == 1) return batch_fwd_kernel<1, false>;
-  if (depth >= 4) return batch_fwd_kernel<4, false>;
-  return batch_fwd_kernel<2, false>;
+template <int B, int W, int K>
+BatchKernel pick_class_depth(int depth) {
+  if (depth == 1) return batch_class_kernel<B, W, K, 1>;
+  if (depth >= 4) return batch_class_kernel<B, W, K, 4>;
+  return batch_class_kernel<B, W, K, 2>;
+}
+
+template <int B, int W>
+BatchKernel pick_class_k(int ki, int depth) {
+  if (ki == 0) return pick_class_depth<B, W, W>(depth);
+  if (ki == 1) return pick_class_depth<B, W, W / 2>(depth);
+  return pick_class_depth<B, W, W / 4>(depth);
+}
+
+template <int B>
+BatchKernel pick_class_w(int wi, int ki, int depth) {
+  if (wi == 0) return pick_class_k<B, 32>(ki, depth);
+  if (wi == 1) return pick_class_k<B, 16>(ki, depth);
+  return pick_class_k<B, 8>(ki, depth);
+}
+
+// Kernel of class `kind` (kind_of numbering) with the given ring depth.
+BatchKernel class_kernel_for(int kind, int depth) {
+  const int ki = kind % 3, wi = (kind / 3) % 3;
+  return kind < 9 ? pick_class_w<8>(wi, ki, depth) : pick_class_w<10>(wi, ki, depth);
 }
 
 }  // namespace
@@ -229,7 +208,7 @@ struct vca_batch {
   int32_t* frame_err = nullptr;    // per frame of a round: validation marks (device)
   int32_t* err_rings = nullptr;    // device view of err_rings_host
   int32_t* err_rings_host = nullptr;   // pinned, mapped: per stream [feature_capacity] marks
-  int32_t* queue = nullptr;        // chunk counter of the forward launch
+  int32_t* queue = nullptr;        // [kKinds] chunk counters of the forward launches
   std::vector<int> cur_state;
   std::vector<char> has_prev;
   std::vector<int64_t> submitted;
@@ -241,14 +220,24 @@ struct vca_batch {
   ReduceParams* h_red = nullptr;
   hipEvent_t uploaded = nullptr;   // staging buffers reusable once this completes
   bool upload_pending = false;
-  // graph of the last launch signature
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  std::vector<int32_t> graph_sig;
+  // executable graphs of the recent launch signatures (frames per stream and
+  // per-class launch shapes), least recently used first out
+  struct CachedGraph {
+    std::vector<int32_t> sig;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+  };
+  std::vector<CachedGraph> graphs;
+  uint64_t graph_clock = 0;
   bool use_graph = true;
-  bool only8 = true;               // no 10-bit stream: the 8-bit-only kernel serves
   KindRange kinds[kKinds] = {};    // flat-list ranges of the current round
-  LaunchChoice tuned;
+  int32_t kind_frames[kKinds] = {};   // frames of each class in the current round
+  hipStream_t branch[kKinds] = {};    // one per class launched, forked from the launch stream
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kKinds] = {};
+  LaunchChoice kind_tuned[kKinds];    // per class: ring depth, workgroups per CU, ms
+  LaunchChoice tuned;                 // summary: the most expensive class's shape, total ms
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -279,12 +268,17 @@ vca_status balloc(vca_batch* b, T** p, size_t count) {
   return VCA_OK;
 }
 
-void drop_graph(vca_batch* b) {
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->exec = nullptr;
-  b->graph = nullptr;
-  b->graph_sig.clear();
+constexpr size_t kMaxGraphs = 8;
+
+// Destroys every cached graph.  The caller has drained the batch's stream:
+// an executable graph whose launch may still be pending is never destroyed
+// (its independent branches run on streams the executable owns).
+void drop_graphs(vca_batch* b) {
+  for (auto& c : b->graphs) {
+    if (c.exec) (void)hipGraphExecDestroy(c.exec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+  }
+  b->graphs.clear();
 }
 
 // Fills the staging descriptors for one round: stream s analyses frames
@@ -328,64 +322,115 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
     kr.desc_end = i;
     kr.chunk_end = chunks;
   }
-  for (int s = 0; s < b->n; s++) {
-    const Geometry& g = b->geos[s];
-    const vca_config& c = b->cfgs[s];
-    ReduceParams& rp = b->h_red[s];
-    std::memset(&rp, 0, sizeof(rp));
-    const double ww = (double)c.block_size * c.block_size;
-    rp.blk_h = b->blk_h + b->blk_base[s];
-    rp.blk_dc = b->blk_dc + b->blk_base[s];
-    double* st = b->state + b->state_off[s];
-    rp.state_in = b->has_prev[s] ? st + (int64_t)b->cur_state[s] * g.cnt[0] : nullptr;
-    rp.state_out = st + (int64_t)(b->cur_state[s] ^ 1) * g.cnt[0];
-    rp.ring = b->rings + b->ring_off[s];
-    rp.frame_err = (c.flags & VCA_F_VALIDATE) ? b->frame_err + frames : nullptr;
-    rp.err_ring = b->err_rings + b->ring_off[s] / 7;
-    rp.first_frame = b->submitted[s];
-    rp.capacity = c.feature_capacity;
-    for (int P = 0; P < 3; P++) {
-      rp.cnt[P] = g.cnt[P];
-      rp.inv_norm[P] = 1.0 / ((double)g.cnt[P] * ww);
+  // reduction records in the flat order (by class, then stream); each
+  // class's reduction launch numbers its workgroups from 0
+  for (int k = 0; k < kKinds; k++) {
+    int32_t kframes = 0;
+    for (int i2 = b->kinds[k].desc_begin; i2 < b->kinds[k].desc_end; i2++) {
+      const int s = b->h_streams[i2].stream;
+      const Geometry& g = b->geos[s];
+      const vca_config& c = b->cfgs[s];
+      ReduceParams& rp = b->h_red[i2];
+      std::memset(&rp, 0, sizeof(rp));
+      const double ww = (double)c.block_size * c.block_size;
+      rp.blk_h = b->blk_h + b->blk_base[s];
+      rp.blk_dc = b->blk_dc + b->blk_base[s];
+      double* st = b->state + b->state_off[s];
+      rp.state_in = b->has_prev[s] ? st + (int64_t)b->cur_state[s] * g.cnt[0] : nullptr;
+      rp.state_out = st + (int64_t)(b->cur_state[s] ^ 1) * g.cnt[0];
+      rp.ring = b->rings + b->ring_off[s];
+      rp.frame_err = (c.flags & VCA_F_VALIDATE) ? b->frame_err + frame_begin[s] : nullptr;
+      rp.err_ring = b->err_rings + b->ring_off[s] / 7;
+      rp.first_frame = b->submitted[s];
+      rp.capacity = c.feature_capacity;
+      for (int P = 0; P < 3; P++) {
+        rp.cnt[P] = g.cnt[P];
+        rp.inv_norm[P] = 1.0 / ((double)g.cnt[P] * ww);
+      }
+      rp.per_frame = g.per_frame;
+      rp.n_frames = cnt[s];
+      rp.frame_begin = kframes;
+      kframes += cnt[s];
+      frames += cnt[s];
     }
-    rp.per_frame = g.per_frame;
-    rp.n_frames = cnt[s];
-    rp.frame_begin = frames;
-    frames += cnt[s];
+    b->kind_frames[k] = kframes;
   }
   *total_chunks = chunks;
   *total_frames = frames;
 }
 
-vca_status enqueue_launches(vca_batch* b, hipStream_t st, int32_t total_chunks, int32_t total_frames,
-                            int depth, int gpc) {
-  BatchKernel kern = batch_kernel_for(depth, b->only8);
+// Launch shape of class k: tuned, else ring depth 2 and as many workgroups
+// per CU as fit.
+LaunchChoice class_choice(const vca_batch* b, int k) {
+  LaunchChoice c = b->kind_tuned[k];
+  if (c.depth <= 0) c = LaunchChoice{2, 0, 0.0};
+  return c;
+}
+
+// Enqueues class k's forward launch (and, with_reduce, its reduction) on st.
+vca_status launch_class(vca_batch* b, hipStream_t st, int k, const LaunchChoice& lc, bool with_reduce) {
+  const KindRange& kr = b->kinds[k];
+  BatchKernel kern = class_kernel_for(k, lc.depth);
   int resident = 0;
   BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kThreads, 0));
   resident = std::max(1, resident);
-  if (gpc > 0) resident = std::min(resident, gpc);
-  const int64_t groups = ((int64_t)total_chunks + kWaves - 1) / kWaves;
+  if (lc.groups_per_cu > 0) resident = std::min(resident, lc.groups_per_cu);
+  const int64_t groups = ((int64_t)(kr.chunk_end - kr.chunk_begin) + kWaves - 1) / kWaves;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)b->num_cus * resident));
   BatchParams bp{};
   bp.streams = b->d_streams;
-  for (int k = 0; k < kKinds; k++) bp.kinds[k] = b->kinds[k];
-  bp.total_chunks = total_chunks;
-  bp.tab_b1p = b->tab_b1p;
-  bp.tab_a2 = b->tab_a2;
-  bp.tab_wp = b->tab_wp;
+  bp.kr = kr;
+  bp.tab_b1p = b->tab_b1p + k * kMaxPack * 64;
+  bp.tab_a2 = b->tab_a2 + k * 64;
+  bp.tab_wp = b->tab_wp + k * 16 * 64;
   bp.blk_h = b->blk_h;
   bp.blk_dc = b->blk_dc;
   bp.err_flag = b->frame_err;
-  bp.queue = b->queue;
-  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, b->queue);
-  BHIP_TRY(b, hipGetLastError());
+  bp.queue = b->queue + k;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, bp);
   BHIP_TRY(b, hipGetLastError());
-  if (total_frames > 0) {
-    BatchReduceParams rp{b->d_red, b->n};
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(total_frames), dim3(kReduceThreads), 0, st, rp);
+  if (with_reduce && b->kind_frames[k] > 0) {
+    BatchReduceParams rp{b->d_red + kr.desc_begin, kr.desc_end - kr.desc_begin};
+    hipLaunchKernelGGL(batch_reduce_kernel, dim3(b->kind_frames[k]), dim3(kReduceThreads), 0, st, rp);
     BHIP_TRY(b, hipGetLastError());
   }
+  return VCA_OK;
+}
+
+// Classes with work in the current round.
+int present_classes(const vca_batch* b, int* list) {
+  int n = 0;
+  for (int k = 0; k < kKinds; k++)
+    if (b->kinds[k].chunk_end > b->kinds[k].chunk_begin) list[n++] = k;
+  return n;
+}
+
+// Streams and events of the fork (created before any capture).
+vca_status ensure_branches(vca_batch* b, int n) {
+  if (!b->fork_ev) BHIP_TRY(b, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
+  for (int j = 0; j < n; j++) {
+    if (!b->branch[j]) BHIP_TRY(b, hipStreamCreateWithFlags(&b->branch[j], hipStreamNonBlocking));
+    if (!b->join_ev[j]) BHIP_TRY(b, hipEventCreateWithFlags(&b->join_ev[j], hipEventDisableTiming));
+  }
+  return VCA_OK;
+}
+
+// One round on st: the counters reset, then each class's forward launch and
+// reduction on its own branch, joined back into st.
+vca_status enqueue_round(vca_batch* b, hipStream_t st) {
+  int list[kKinds];
+  const int n = present_classes(b, list);
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, b->queue);
+  BHIP_TRY(b, hipGetLastError());
+  if (n == 0) return VCA_OK;
+  BHIP_TRY(b, hipEventRecord(b->fork_ev, st));
+  for (int j = 0; j < n; j++) {
+    BHIP_TRY(b, hipStreamWaitEvent(b->branch[j], b->fork_ev, 0));
+    vca_status s = launch_class(b, b->branch[j], list[j], class_choice(b, list[j]), true);
+    if (s != VCA_OK) return s;
+    BHIP_TRY(b, hipEventRecord(b->join_ev[j], b->branch[j]));
+  }
+  for (int j = 0; j < n; j++) BHIP_TRY(b, hipStreamWaitEvent(st, b->join_ev[j], 0));
   return VCA_OK;
 }
 
@@ -424,6 +469,23 @@ std::string batch_tune_key(const vca_batch* b) {
   return buf;
 }
 
+std::string class_tune_key(const vca_batch* b, int k) { return batch_tune_key(b) + "/k" + std::to_string(k); }
+
+// Per-class shapes cached for this stream list (from an earlier vca_tune_batch
+// in the process or the VCA_TUNE_CACHE file), and their summary.
+void load_tuned(vca_batch* b) {
+  double total = 0.0, worst = -1.0;
+  for (int k = 0; k < kKinds; k++) {
+    if (!TuneCache::get().find(class_tune_key(b, k), &b->kind_tuned[k])) continue;
+    total += b->kind_tuned[k].ms;
+    if (b->kind_tuned[k].ms > worst) {
+      worst = b->kind_tuned[k].ms;
+      b->tuned = b->kind_tuned[k];
+    }
+  }
+  if (worst >= 0.0) b->tuned.ms = total;
+}
+
 // Validation marks of frames [first, first + count) of a stream (whose round
 // has completed): a message if one of them held a 10-bit sample above 1023.
 const char* invalid_frames(const vca_batch* b, int32_t s, int64_t first, int32_t count) {
@@ -456,7 +518,7 @@ void vca_close_batch(vca_batch* b) {
   {
     DeviceGuard g(b->device);
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    drop_graph(b);
+    drop_graphs(b);
     void* bufs[] = {b->tab_b1p, b->tab_a2,    b->tab_wp, b->blk_h,  b->blk_dc,
                     b->state,   b->d_streams, b->d_red,  b->queue, b->frame_err};
     for (void* p : bufs)
@@ -466,6 +528,11 @@ void vca_close_batch(vca_batch* b) {
     if (b->h_streams) (void)hipHostFree(b->h_streams);
     if (b->h_red) (void)hipHostFree(b->h_red);
     if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    for (int k = 0; k < kKinds; k++) {
+      if (b->join_ev[k]) (void)hipEventDestroy(b->join_ev[k]);
+      if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
+    }
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
     b->done.destroy();
     if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -514,7 +581,6 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
     round_frames += c.max_batch;
     b->geos[s].init(c);
     if (c.flags & VCA_F_TIMING) b->timing = true;
-    if (c.bit_depth != 8) b->only8 = false;
     b->blk_base[s] = blk;
     blk += (int64_t)c.max_batch * b->geos[s].per_frame;
     b->state_off[s] = st_total;
@@ -561,7 +627,7 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
     return bail(VCA_ERR_DEVICE);
   if ((s = balloc(b, &b->d_streams, n_streams)) != VCA_OK) return bail(s);
   if ((s = balloc(b, &b->d_red, n_streams)) != VCA_OK) return bail(s);
-  if ((s = balloc(b, &b->queue, 1)) != VCA_OK) return bail(s);
+  if ((s = balloc(b, &b->queue, kKinds)) != VCA_OK) return bail(s);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->h_streams), sizeof(StreamDesc) * n_streams, 0) != hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(ReduceParams) * n_streams, 0) != hipSuccess)
     return bail(VCA_ERR_OOM);
@@ -586,7 +652,7 @@ vca_status vca_open_batch(const vca_config* cfgs, int32_t n_streams, void* hip_s
       hipMemcpy(b->tab_wp, wall.data(), wall.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
     return bail(VCA_ERR_DEVICE);
   if (const char* e = std::getenv("VCA_BATCH_NO_GRAPH")) b->use_graph = !(e[0] == '1');
-  TuneCache::get().find(batch_tune_key(b), &b->tuned);
+  load_tuned(b);
   *out = b;
   return VCA_OK;
 }
@@ -596,8 +662,6 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
   vca_status st = check_batch_frames(b, frames, n_frames);
   if (st != VCA_OK) return st;
   DeviceGuard guard(b->device);
-  const int depth = b->tuned.depth > 0 ? b->tuned.depth : 2;
-  const int gpc = b->tuned.groups_per_cu;
   std::vector<int32_t> off(b->n, 0), cnt(b->n, 0);
   for (;;) {
     bool any = false;
@@ -610,6 +674,10 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
     int32_t chunks = 0, nfr = 0;
     fill_descriptors(b, frames, off.data(), cnt.data(), &chunks, &nfr);
     if ((st = upload_descriptors(b)) != VCA_OK) return st;
+    {
+      int list[kKinds];
+      if ((st = ensure_branches(b, present_classes(b, list))) != VCA_OK) return st;
+    }
     hipEvent_t* ev = nullptr;
     if (b->timing) {
       if (b->ev_used + 2 > b->ev_pool.size()) {
@@ -626,12 +694,26 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
     }
     if (b->use_graph) {
       std::vector<int32_t> sig(cnt);
-      sig.push_back(depth);
-      sig.push_back(gpc);
-      if (!b->exec || sig != b->graph_sig) {
-        drop_graph(b);
+      for (int k = 0; k < kKinds; k++) {
+        const LaunchChoice lc = class_choice(b, k);
+        sig.push_back(lc.depth);
+        sig.push_back(lc.groups_per_cu);
+      }
+      vca_batch::CachedGraph* hit = nullptr;
+      for (auto& c : b->graphs)
+        if (c.sig == sig) hit = &c;
+      if (!hit) {
+        if (b->graphs.size() >= kMaxGraphs) {
+          // evict the least recently used once the stream has drained
+          BHIP_TRY(b, hipStreamSynchronize(b->stream));
+          auto lru = std::min_element(b->graphs.begin(), b->graphs.end(),
+                                      [](const auto& x, const auto& y) { return x.used < y.used; });
+          (void)hipGraphExecDestroy(lru->exec);
+          (void)hipGraphDestroy(lru->graph);
+          b->graphs.erase(lru);
+        }
         BHIP_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-        st = enqueue_launches(b, b->capture, chunks, nfr, depth, gpc);
+        st = enqueue_round(b, b->capture);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(b->capture, &g);
         if (st != VCA_OK) {
@@ -639,13 +721,19 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
           return st;
         }
         if (ec != hipSuccess) return bfail(b, VCA_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
-        b->graph = g;
-        BHIP_TRY(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-        b->graph_sig = sig;
+        hipGraphExec_t x = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          (void)hipGraphDestroy(g);
+          return bfail(b, VCA_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        b->graphs.push_back(vca_batch::CachedGraph{sig, g, x, 0});
+        hit = &b->graphs.back();
       }
-      BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+      hit->used = ++b->graph_clock;
+      BHIP_TRY(b, hipGraphLaunch(hit->exec, b->stream));
     } else {
-      if ((st = enqueue_launches(b, b->stream, chunks, nfr, depth, gpc)) != VCA_OK) return st;
+      if ((st = enqueue_round(b, b->stream)) != VCA_OK) return st;
     }
     if (ev) BHIP_TRY(b, hipEventRecord(ev[1], b->stream));
     for (int s = 0; s < b->n; s++) {
@@ -679,34 +767,49 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
     (void)hipEventDestroy(e0);
     return bfail(b, VCA_ERR_DEVICE, "hipEventCreate");
   }
-  LaunchChoice best;
-  best.ms = 1e30;
-  for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
-    int resident = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, batch_kernel_for(depth, b->only8), kThreads, 0) != hipSuccess)
-      resident = 1;
-    for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
-      // forward launch only (no reduction: features and h state are untouched)
-      st = enqueue_launches(b, b->stream, chunks, 0, depth, gpc);
-      if (st != VCA_OK) break;
-      if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
-      for (int r = 0; r < reps && st == VCA_OK; r++) st = enqueue_launches(b, b->stream, chunks, 0, depth, gpc);
-      if (st != VCA_OK) break;
-      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
-        break;
+  // each class alone: every (ring depth, workgroups per CU) pair, forward
+  // launch only (no reduction: features and h state are untouched)
+  int list[kKinds];
+  const int n = present_classes(b, list);
+  for (int j = 0; j < n && st == VCA_OK; j++) {
+    const int k = list[j];
+    LaunchChoice best;
+    best.ms = 1e30;
+    for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
+      int resident = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, class_kernel_for(k, depth), kThreads, 0) !=
+          hipSuccess)
+        resident = 1;
+      for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
+        const LaunchChoice lc{depth, gpc, 0.0};
+        auto once = [&]() {
+          hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, b->stream, b->queue);
+          return launch_class(b, b->stream, k, lc, false);
+        };
+        st = once();   // warm-up
+        if (st != VCA_OK) break;
+        if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && st == VCA_OK; r++) st = once();
+        if (st != VCA_OK) break;
+        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+          st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
+          break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best.ms) best = LaunchChoice{depth, gpc, ms};
       }
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      ms /= reps;
-      if (ms < best.ms) best = LaunchChoice{depth, gpc, ms};
+    }
+    if (st == VCA_OK) {
+      b->kind_tuned[k] = best;
+      TuneCache::get().put(class_tune_key(b, k), best);
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != VCA_OK) return st;
-  b->tuned = best;
-  TuneCache::get().put(batch_tune_key(b), best);
+  load_tuned(b);
   return VCA_OK;
 }
 
@@ -715,6 +818,17 @@ vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* g
   if (depth) *depth = b->tuned.depth;
   if (groups_per_cu) *groups_per_cu = b->tuned.groups_per_cu;
   if (ms) *ms = b->tuned.ms;
+  return VCA_OK;
+}
+
+vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
+                                 int32_t* groups_per_cu) {
+  if (!b) return VCA_ERR_INVALID_ARG;
+  for (int k = 0; k < kKinds; k++) {
+    if (ms) ms[k] = b->kind_tuned[k].depth > 0 ? b->kind_tuned[k].ms : 0.0;
+    if (depth) depth[k] = b->kind_tuned[k].depth;
+    if (groups_per_cu) groups_per_cu[k] = b->kind_tuned[k].groups_per_cu;
+  }
   return VCA_OK;
 }
 
