@@ -232,7 +232,8 @@ def small_streams(n: int = 256, frames: int = 8) -> list:
 def run_batch(vca, steps: int, warmup: int, tune: bool, descs: list, workload: str) -> dict:
     """The streams `descs` in one graph-replayed round per step (one persistent
     launch per class of streams, each followed by its reduction; per_class
-    gives each class's tuned forward time alone),
+    gives each class's tuned forward time alone, arrangement whether the
+    classes ran one after another or side by side),
     against the same streams analysed one after another by plain contexts
     (each on its own stream).  Both sides submit descriptors prepared once
     for the fixed frame buffers; the batch reads every stream's features
@@ -251,6 +252,7 @@ def run_batch(vca, steps: int, warmup: int, tune: bool, descs: list, workload: s
     b = vca.Batch(cfg, timing=True)
     launch = b.tune(frames, reps=1) if tune else b.tuned_launch()
     per_class = b.class_times()
+    arrangement = b.arrangement()
     prepared = b.prepare(frames)
     for _ in range(warmup):
         b.submit(prepared)
@@ -297,6 +299,7 @@ def run_batch(vca, steps: int, warmup: int, tune: bool, descs: list, workload: s
         "speedup_vs_plain": dt_plain / dt,
         "launch": launch,
         "per_class": per_class,
+        "arrangement": arrangement,
     }
 
 

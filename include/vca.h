@@ -338,6 +338,21 @@ vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* g
 vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
                                  int32_t* groups_per_cu);
 
+/* Arrangement of the classes in a round: *serial = 1 when the classes'
+ * forward launches run one after another (each class's reduction overlapping
+ * the next class), 0 when they run side by side on parallel branches.
+ * Serial unless vca_tune_batch (here or earlier in the process, or through
+ * VCA_TUNE_CACHE) measured side by side faster; *serial_ms and *parallel_ms
+ * are those tuned forward-round times (0 when not measured).  Each output
+ * may be NULL.  Host only. */
+vca_status vca_batch_arrangement(const vca_batch* b, int32_t* serial, double* serial_ms,
+                                 double* parallel_ms);
+
+/* Sets the arrangement of the later rounds (serial = 1: one class after
+ * another, 0: side by side) in place of the tuned one, until the next
+ * vca_tune_batch.  VCA_ERR_INVALID_ARG for another value.  Host only. */
+vca_status vca_batch_set_arrangement(vca_batch* b, int32_t serial);
+
 /* Device time of the batch's launches (both kernels), measured with HIP
  * events on its stream when any stream was opened with VCA_F_TIMING. */
 vca_status vca_batch_timing(vca_batch* b, double* total_ms, int64_t* launches, int64_t* frames,

@@ -477,6 +477,21 @@ class Batch:
             out[f"b{bits}_w{w}_k{kk}"] = {"ms": ms[k], "depth": dp[k], "groups_per_cu": gp[k]}
         return out
 
+    def arrangement(self) -> dict:
+        """How a round runs its classes: {"serial": bool, "serial_ms", "parallel_ms"}
+        (the tuned forward-round times of either arrangement, 0 if not measured)."""
+        sr, sm, pm = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+        check(_lib.lib().vca_batch_arrangement(self._b, ctypes.byref(sr), ctypes.byref(sm),
+                                               ctypes.byref(pm)), "vca_batch_arrangement",
+              batch=self._b)
+        return {"serial": bool(sr.value), "serial_ms": sm.value, "parallel_ms": pm.value}
+
+    def set_arrangement(self, serial: bool) -> None:
+        """Runs the later rounds' classes one after another (True) or side by
+        side (False), in place of the tuned choice."""
+        check(_lib.lib().vca_batch_set_arrangement(self._b, int(serial)),
+              "vca_batch_set_arrangement", batch=self._b)
+
     def timing(self, reset: bool = False) -> dict:
         ms, n, fr = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
         check(_lib.lib().vca_batch_timing(self._b, ctypes.byref(ms), ctypes.byref(n),

@@ -236,6 +236,9 @@ struct vca_batch {
   hipStream_t branch[kKinds] = {};    // one per class launched, forked from the launch stream
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kKinds] = {};
+  hipEvent_t fwd_ev[kKinds] = {};     // serial arrangement: class j's forward launch done
+  int serial = 1;                     // classes one after another (1) or side by side (0)
+  double serial_ms = 0.0, parallel_ms = 0.0;   // tuned forward rounds of either arrangement
   LaunchChoice kind_tuned[kKinds];    // per class: ring depth, workgroups per CU, ms
   LaunchChoice tuned;                 // summary: the most expensive class's shape, total ms
   // timing
@@ -367,8 +370,8 @@ LaunchChoice class_choice(const vca_batch* b, int k) {
   return c;
 }
 
-// Enqueues class k's forward launch (and, with_reduce, its reduction) on st.
-vca_status launch_class(vca_batch* b, hipStream_t st, int k, const LaunchChoice& lc, bool with_reduce) {
+// Enqueues class k's forward launch on st.
+vca_status launch_forward(vca_batch* b, hipStream_t st, int k, const LaunchChoice& lc) {
   const KindRange& kr = b->kinds[k];
   BatchKernel kern = class_kernel_for(k, lc.depth);
   int resident = 0;
@@ -389,11 +392,16 @@ vca_status launch_class(vca_batch* b, hipStream_t st, int k, const LaunchChoice&
   bp.queue = b->queue + k;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, bp);
   BHIP_TRY(b, hipGetLastError());
-  if (with_reduce && b->kind_frames[k] > 0) {
-    BatchReduceParams rp{b->d_red + kr.desc_begin, kr.desc_end - kr.desc_begin};
-    hipLaunchKernelGGL(batch_reduce_kernel, dim3(b->kind_frames[k]), dim3(kReduceThreads), 0, st, rp);
-    BHIP_TRY(b, hipGetLastError());
-  }
+  return VCA_OK;
+}
+
+// Enqueues class k's reduction (features and h state of its streams) on st.
+vca_status launch_reduce(vca_batch* b, hipStream_t st, int k) {
+  const KindRange& kr = b->kinds[k];
+  if (b->kind_frames[k] <= 0) return VCA_OK;
+  BatchReduceParams rp{b->d_red + kr.desc_begin, kr.desc_end - kr.desc_begin};
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(b->kind_frames[k]), dim3(kReduceThreads), 0, st, rp);
+  BHIP_TRY(b, hipGetLastError());
   return VCA_OK;
 }
 
@@ -405,33 +413,57 @@ int present_classes(const vca_batch* b, int* list) {
   return n;
 }
 
-// Streams and events of the fork (created before any capture).
+// Streams and events of the forks (created before any capture).
 vca_status ensure_branches(vca_batch* b, int n) {
   if (!b->fork_ev) BHIP_TRY(b, hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming));
   for (int j = 0; j < n; j++) {
     if (!b->branch[j]) BHIP_TRY(b, hipStreamCreateWithFlags(&b->branch[j], hipStreamNonBlocking));
     if (!b->join_ev[j]) BHIP_TRY(b, hipEventCreateWithFlags(&b->join_ev[j], hipEventDisableTiming));
+    if (!b->fwd_ev[j]) BHIP_TRY(b, hipEventCreateWithFlags(&b->fwd_ev[j], hipEventDisableTiming));
   }
   return VCA_OK;
 }
 
-// One round on st: the counters reset, then each class's forward launch and
-// reduction on its own branch, joined back into st.
-vca_status enqueue_round(vca_batch* b, hipStream_t st) {
+// The classes of the current round on st, after the counters are reset.
+// Parallel: each class's forward launch (and, with_reduce, its reduction) on
+// a branch of its own, all forked from st.  Serial: the forward launches one
+// after another on st, each class's reduction on a branch forked after its
+// forward launch, so that it overlaps the next class.  Either way every
+// branch joins st again.
+vca_status enqueue_classes(vca_batch* b, hipStream_t st, bool serial, bool with_reduce) {
   int list[kKinds];
   const int n = present_classes(b, list);
   hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, b->queue);
   BHIP_TRY(b, hipGetLastError());
   if (n == 0) return VCA_OK;
+  vca_status s = VCA_OK;
+  if (serial) {
+    for (int j = 0; j < n; j++) {
+      if ((s = launch_forward(b, st, list[j], class_choice(b, list[j]))) != VCA_OK) return s;
+      if (!with_reduce) continue;
+      BHIP_TRY(b, hipEventRecord(b->fwd_ev[j], st));
+      BHIP_TRY(b, hipStreamWaitEvent(b->branch[j], b->fwd_ev[j], 0));
+      if ((s = launch_reduce(b, b->branch[j], list[j])) != VCA_OK) return s;
+      BHIP_TRY(b, hipEventRecord(b->join_ev[j], b->branch[j]));
+    }
+    if (with_reduce)
+      for (int j = 0; j < n; j++) BHIP_TRY(b, hipStreamWaitEvent(st, b->join_ev[j], 0));
+    return VCA_OK;
+  }
   BHIP_TRY(b, hipEventRecord(b->fork_ev, st));
   for (int j = 0; j < n; j++) {
     BHIP_TRY(b, hipStreamWaitEvent(b->branch[j], b->fork_ev, 0));
-    vca_status s = launch_class(b, b->branch[j], list[j], class_choice(b, list[j]), true);
-    if (s != VCA_OK) return s;
+    if ((s = launch_forward(b, b->branch[j], list[j], class_choice(b, list[j]))) != VCA_OK) return s;
+    if (with_reduce && (s = launch_reduce(b, b->branch[j], list[j])) != VCA_OK) return s;
     BHIP_TRY(b, hipEventRecord(b->join_ev[j], b->branch[j]));
   }
   for (int j = 0; j < n; j++) BHIP_TRY(b, hipStreamWaitEvent(st, b->join_ev[j], 0));
   return VCA_OK;
+}
+
+// One round on st in the batch's arrangement of classes.
+vca_status enqueue_round(vca_batch* b, hipStream_t st) {
+  return enqueue_classes(b, st, b->serial != 0, true);
 }
 
 // Copies the staging descriptors to the device on the batch's stream.
@@ -484,6 +516,14 @@ void load_tuned(vca_batch* b) {
     }
   }
   if (worst >= 0.0) b->tuned.ms = total;
+  // the arrangement of the classes: serial unless side by side measured faster
+  LaunchChoice par, ser;
+  if (TuneCache::get().find(batch_tune_key(b) + "/parallel", &par) &&
+      TuneCache::get().find(batch_tune_key(b) + "/serial", &ser)) {
+    b->parallel_ms = par.ms;
+    b->serial_ms = ser.ms;
+    b->serial = ser.ms <= par.ms ? 1 : 0;
+  }
 }
 
 // Validation marks of frames [first, first + count) of a stream (whose round
@@ -531,6 +571,7 @@ void vca_close_batch(vca_batch* b) {
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     for (int k = 0; k < kKinds; k++) {
       if (b->join_ev[k]) (void)hipEventDestroy(b->join_ev[k]);
+      if (b->fwd_ev[k]) (void)hipEventDestroy(b->fwd_ev[k]);
       if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
     }
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
@@ -699,6 +740,7 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
         sig.push_back(lc.depth);
         sig.push_back(lc.groups_per_cu);
       }
+      sig.push_back(b->serial);
       vca_batch::CachedGraph* hit = nullptr;
       for (auto& c : b->graphs)
         if (c.sig == sig) hit = &c;
@@ -784,7 +826,7 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
         const LaunchChoice lc{depth, gpc, 0.0};
         auto once = [&]() {
           hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, b->stream, b->queue);
-          return launch_class(b, b->stream, k, lc, false);
+          return launch_forward(b, b->stream, k, lc);
         };
         st = once();   // warm-up
         if (st != VCA_OK) break;
@@ -805,6 +847,28 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
       b->kind_tuned[k] = best;
       TuneCache::get().put(class_tune_key(b, k), best);
     }
+  }
+  // then the arrangement of the tuned classes: forward launches only, one
+  // after another or side by side
+  double arr_ms[2] = {0.0, 0.0};
+  if (st == VCA_OK && n > 1) st = ensure_branches(b, n);
+  for (int serial = 0; serial < 2 && st == VCA_OK && n > 1; serial++) {
+    st = enqueue_classes(b, b->stream, serial != 0, false);   // warm-up
+    if (st != VCA_OK) break;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
+    for (int r = 0; r < reps && st == VCA_OK; r++) st = enqueue_classes(b, b->stream, serial != 0, false);
+    if (st != VCA_OK) break;
+    if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    arr_ms[serial] = ms / reps;
+  }
+  if (st == VCA_OK && n > 1) {
+    TuneCache::get().put(batch_tune_key(b) + "/parallel", LaunchChoice{1, 0, arr_ms[0]});
+    TuneCache::get().put(batch_tune_key(b) + "/serial", LaunchChoice{1, 0, arr_ms[1]});
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -829,6 +893,21 @@ vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
     if (depth) depth[k] = b->kind_tuned[k].depth;
     if (groups_per_cu) groups_per_cu[k] = b->kind_tuned[k].groups_per_cu;
   }
+  return VCA_OK;
+}
+
+vca_status vca_batch_arrangement(const vca_batch* b, int32_t* serial, double* serial_ms,
+                                double* parallel_ms) {
+  if (!b) return VCA_ERR_INVALID_ARG;
+  if (serial) *serial = b->serial;
+  if (serial_ms) *serial_ms = b->serial_ms;
+  if (parallel_ms) *parallel_ms = b->parallel_ms;
+  return VCA_OK;
+}
+
+vca_status vca_batch_set_arrangement(vca_batch* b, int32_t serial) {
+  if (!b || (serial != 0 && serial != 1)) return bfail(b, VCA_ERR_INVALID_ARG, "serial must be 0 or 1");
+  b->serial = serial;
   return VCA_OK;
 }
 

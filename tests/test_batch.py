@@ -60,10 +60,15 @@ def plain_features(vca, d, planes, calls):
     return f
 
 
-def test_batch_graph_replays_match_plain(vca, frames):
-    print_case(test="batch_vs_plain", streams=len(STREAMS))
+@pytest.mark.parametrize("serial", [True, False], ids=["serial", "side_by_side"])
+def test_batch_graph_replays_match_plain(vca, frames, serial):
+    """Both arrangements of the classes in a round (one after another, side
+    by side on parallel graph branches) give the plain path's features."""
+    print_case(test="batch_vs_plain", streams=len(STREAMS), serial=serial)
     calls = 3
     b = vca.Batch(STREAMS)
+    b.set_arrangement(serial)
+    assert b.arrangement()["serial"] == serial
     for c in range(calls):
         b.submit(list(frames))
         # eager work and a synchronisation between graph replays
@@ -176,16 +181,33 @@ def test_batch_tune_and_no_graph_path(vca, frames, monkeypatch):
     b = vca.Batch(STREAMS[:6])
     choice = b.tune(sub, reps=1)
     assert choice["depth"] in (1, 2, 4) and choice["groups_per_cu"] >= 1 and choice["ms"] > 0
+    arr = b.arrangement()
+    assert arr["serial_ms"] > 0 and arr["parallel_ms"] > 0
+    assert arr["serial"] == (arr["serial_ms"] <= arr["parallel_ms"])
+    times = b.class_times()
+    assert set(times) == {"b8_w8_k8", "b8_w32_k16", "b8_w16_k16", "b8_w32_k32", "b8_w8_k4"}
+    assert all(t["ms"] > 0 and t["depth"] in (1, 2, 4) and t["groups_per_cu"] >= 1 for t in times.values())
     b.submit(sub)
     tuned = [b.features(s, 0, d["n"]) for s, d in enumerate(STREAMS[:6])]
     b.close()
     monkeypatch.setenv("VCA_BATCH_NO_GRAPH", "1")
-    b2 = vca.Batch(STREAMS[:6])
-    b2.submit(sub)
-    eager = [b2.features(s, 0, d["n"]) for s, d in enumerate(STREAMS[:6])]
-    b2.close()
-    for s in range(6):
-        assert tuned[s].tobytes() == eager[s].tobytes()
+    for serial in (True, False):
+        b2 = vca.Batch(STREAMS[:6])
+        b2.set_arrangement(serial)
+        b2.submit(sub)
+        b2.submit(sub)
+        eager = [b2.features(s, 0, 2 * d["n"]) for s, d in enumerate(STREAMS[:6])]
+        b2.close()
+        for s, d in enumerate(STREAMS[:6]):
+            assert tuned[s].tobytes() == eager[s][:d["n"]].tobytes(), (serial, s)
+            ref = plain_features(vca, d, frames[s], 2)
+            assert eager[s].tobytes() == ref.tobytes(), (serial, s)
+    with pytest.raises(vca.VcaError):
+        b3 = vca.Batch(STREAMS[:1])
+        try:
+            b3.set_arrangement(2)
+        finally:
+            b3.close()
 
 
 def test_plain_tune(vca, frames):
