@@ -233,6 +233,7 @@ struct vca_batch {
   bool use_graph = true;
   KindRange kinds[kKinds] = {};    // flat-list ranges of the current round
   int32_t kind_frames[kKinds] = {};   // frames of each class in the current round
+  int64_t kind_blocks[kKinds] = {};   // blocks of each class in the current round
   hipStream_t branch[kKinds] = {};    // one per class launched, forked from the launch stream
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kKinds] = {};
@@ -329,6 +330,7 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
   // class's reduction launch numbers its workgroups from 0
   for (int k = 0; k < kKinds; k++) {
     int32_t kframes = 0;
+    int64_t kblocks = 0;
     for (int i2 = b->kinds[k].desc_begin; i2 < b->kinds[k].desc_end; i2++) {
       const int s = b->h_streams[i2].stream;
       const Geometry& g = b->geos[s];
@@ -354,9 +356,11 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
       rp.n_frames = cnt[s];
       rp.frame_begin = kframes;
       kframes += cnt[s];
+      kblocks += (int64_t)cnt[s] * g.per_frame;
       frames += cnt[s];
     }
     b->kind_frames[k] = kframes;
+    b->kind_blocks[k] = kblocks;
   }
   *total_chunks = chunks;
   *total_frames = frames;
@@ -427,9 +431,9 @@ vca_status ensure_branches(vca_batch* b, int n) {
 // The classes of the current round on st, after the counters are reset.
 // Parallel: each class's forward launch (and, with_reduce, its reduction) on
 // a branch of its own, all forked from st.  Serial: the forward launches one
-// after another on st, each class's reduction on a branch forked after its
-// forward launch, so that it overlaps the next class.  Either way every
-// branch joins st again.
+// after another on st (the class with the most blocks first), each class's
+// reduction on a branch forked after its forward launch, so that it overlaps
+// the next class.  Either way every branch joins st again.
 vca_status enqueue_classes(vca_batch* b, hipStream_t st, bool serial, bool with_reduce) {
   int list[kKinds];
   const int n = present_classes(b, list);
@@ -438,6 +442,10 @@ vca_status enqueue_classes(vca_batch* b, hipStream_t st, bool serial, bool with_
   if (n == 0) return VCA_OK;
   vca_status s = VCA_OK;
   if (serial) {
+    // most blocks first: the last class's reduction is the one left
+    // exposed, and a reduction's cost follows the blocks it sums
+    std::stable_sort(list, list + n,
+                     [b](int x, int y) { return b->kind_blocks[x] > b->kind_blocks[y]; });
     for (int j = 0; j < n; j++) {
       if ((s = launch_forward(b, st, list[j], class_choice(b, list[j]))) != VCA_OK) return s;
       if (!with_reduce) continue;

@@ -308,18 +308,85 @@ __device__ inline TileData strip_load(const StripWork& s, const LaneOffsets& o, 
 // strips).  Every unit issues the same loads whatever the strip length (tile
 // indices are clamped into the strip, and the last strip prefetches itself
 // again), so the compiler waits for exactly the oldest unit's loads; the
-// missing tiles of a short strip are transformed but never stored.  w = 16
-// and 8 reduce each unit over the lanes of its blocks and write them to a
-// per-wavefront LDS staging area laid out as the segment of the tile row
-// being walked (block row x block column, up to kSegCols columns); the
-// segment is copied out with row-contiguous stores when the next strip
-// leaves the tile row, would overflow it, or the run ends.
+// missing tiles of a short strip are transformed but never stored.
+//
+// w = 16 and 8: a tile holds several blocks, each spread over 2 K lanes
+// with one FP64 share per block row.  Each unit's shares (and the lanes'
+// row-0 coefficients, the DC candidates) go to a per-wavefront LDS area,
+// lane-major, with no arithmetic; every LdsGroup units the lanes read them
+// back block by block (RedMap below), sum a block's shares in 8-term chunks
+// and combine a block's chunks across adjacent lanes, and one lane per block
+// writes its H and DC into the segment of the tile row being walked (block
+// row x block column, up to seg_cols(w) columns) -- copied out with
+// row-contiguous stores when the next strip leaves the tile row, would
+// overflow it, or the run ends.
 constexpr int kRun = 8;   // strips per run (w = 32: at most 64 blocks, one per lane)
-constexpr int kSegCols = 128;   // block columns of a staged segment (w = 16, 8)
+
+// Block columns of a staged segment (w = 16, 8): 3 KiB of H and DC.
+constexpr int seg_cols(int w) { return w == 16 ? 128 : 64; }
 
 // LDS bytes of one wavefront's staging area: w = 32, the DC of the run's 64
-// blocks; else the segment's FP64 H, then int32 DC.
-constexpr int stage_bytes(int w) { return w == 32 ? 64 * 4 : (kTile / w) * kSegCols * 12; }
+// blocks; else the shares of one group (4 KiB), the DC candidates of one
+// group (2 KiB), then the segment's FP64 H and int32 DC.
+constexpr int kLdsShareBytes = 8 * 64 * 8;   // LdsGroup units x block rows = 8 share rows
+constexpr int kLdsDcBytes = 8 * 64 * 4;
+constexpr int stage_bytes(int w) {
+  return w == 32 ? 64 * 4 : kLdsShareBytes + kLdsDcBytes + (kTile / w) * seg_cols(w) * 12;
+}
+
+// The LDS reduction of w = 16, 8 units: per group of kGroup units, share
+// row (ul, b) holds the 64 lanes' shares of block row b of unit ul.  Block
+// beta = ((ul * kBpt + b) * kBpt + bc) * kPack + q of the group owns the
+// lanes g * 32 + bc * w + q * K + k (g = 0, 1; k < K) of its share row.  The
+// 64 reader lanes take kPer terms each: with 2 K >= kPer, kLanes = 2 K / kPer
+// adjacent lanes share a block (chunk = lane % kLanes); otherwise a lane
+// sums kBlocks = kPer / (2 K) consecutive blocks (consecutive q).
+template <int kW, int kK>
+struct RedMap {
+  static constexpr int kBpt = kTile / kW;
+  static constexpr int kPack = kW / kK;
+  static constexpr int kUnits = kStrip / kPack;
+  static constexpr int kGroup = (8 / kBpt) < kUnits ? (8 / kBpt) : kUnits;
+  static constexpr int kPer = kGroup * kBpt;                 // terms per reader lane
+  static constexpr int kLanes = 2 * kK >= kPer ? 2 * kK / kPer : 1;
+  static constexpr int kBlocks = 2 * kK >= kPer ? 1 : kPer / (2 * kK);
+  static constexpr int kNb = kGroup * kPack * kBpt * kBpt;   // blocks per group
+  static_assert(kNb == 64 / kLanes * kBlocks, "every block read exactly once");
+  static_assert(kPer % 2 == 0 && kK % 2 == 0, "terms read in aligned pairs");
+
+  // Byte offset of the reader's term pair p (terms 2p, 2p + 1 of its
+  // chunk, or of its blocks) from the reader's first term.
+  static constexpr int pair_offset(int p) {
+    if (kBlocks > 1) {                       // p: block p / (K), g and k within it
+      const int per_block = kK;              // pairs per block: 2 K terms
+      const int blk = p / per_block, r = p % per_block;
+      return blk * kK * 8 + (r / (kK / 2)) * 32 * 8 + (r % (kK / 2)) * 16;
+    }
+    if (kK >= kPer) return p * 16;           // the chunk lies in one g half
+    return (2 * p / kK) * 32 * 8 + (2 * p % kK) * 8;   // chunk = whole block, both halves
+  }
+  // The reader lane's first block and chunk, its share-row offset and the
+  // block's (ul, b, bc, q).
+  int beta, chunk, ul, b, bc, q;
+  __device__ explicit RedMap(int lane) {
+    beta = kBlocks > 1 ? lane * kBlocks : lane / kLanes;
+    chunk = kBlocks > 1 ? 0 : lane % kLanes;
+    q = beta % kPack;
+    bc = (beta / kPack) % kBpt;
+    b = (beta / (kPack * kBpt)) % kBpt;
+    ul = beta / (kPack * kBpt * kBpt);
+  }
+  // byte offset of the reader's first term in the share area
+  __device__ int first_term() const {
+    const int t0 = chunk * kPer;             // term index within the block
+    const int g = t0 / kK, k = t0 % kK;
+    return ((ul * kBpt + b) * 64 + g * 32 + bc * kW + q * kK + k) * 8;
+  }
+  // byte offset of the block's DC candidate (lane g = 0, k = 0) in the DC area
+  __device__ int dc_slot(int extra) const {
+    return ((ul * kBpt + b) * 64 + bc * kW + (q + extra) * kK) * 4;
+  }
+};
 
 // Coefficient export (VCA_F_KEEP_COEFFS, tests): the K x K coefficients of
 // the blocks of unit u of strip S, DC corrected, at ((block * K + i) * K + k)
@@ -363,7 +430,7 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     TileData t[kPack];
   };
   const int c = lane & 31, g = lane >> 5;
-  const int cc = c % kW, q = cc / kK, bc = c / kW;   // lane's tile in its unit, block column
+  const int cc = c % kW, q = cc / kK;   // lane's column and tile within its unit
 
   auto load_unit = [&](const StripWork& S, const LaneOffsets& O, int u) {
     Unit d;
@@ -389,9 +456,26 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
   double hrun = 0.0;
   int run_out0 = S.out0;
   uint32_t seen = 0;   // kValidate: OR of every sample of the current strip
-  double* st_h = reinterpret_cast<double*>(stage);            // [kBpt][kSegCols]
-  int* st_dc = reinterpret_cast<int*>(st_h + kBpt * kSegCols);  // [kBpt][kSegCols]
+  constexpr int kSeg = seg_cols(kW);
   int* st_run_dc = reinterpret_cast<int*>(stage);              // w = 32: [64] DC of the run
+  // w < 32: the group's shares and DC candidates, then the segment
+  double* st_share = reinterpret_cast<double*>(stage);         // [share row][64 lanes]
+  int* st_dcc = reinterpret_cast<int*>(stage + kLdsShareBytes);  // [share row][64 lanes]
+  double* st_h = reinterpret_cast<double*>(stage + kLdsShareBytes + kLdsDcBytes);  // [kBpt][kSeg]
+  int* st_dc = reinterpret_cast<int*>(st_h + kBpt * kSeg);     // [kBpt][kSeg]
+  using RM = RedMap<kW, kK>;
+  // w < 32, per reader lane: its first share and DC candidate (bytes), its
+  // first block's tile within the group (past every tile for lanes that
+  // read a later chunk: they never write), block column and segment row
+  int red_first = 0, red_dc = 0, red_t = 0, red_bc = 0, red_row = 0;
+  if constexpr (kW != 32) {
+    const RM rm(lane);
+    red_first = rm.first_term();
+    red_dc = rm.dc_slot(0);
+    red_t = rm.chunk == 0 ? rm.ul * kPack + rm.q : 1 << 20;
+    red_bc = rm.bc;
+    red_row = rm.b * kSeg;
+  }
 
   while (true) {
     const int id2 = next_id(id);
@@ -414,19 +498,41 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
         hs[u] = h[0];
         dcs[u] = dc[0];
       } else {
-        // every row's shares summed over the block's lanes; lane keeps one row
-        const double hr = rows_reduce<kW, kK>(h, lane);
-        const int r = rows_lane_row<kW, kK>(lane);
-        const int t = u * kPack + q;   // this lane's tile within the strip
-        const int vc = t == S.n - 1 ? S.vc_last : kBpt;
-        const bool mine = t < S.n && bc < vc;
-        // one writer per (block, tile): the group's lanes holding a row
-        constexpr int kFree = kBpt == 2 ? kK - 1 : kK / 2 - 1;   // in-group bits summed over
-        const int col = S.out0 - run_out0 + t * kBpt + bc;        // column in the segment
-        if ((cc & kFree) == 0 && mine) st_h[r * kSegCols + col] = hr;
-        if (g == 0 && cc % kK == 0 && mine) {
+        // the unit's shares and DC candidates into the group's share rows
+        const int ul = u % RM::kGroup;
 #pragma unroll
-          for (int b = 0; b < kBpt; b++) st_dc[b * kSegCols + col] = dc[b] + kDcAdd;
+        for (int b = 0; b < kBpt; b++) {
+          st_share[(ul * kBpt + b) * 64 + lane] = h[b];
+          st_dcc[(ul * kBpt + b) * 64 + lane] = dc[b];
+        }
+        if (ul == RM::kGroup - 1) {
+          // the group's blocks: sum each reader's terms, then its chunks
+          const uint8_t* sh = reinterpret_cast<const uint8_t*>(st_share) + red_first;
+          constexpr int kPairs = RM::kPer / 2 / RM::kBlocks;   // pairs per block
+          double sum[RM::kBlocks];
+#pragma unroll
+          for (int k = 0; k < RM::kBlocks; k++) {
+#pragma unroll
+            for (int p = 0; p < kPairs; p++) {
+              const double2 v =
+                  *reinterpret_cast<const double2*>(sh + RM::pair_offset(k * kPairs + p));
+              sum[k] = p == 0 ? v.x + v.y : sum[k] + (v.x + v.y);
+            }
+            if constexpr (RM::kLanes >= 2) sum[k] += dpp64<kDppXor1>(sum[k]);
+            if constexpr (RM::kLanes >= 4) sum[k] += dpp64<kDppXor2>(sum[k]);
+          }
+          // one writer per block: its H and DC into the segment
+          const int t0 = (u / RM::kGroup) * RM::kGroup * kPack + red_t;
+#pragma unroll
+          for (int k = 0; k < RM::kBlocks; k++) {
+            const int t = t0 + k;   // the block's tile within the strip
+            const int vc = t == S.n - 1 ? S.vc_last : kBpt;
+            if (t < S.n && red_bc < vc) {
+              const int col = S.out0 - run_out0 + t * kBpt + red_bc;
+              st_h[red_row + col] = sum[k];
+              st_dc[red_row + col] = st_dcc[(red_dc >> 2) + k * kK] + kDcAdd;
+            }
+          }
         }
       }
     };
@@ -475,15 +581,15 @@ __device__ __forceinline__ void run_strips(const StripGeom& G, const TileOut& ou
     if constexpr (kW != 32) {
       // copy the segment out when the next strip leaves it
       const bool leave = !more || id2 % kRunLen == 0 || S2.row0 != S.row0 ||
-                         S2.out0 - run_out0 + kStrip * kBpt > kSegCols;
+                         S2.out0 - run_out0 + kStrip * kBpt > kSeg;
       if (leave) {
         const int cols = S.out0 - run_out0 + (S.n - 1) * kBpt + S.vc_last;
         for (int b = 0; b < S.vr; b++) {
           for (int cb = 0; cb < cols; cb += 64) {
             const int col = cb + lane;
             if (col < cols) {
-              out.blk_h[run_out0 + b * S.out_row + col] = st_h[b * kSegCols + col];
-              out.blk_dc[run_out0 + b * S.out_row + col] = st_dc[b * kSegCols + col];
+              out.blk_h[run_out0 + b * S.out_row + col] = st_h[b * kSeg + col];
+              out.blk_dc[run_out0 + b * S.out_row + col] = st_dc[b * kSeg + col];
             }
           }
         }
