@@ -475,7 +475,7 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
 
 
 KERNEL_SOURCES = ("vca.hip", "vca_strip.h", "vca_tile.h", "vca_host.h", "vca_reduce.h")
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_fwd32_2160p.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_forward_kernels.md")
 
 
 def kernel_sources_sha() -> str:
@@ -507,13 +507,31 @@ def measured_traffic():
         return None
     if data.get("kernel_sources_sha256") != kernel_sources_sha():
         return None
-    return {mode: data[mode]["hbm_bytes_per_launch"] for mode in ("full", "lowpass") if mode in data}
+    return {mode: v["hbm_bytes_per_launch"] for mode, v in data.items() if isinstance(v, dict)}
+
+
+def attach_traffic(line: dict, traffic) -> None:
+    """Sets roofline.traffic of each record the traffic summary covers (the
+    head line is the full-DCT record unless only K = 16 ran)."""
+    if not traffic:
+        return
+    head = "full" if line.get("config", {}).get("lowpass_k", 0) == 0 else "lowpass"
+    spots = [(head, line), ("lowpass", line.get("lowpass_k16")),
+             ("downsample", line.get("lowpass_downsample"))]
+    for k in ("w16", "w8"):
+        spots.append((k, (line.get("block_sizes_8bit") or {}).get(k)))
+    for k in ("3840x2160_w32", "3840x2160_w16"):
+        spots.append(("tenbit_" + k, (line.get("tenbit_stress") or {}).get(k)))
+    for mode, entry in spots:
+        if isinstance(entry, dict) and "roofline" in entry and mode in traffic:
+            entry["roofline"]["traffic"] = traffic[mode]
 
 
 def calibration_copy(mib: int) -> dict:
-    """One plain device copy of `mib` MiB whose source was written before a
-    1 GiB flush buffer, so that it is read from HBM: the reference that scales
-    FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    """One plain device kernel that reads `mib` MiB and writes as many
+    (bitwise NOT of uint8, a kernel of its own name in a counter run), its
+    source written before a 1 GiB flush buffer so that it is read from HBM:
+    the reference that scales FETCH_SIZE / WRITE_SIZE readings to bytes."""
     import torch
     n = mib << 20
     src = torch.empty(n, dtype=torch.uint8, device="cuda").fill_(7)
@@ -522,17 +540,18 @@ def calibration_copy(mib: int) -> dict:
     torch.cuda.synchronize()
     del flush
     t0 = time.perf_counter()
-    dst.copy_(src)
+    torch.bitwise_not(src, out=dst)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"bytes": n, "ms": dt * 1e3}
+    return {"bytes": n, "ms": dt * 1e3, "kernel": "bitwise_not (uint8)"}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10,
+                    help="untimed launches per mode first: the launch time settles over about ten")
     ap.add_argument("--cpu-frames", type=int, default=60,
                     help="2160p frames of the oracle's bounded CPU sample (0 skips it)")
     ap.add_argument("--modes",
@@ -682,11 +701,6 @@ def main() -> int:
                                "ms_per_step": lp["ms_per_step"], "roofline": lp["roofline"],
                                "mfma": lp["mfma"], "forward_kernel_ms": lp["forward_kernel_ms"],
                                "launch": lp["launch"]}
-    traffic = measured_traffic()
-    if traffic is not None:
-        for mode, entry in (("full", line), ("lowpass", line.get("lowpass_k16"))):
-            if entry is not None and mode in traffic and mode in results:
-                entry["roofline"]["traffic"] = traffic[mode]
     if copy is not None:
         line["calibration_copy"] = copy
     if sizes:
@@ -714,6 +728,7 @@ def main() -> int:
         line["batched_small_streams"] = batch_small
     if backward is not None:
         line["backward"] = backward
+    attach_traffic(line, measured_traffic())
     print(json.dumps(line), flush=True)
     return 0
 

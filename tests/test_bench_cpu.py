@@ -61,3 +61,27 @@ def test_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_traffic_summary_parses_and_attaches():
+    """The committed traffic summary parses (it is ignored once the kernel
+    sources no longer hash to its recorded value), and each covered record
+    of a bench line gets its own per-launch bytes."""
+    t = bench.measured_traffic()
+    assert t is None or {"full", "lowpass", "w16", "w8"} <= set(t)
+    line = {"config": {"lowpass_k": 0}, "roofline": {},
+            "lowpass_k16": {"roofline": {}}, "lowpass_downsample": {"roofline": {}},
+            "block_sizes_8bit": {"w16": {"roofline": {}}, "w8": {"roofline": {}}, "workload": "x"},
+            "tenbit_stress": {"3840x2160_w32": {"roofline": {}}, "workload": "y"}}
+    bench.attach_traffic(line, {"full": 1, "lowpass": 2, "downsample": 3, "w16": 4, "w8": 5,
+                                "tenbit_3840x2160_w32": 6})
+    assert line["roofline"]["traffic"] == 1
+    assert line["lowpass_k16"]["roofline"]["traffic"] == 2
+    assert line["lowpass_downsample"]["roofline"]["traffic"] == 3
+    assert line["block_sizes_8bit"]["w16"]["roofline"]["traffic"] == 4
+    assert line["block_sizes_8bit"]["w8"]["roofline"]["traffic"] == 5
+    assert line["tenbit_stress"]["3840x2160_w32"]["roofline"]["traffic"] == 6
+    only_k16 = {"config": {"lowpass_k": 16}, "roofline": {}}
+    bench.attach_traffic(only_k16, {"full": 1, "lowpass": 2})
+    assert only_k16["roofline"]["traffic"] == 2
+    bench.attach_traffic(only_k16, None)
