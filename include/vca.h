@@ -319,9 +319,13 @@ vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32
 
 /* Autotuner of the batched launch shapes: over the first round of the given
  * frames of every stream, times each class's forward launch alone for every
- * ring depth (1, 2, 4) and every count of workgroups per compute unit that
- * fits, and keeps the fastest per class; cached under the batch's stream
- * list.  Features and h state are unchanged. */
+ * ring depth (1, 2, 4), wavefronts per workgroup (4, 8) and count of
+ * workgroups per compute unit that fits, then every chunk size (8, 16, 32,
+ * 64 strips) at the fastest of those, and keeps the fastest per class; then
+ * times the tuned classes one after another and side by side and keeps the
+ * faster arrangement (vca_batch_arrangement).  Cached under the batch's
+ * stream list for the process (and in the file named by VCA_TUNE_CACHE).
+ * Features and h state are unchanged. */
 vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames,
                           int32_t reps);
 
@@ -331,12 +335,14 @@ vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* g
                                   double* ms);
 
 /* Per class of streams, the tuned forward launch: ms[k] its device time alone
- * (0 for a class not tuned), depth[k] and groups_per_cu[k] its shape (0 when
- * untuned).  Each output may be NULL, else an array of 18 entries indexed by
- * class k = (B == 10 ? 9 : 0) + 3 * (w == 32 ? 0 : w == 16 ? 1 : 2) +
- * (K == w ? 0 : K == w / 2 ? 1 : 2).  Host only. */
+ * (0 for a class not tuned), depth[k] its ring depth, groups_per_cu[k] its
+ * workgroups per compute unit, waves[k] its wavefronts per workgroup (4 or
+ * 8) and chunk_strips[k] the strips a wavefront draws at a time (8 to 64),
+ * all 0 when untuned.  Each output may be NULL, else an array of 18 entries
+ * indexed by class k = (B == 10 ? 9 : 0) + 3 * (w == 32 ? 0 : w == 16 ? 1 :
+ * 2) + (K == w ? 0 : K == w / 2 ? 1 : 2).  Host only. */
 vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
-                                 int32_t* groups_per_cu);
+                                 int32_t* groups_per_cu, int32_t* waves, int32_t* chunk_strips);
 
 /* Arrangement of the classes in a round: *serial = 1 when the classes'
  * forward launches run one after another (each class's reduction overlapping
@@ -347,6 +353,15 @@ vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
  * may be NULL.  Host only. */
 vca_status vca_batch_arrangement(const vca_batch* b, int32_t* serial, double* serial_ms,
                                  double* parallel_ms);
+
+/* Sets class cls's launch shape for the later rounds in place of the tuned
+ * one (until the next vca_tune_batch): ring depth 1, 2 or 4, workgroups per
+ * compute unit (0: as many as fit), wavefronts per workgroup 4 or 8, and
+ * strips per chunk 8, 16, 32 or 64; cls numbered as in
+ * vca_batch_class_times.  VCA_ERR_INVALID_ARG for any other value; its
+ * ms in vca_batch_class_times reads 0.  Host only. */
+vca_status vca_batch_set_class_shape(vca_batch* b, int32_t cls, int32_t depth, int32_t groups_per_cu,
+                                     int32_t waves, int32_t chunk_strips);
 
 /* Sets the arrangement of the later rounds (serial = 1: one class after
  * another, 0: side by side) in place of the tuned one, until the next

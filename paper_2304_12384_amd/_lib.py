@@ -31,7 +31,7 @@ EXPORTS = (
     "vca_frames_submitted", "vca_close", "vca_status_str", "vca_last_error",
     "vca_open_batch", "vca_analyze_batch", "vca_batch_features", "vca_batch_features_many",
     "vca_tune_batch",
-    "vca_batch_tuned_launch", "vca_batch_class_times", "vca_batch_arrangement", "vca_batch_set_arrangement", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
+    "vca_batch_tuned_launch", "vca_batch_class_times", "vca_batch_arrangement", "vca_batch_set_arrangement", "vca_batch_set_class_shape", "vca_batch_timing", "vca_reset_batch", "vca_batch_submitted",
     "vca_batch_last_error", "vca_close_batch",
     "vca_grad_workspace", "vca_energy_forward", "vca_energy_backward",
     "vca_analyze_noalloc",
@@ -115,9 +115,10 @@ def lib() -> ctypes.CDLL:
             "vca_batch_features_many": (St, [P, ctypes.c_int32, P, P, P, P]),
             "vca_tune_batch": (St, [P, ctypes.POINTER(VcaFrames), P, ctypes.c_int32]),
             "vca_batch_tuned_launch": (St, [P, P, P, P]),
-            "vca_batch_class_times": (St, [P, P, P, P]),
+            "vca_batch_class_times": (St, [P, P, P, P, P, P]),
             "vca_batch_arrangement": (St, [P, P, P, P]),
             "vca_batch_set_arrangement": (St, [P, ctypes.c_int32]),
+            "vca_batch_set_class_shape": (St, [P] + [ctypes.c_int32] * 5),
             "vca_batch_timing": (St, [P, P, P, P, ctypes.c_int32]),
             "vca_reset_batch": (St, [P, ctypes.c_int32]),
             "vca_batch_submitted": (ctypes.c_int64, [P, ctypes.c_int32]),

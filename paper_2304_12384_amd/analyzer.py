@@ -461,11 +461,11 @@ class Batch:
 
     def class_times(self) -> dict:
         """Tuned forward launch of each class present: {"b8_w32_k32": {"ms", "depth",
-        "groups_per_cu"}, ...} (device time of the class's launch alone)."""
+        "groups_per_cu", "waves", "chunk_strips"}, ...} (device time of the class's
+        launch alone)."""
         ms = (ctypes.c_double * 18)()
-        dp = (ctypes.c_int32 * 18)()
-        gp = (ctypes.c_int32 * 18)()
-        check(_lib.lib().vca_batch_class_times(self._b, ms, dp, gp), "vca_batch_class_times",
+        dp, gp, wv, ch = [(ctypes.c_int32 * 18)() for _ in range(4)]
+        check(_lib.lib().vca_batch_class_times(self._b, ms, dp, gp, wv, ch), "vca_batch_class_times",
               batch=self._b)
         out = {}
         for k in range(18):
@@ -474,7 +474,8 @@ class Batch:
             bits = 10 if k >= 9 else 8
             w = (32, 16, 8)[(k // 3) % 3]
             kk = w // (1, 2, 4)[k % 3]
-            out[f"b{bits}_w{w}_k{kk}"] = {"ms": ms[k], "depth": dp[k], "groups_per_cu": gp[k]}
+            out[f"b{bits}_w{w}_k{kk}"] = {"ms": ms[k], "depth": dp[k], "groups_per_cu": gp[k],
+                                         "waves": wv[k], "chunk_strips": ch[k]}
         return out
 
     def arrangement(self) -> dict:
@@ -485,6 +486,16 @@ class Batch:
                                                ctypes.byref(pm)), "vca_batch_arrangement",
               batch=self._b)
         return {"serial": bool(sr.value), "serial_ms": sm.value, "parallel_ms": pm.value}
+
+    def set_class_shape(self, cls: str, depth: int, groups_per_cu: int, waves: int,
+                        chunk_strips: int) -> None:
+        """Pins class `cls` ("b8_w16_k16", as class_times names them) to a launch
+        shape in place of the tuned one."""
+        bits, w, kk = (int(x[1:]) for x in cls.split("_"))
+        k = (9 if bits == 10 else 0) + 3 * {32: 0, 16: 1, 8: 2}[w] + {w: 0, w // 2: 1, w // 4: 2}[kk]
+        check(_lib.lib().vca_batch_set_class_shape(self._b, k, depth, groups_per_cu, waves,
+                                                   chunk_strips), "vca_batch_set_class_shape",
+              batch=self._b)
 
     def set_arrangement(self, serial: bool) -> None:
         """Runs the later rounds' classes one after another (True) or side by

@@ -3,19 +3,18 @@
 // Many independent video streams of different resolution, block size, bit
 // depth and frame count are analysed in one round of launches: the streams
 // are grouped by class (bit depth, w, K), and each class present gets ONE
-// persistent launch of a kernel specialised for it (its own register budget,
-// ring depth and workgroups per CU, chosen by vca_tune_batch).  Its
-// wavefronts take chunks of the class's flat list (runs of kChunkStrips
-// consecutive strips of one stream, vca_strip.h; a stream's chunks are
-// contiguous) from the class's device counter, so that waves that drew cheap
-// chunks take more and all finish together, and run the plain path's strip
-// loop.  Right after a class's forward launch, a reduction launch turns each
-// of the class's (stream, frame) pairs into its seven features
-// (vca_reduce.h).  Classes run on parallel branches (forked streams), so one
-// class's reduction and tail overlap another's forward work.  A round's
-// launches (counter reset, then the branches) are captured once into a
-// hipGraph per frame-count signature and replayed; per call only the
-// descriptor tables (frame pointers, state buffers) are uploaded.
+// persistent launch of a kernel specialised for it (its own register budget;
+// ring depth, wavefronts per workgroup, workgroups per CU and strips per
+// chunk chosen by vca_tune_batch).  Its wavefronts take chunks of the class's
+// flat list (runs of consecutive strips of one stream, vca_strip.h; a
+// stream's chunks are contiguous) from the class's device counter, so that
+// waves that drew cheap chunks take more and all finish together, and run
+// the plain path's strip loop.  After a class's forward launch, a reduction
+// launch turns each of the class's (stream, frame) pairs into its seven
+// features (vca_reduce.h).  The classes run one after another or side by
+// side on forked streams (the tuned arrangement).  A round's launches are
+// captured once into a hipGraph per signature and replayed; per call only
+// the descriptor tables (frame pointers, state buffers) are uploaded.
 
 #include <hip/hip_runtime.h>
 
@@ -37,8 +36,7 @@ using namespace vca;
 
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
+constexpr int kDefaultWaves = 4;   // wavefronts per workgroup of a class launch (or 8)
 constexpr int kKinds = 18;          // bit depth {8, 10} x w {32, 16, 8} x K {w, w/2, w/4}
 constexpr int32_t kDefaultMaxBatch = 300;    // frames per stream and round (max_batch = 0)
 constexpr int32_t kDefaultCapacity = 4096;   // feature ring per stream (feature_capacity = 0)
@@ -61,9 +59,11 @@ struct StreamDesc {
 
 using ConstDesc = __attribute__((address_space(4))) const StreamDesc;
 
-// Consecutive strips of one stream handed to a wavefront at a time.
-constexpr int kChunkStrips = 32;
-static_assert(kChunkStrips % kRun == 0, "chunks start on a run boundary");
+// Consecutive strips of one stream handed to a wavefront at a time (a
+// multiple of kRun, so chunks start on a run boundary): 32 unless tuned to
+// one of kChunkChoices.
+constexpr int kDefaultChunk = 32;
+constexpr int kChunkChoices[] = {8, 16, 32, 64};
 constexpr int kMaxPack = 4;        // w / K at most
 
 // Descriptors and chunks of one class, ranges in the launch's flat lists
@@ -71,6 +71,7 @@ constexpr int kMaxPack = 4;        // w / K at most
 struct KindRange {
   int32_t desc_begin, desc_end;
   int32_t chunk_begin, chunk_end;
+  int32_t chunk_strips;   // strips per chunk
 };
 
 struct BatchParams {
@@ -102,8 +103,8 @@ __device__ __forceinline__ int next_chunk(int32_t* queue, int lane) {
 // Persistent kernel of one class: every wavefront draws the class's chunks
 // until its list is exhausted.  The class's descriptors are contiguous and a
 // wavefront's chunks only grow, so its stream search only moves forward.
-template <int kBits, int kW, int kK, int kDepth>
-__global__ __launch_bounds__(kThreads) void batch_class_kernel(BatchParams p) {
+template <int kBits, int kW, int kK, int kDepth, int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void batch_class_kernel(BatchParams p) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   constexpr int kStage = stage_bytes(kW);
@@ -126,8 +127,8 @@ __global__ __launch_bounds__(kThreads) void batch_class_kernel(BatchParams p) {
        c = p.kr.chunk_begin + next_chunk(p.queue, lane)) {
     while (d < p.kr.desc_end - 1 && c >= streams[d].chunk_end) d++;
     o.validate = streams[d].validate;
-    const int s0 = (c - streams[d].chunk_begin) * kChunkStrips;
-    const int s1 = min(s0 + kChunkStrips, streams[d].strips);
+    const int s0 = (c - streams[d].chunk_begin) * p.kr.chunk_strips;
+    const int s1 = min(s0 + p.kr.chunk_strips, streams[d].strips);
     run_strips<kBits, kW, kK, kDepth, false, (kBits != 8)>(
         *(const StripGeom*)&streams[d].geom, o, pc, s0 / kRun, 1, s1, lane,
         stage_mem[wave]);
@@ -154,31 +155,37 @@ __global__ __launch_bounds__(kReduceThreads) void batch_reduce_kernel(BatchReduc
 
 using BatchKernel = void (*)(BatchParams);
 
-template <int B, int W, int K>
+template <int B, int W, int K, int V>
 BatchKernel pick_class_depth(int depth) {
-  if (depth == 1) return batch_class_kernel<B, W, K, 1>;
-  if (depth >= 4) return batch_class_kernel<B, W, K, 4>;
-  return batch_class_kernel<B, W, K, 2>;
+  if (depth == 1) return batch_class_kernel<B, W, K, 1, V>;
+  if (depth >= 4) return batch_class_kernel<B, W, K, 4, V>;
+  return batch_class_kernel<B, W, K, 2, V>;
+}
+
+template <int B, int W, int K>
+BatchKernel pick_class_waves(int depth, int waves) {
+  return waves == 8 ? pick_class_depth<B, W, K, 8>(depth) : pick_class_depth<B, W, K, 4>(depth);
 }
 
 template <int B, int W>
-BatchKernel pick_class_k(int ki, int depth) {
-  if (ki == 0) return pick_class_depth<B, W, W>(depth);
-  if (ki == 1) return pick_class_depth<B, W, W / 2>(depth);
-  return pick_class_depth<B, W, W / 4>(depth);
+BatchKernel pick_class_k(int ki, int depth, int waves) {
+  if (ki == 0) return pick_class_waves<B, W, W>(depth, waves);
+  if (ki == 1) return pick_class_waves<B, W, W / 2>(depth, waves);
+  return pick_class_waves<B, W, W / 4>(depth, waves);
 }
 
 template <int B>
-BatchKernel pick_class_w(int wi, int ki, int depth) {
-  if (wi == 0) return pick_class_k<B, 32>(ki, depth);
-  if (wi == 1) return pick_class_k<B, 16>(ki, depth);
-  return pick_class_k<B, 8>(ki, depth);
+BatchKernel pick_class_w(int wi, int ki, int depth, int waves) {
+  if (wi == 0) return pick_class_k<B, 32>(ki, depth, waves);
+  if (wi == 1) return pick_class_k<B, 16>(ki, depth, waves);
+  return pick_class_k<B, 8>(ki, depth, waves);
 }
 
-// Kernel of class `kind` (kind_of numbering) with the given ring depth.
-BatchKernel class_kernel_for(int kind, int depth) {
+// Kernel of class `kind` (kind_of numbering) with the given ring depth and
+// wavefronts per workgroup (4 or 8).
+BatchKernel class_kernel_for(int kind, int depth, int waves) {
   const int ki = kind % 3, wi = (kind / 3) % 3;
-  return kind < 9 ? pick_class_w<8>(wi, ki, depth) : pick_class_w<10>(wi, ki, depth);
+  return kind < 9 ? pick_class_w<8>(wi, ki, depth, waves) : pick_class_w<10>(wi, ki, depth, waves);
 }
 
 }  // namespace
@@ -285,6 +292,16 @@ void drop_graphs(vca_batch* b) {
   b->graphs.clear();
 }
 
+// Launch shape of class k: tuned, else ring depth 2, 4 wavefronts per
+// workgroup, as many workgroups per CU as fit and 32 strips per chunk.
+LaunchChoice class_choice(const vca_batch* b, int k) {
+  LaunchChoice c = b->kind_tuned[k];
+  if (c.depth <= 0) c = LaunchChoice{2, 0, 0.0, kDefaultWaves, kDefaultChunk};
+  if (c.waves != 4 && c.waves != 8) c.waves = kDefaultWaves;
+  if (c.chunk <= 0 || c.chunk % kRun != 0) c.chunk = kDefaultChunk;
+  return c;
+}
+
 // Fills the staging descriptors for one round: stream s analyses frames
 // [off[s], off[s] + cnt[s]) of its call.  Returns the number of chunks and of
 // frames of the round.
@@ -302,6 +319,7 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
     KindRange& kr = b->kinds[k];
     kr.desc_begin = i;
     kr.chunk_begin = chunks;
+    kr.chunk_strips = class_choice(b, k).chunk;
     for (int s = 0; s < b->n; s++) {
       const Geometry& g = b->geos[s];
       const vca_config& c = b->cfgs[s];
@@ -318,7 +336,7 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
       sd.kind = k;
       sd.strips = cnt[s] * sd.geom.strips_per_frame;
       sd.chunk_begin = chunks;
-      chunks += (sd.strips + kChunkStrips - 1) / kChunkStrips;
+      chunks += (sd.strips + kr.chunk_strips - 1) / kr.chunk_strips;
       sd.chunk_end = chunks;
       sd.validate = (c.flags & VCA_F_VALIDATE) && c.bit_depth == 10 ? 1 : 0;
       sd.stream = s;
@@ -366,23 +384,16 @@ void fill_descriptors(vca_batch* b, const vca_frames* fr, const int32_t* off, co
   *total_frames = frames;
 }
 
-// Launch shape of class k: tuned, else ring depth 2 and as many workgroups
-// per CU as fit.
-LaunchChoice class_choice(const vca_batch* b, int k) {
-  LaunchChoice c = b->kind_tuned[k];
-  if (c.depth <= 0) c = LaunchChoice{2, 0, 0.0};
-  return c;
-}
-
 // Enqueues class k's forward launch on st.
 vca_status launch_forward(vca_batch* b, hipStream_t st, int k, const LaunchChoice& lc) {
   const KindRange& kr = b->kinds[k];
-  BatchKernel kern = class_kernel_for(k, lc.depth);
+  const int waves = lc.waves == 8 ? 8 : 4;
+  BatchKernel kern = class_kernel_for(k, lc.depth, waves);
   int resident = 0;
-  BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, kThreads, 0));
+  BHIP_TRY(b, hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, kern, 64 * waves, 0));
   resident = std::max(1, resident);
   if (lc.groups_per_cu > 0) resident = std::min(resident, lc.groups_per_cu);
-  const int64_t groups = ((int64_t)(kr.chunk_end - kr.chunk_begin) + kWaves - 1) / kWaves;
+  const int64_t groups = ((int64_t)(kr.chunk_end - kr.chunk_begin) + waves - 1) / waves;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)b->num_cus * resident));
   BatchParams bp{};
   bp.streams = b->d_streams;
@@ -394,7 +405,7 @@ vca_status launch_forward(vca_batch* b, hipStream_t st, int k, const LaunchChoic
   bp.blk_dc = b->blk_dc;
   bp.err_flag = b->frame_err;
   bp.queue = b->queue + k;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, st, bp);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * waves), 0, st, bp);
   BHIP_TRY(b, hipGetLastError());
   return VCA_OK;
 }
@@ -747,6 +758,8 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
         const LaunchChoice lc = class_choice(b, k);
         sig.push_back(lc.depth);
         sig.push_back(lc.groups_per_cu);
+        sig.push_back(lc.waves);
+        sig.push_back(lc.chunk);
       }
       sig.push_back(b->serial);
       vca_batch::CachedGraph* hit = nullptr;
@@ -807,53 +820,78 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
   for (int s = 0; s < b->n; s++) cnt[s] = std::min<int32_t>(b->cfgs[s].max_batch, n_frames[s]);
   if ((st = wait_staging(b)) != VCA_OK) return st;
   int32_t chunks = 0, nfr = 0;
-  fill_descriptors(b, frames, off.data(), cnt.data(), &chunks, &nfr);
-  // no validation while tuning: no reduction follows to collect the marks
-  for (int i = 0; i < b->n; i++) b->h_streams[i].validate = 0;
-  if ((st = upload_descriptors(b)) != VCA_OK) return st;
   hipEvent_t e0, e1;
   BHIP_TRY(b, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return bfail(b, VCA_ERR_DEVICE, "hipEventCreate");
   }
-  // each class alone: every (ring depth, workgroups per CU) pair, forward
-  // launch only (no reduction: features and h state are untouched)
+  // the round's descriptors with the classes' current chunk sizes (no
+  // validation while tuning: no reduction follows to collect the marks)
+  auto refill = [&]() -> vca_status {
+    vca_status r = wait_staging(b);
+    if (r != VCA_OK) return r;
+    fill_descriptors(b, frames, off.data(), cnt.data(), &chunks, &nfr);
+    for (int i = 0; i < b->n; i++) b->h_streams[i].validate = 0;
+    return upload_descriptors(b);
+  };
+  // class k's forward launch alone with shape lc: its mean time over reps
+  // launches after one warm-up (features and h state are untouched)
+  auto time_class = [&](int k, const LaunchChoice& lc, double* ms_out) -> vca_status {
+    auto once = [&]() {
+      hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, b->stream, b->queue);
+      return launch_forward(b, b->stream, k, lc);
+    };
+    vca_status r = once();
+    if (r != VCA_OK) return r;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) return bfail(b, VCA_ERR_DEVICE, "hipEventRecord");
+    for (int i = 0; i < reps && r == VCA_OK; i++) r = once();
+    if (r != VCA_OK) return r;
+    if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *ms_out = ms / reps;
+    return VCA_OK;
+  };
+  // each class alone: every (ring depth, wavefronts per workgroup,
+  // workgroups per CU) at the default chunk size, then every chunk size at
+  // the best of those
+  st = refill();
   int list[kKinds];
-  const int n = present_classes(b, list);
+  const int n = st == VCA_OK ? present_classes(b, list) : 0;
   for (int j = 0; j < n && st == VCA_OK; j++) {
     const int k = list[j];
     LaunchChoice best;
     best.ms = 1e30;
-    for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
-      int resident = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, class_kernel_for(k, depth), kThreads, 0) !=
-          hipSuccess)
-        resident = 1;
-      for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
-        const LaunchChoice lc{depth, gpc, 0.0};
-        auto once = [&]() {
-          hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, b->stream, b->queue);
-          return launch_forward(b, b->stream, k, lc);
-        };
-        st = once();   // warm-up
-        if (st != VCA_OK) break;
-        if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
-        for (int r = 0; r < reps && st == VCA_OK; r++) st = once();
-        if (st != VCA_OK) break;
-        if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-          st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
-          break;
+    for (int waves = 4; waves <= 8 && st == VCA_OK; waves += 4) {
+      for (int depth = 1; depth <= 4 && st == VCA_OK; depth *= 2) {
+        int resident = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, class_kernel_for(k, depth, waves), 64 * waves,
+                                                         0) != hipSuccess)
+          resident = 1;
+        for (int gpc = 1; gpc <= std::max(1, resident) && st == VCA_OK; gpc++) {
+          const LaunchChoice lc{depth, gpc, 0.0, waves, class_choice(b, k).chunk};
+          double ms = 0.0;
+          if ((st = time_class(k, lc, &ms)) != VCA_OK) break;
+          if (ms < best.ms) best = LaunchChoice{depth, gpc, ms, waves, lc.chunk};
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        if (ms < best.ms) best = LaunchChoice{depth, gpc, ms};
       }
+    }
+    const int chunk0 = best.chunk;
+    for (int chunk : kChunkChoices) {
+      if (st != VCA_OK || chunk == chunk0) continue;
+      LaunchChoice lc = best;
+      lc.chunk = chunk;
+      b->kind_tuned[k] = lc;   // the descriptors follow the class's chunk size
+      double ms = 0.0;
+      if ((st = refill()) != VCA_OK || (st = time_class(k, lc, &ms)) != VCA_OK) break;
+      if (ms < best.ms) best = LaunchChoice{lc.depth, lc.groups_per_cu, ms, lc.waves, chunk};
     }
     if (st == VCA_OK) {
       b->kind_tuned[k] = best;
       TuneCache::get().put(class_tune_key(b, k), best);
+      st = refill();
     }
   }
   // then the arrangement of the tuned classes: forward launches only, one
@@ -894,12 +932,16 @@ vca_status vca_batch_tuned_launch(const vca_batch* b, int32_t* depth, int32_t* g
 }
 
 vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
-                                 int32_t* groups_per_cu) {
+                                 int32_t* groups_per_cu, int32_t* waves, int32_t* chunk_strips) {
   if (!b) return VCA_ERR_INVALID_ARG;
   for (int k = 0; k < kKinds; k++) {
-    if (ms) ms[k] = b->kind_tuned[k].depth > 0 ? b->kind_tuned[k].ms : 0.0;
-    if (depth) depth[k] = b->kind_tuned[k].depth;
-    if (groups_per_cu) groups_per_cu[k] = b->kind_tuned[k].groups_per_cu;
+    const LaunchChoice& t = b->kind_tuned[k];
+    const bool tuned = t.depth > 0;
+    if (ms) ms[k] = tuned ? t.ms : 0.0;
+    if (depth) depth[k] = tuned ? t.depth : 0;
+    if (groups_per_cu) groups_per_cu[k] = tuned ? t.groups_per_cu : 0;
+    if (waves) waves[k] = tuned ? class_choice(b, k).waves : 0;
+    if (chunk_strips) chunk_strips[k] = tuned ? class_choice(b, k).chunk : 0;
   }
   return VCA_OK;
 }
@@ -910,6 +952,18 @@ vca_status vca_batch_arrangement(const vca_batch* b, int32_t* serial, double* se
   if (serial) *serial = b->serial;
   if (serial_ms) *serial_ms = b->serial_ms;
   if (parallel_ms) *parallel_ms = b->parallel_ms;
+  return VCA_OK;
+}
+
+vca_status vca_batch_set_class_shape(vca_batch* b, int32_t cls, int32_t depth, int32_t groups_per_cu,
+                                     int32_t waves, int32_t chunk_strips) {
+  if (!b) return VCA_ERR_INVALID_ARG;
+  const bool chunk_ok = std::find(std::begin(kChunkChoices), std::end(kChunkChoices), chunk_strips) !=
+                        std::end(kChunkChoices);
+  if (cls < 0 || cls >= kKinds || (depth != 1 && depth != 2 && depth != 4) || groups_per_cu < 0 ||
+      (waves != 4 && waves != 8) || !chunk_ok)
+    return bfail(b, VCA_ERR_INVALID_ARG, "bad class shape");
+  b->kind_tuned[cls] = LaunchChoice{depth, groups_per_cu, 0.0, waves, chunk_strips};
   return VCA_OK;
 }
 

@@ -207,10 +207,13 @@ struct LaunchChoice {
   int depth = 0;          // work units in flight per wavefront (1..4)
   int groups_per_cu = 0;  // 0: as many as fit
   double ms = 0.0;
+  int waves = 0;          // batched form: wavefronts per workgroup (0: the default)
+  int chunk = 0;          // batched form: strips per chunk (0: the default)
 };
 
 // Process-wide cache of tuned launch choices, optionally persisted to the
-// text file named by VCA_TUNE_CACHE (one "key depth groups ms" per line).
+// text file named by VCA_TUNE_CACHE (one "key depth groups ms [waves chunk]"
+// per line).
 class TuneCache {
  public:
   static TuneCache& get() {
@@ -233,8 +236,8 @@ class TuneCache {
     if (!path || !*path) return;
     if (FILE* f = std::fopen(path, "w")) {
       for (const auto& kv : map_)
-        std::fprintf(f, "%s %d %d %.6f\n", kv.first.c_str(), kv.second.depth,
-                     kv.second.groups_per_cu, kv.second.ms);
+        std::fprintf(f, "%s %d %d %.6f %d %d\n", kv.first.c_str(), kv.second.depth,
+                     kv.second.groups_per_cu, kv.second.ms, kv.second.waves, kv.second.chunk);
       std::fclose(f);
     }
   }
@@ -247,10 +250,17 @@ class TuneCache {
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    char key[256];
-    LaunchChoice c;
-    while (std::fscanf(f, "%255s %d %d %lf", key, &c.depth, &c.groups_per_cu, &c.ms) == 4)
-      if (c.depth >= 1 && c.depth <= 4 && c.groups_per_cu >= 0) map_[key] = c;
+    char line[512], key[256];
+    while (std::fgets(line, sizeof(line), f)) {
+      LaunchChoice c;
+      const int n = std::sscanf(line, "%255s %d %d %lf %d %d", key, &c.depth, &c.groups_per_cu, &c.ms,
+                                &c.waves, &c.chunk);
+      if (n != 4 && n != 6) continue;
+      if (n == 4) c.waves = c.chunk = 0;
+      if (c.depth >= 1 && c.depth <= 4 && c.groups_per_cu >= 0 && (c.waves == 0 || c.waves == 4 || c.waves == 8) &&
+          c.chunk >= 0 && c.chunk <= 1024 && c.chunk % 8 == 0)
+        map_[key] = c;
+    }
     std::fclose(f);
   }
   std::mutex mu_;

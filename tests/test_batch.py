@@ -186,7 +186,8 @@ def test_batch_tune_and_no_graph_path(vca, frames, monkeypatch):
     assert arr["serial"] == (arr["serial_ms"] <= arr["parallel_ms"])
     times = b.class_times()
     assert set(times) == {"b8_w8_k8", "b8_w32_k16", "b8_w16_k16", "b8_w32_k32", "b8_w8_k4"}
-    assert all(t["ms"] > 0 and t["depth"] in (1, 2, 4) and t["groups_per_cu"] >= 1 for t in times.values())
+    assert all(t["ms"] > 0 and t["depth"] in (1, 2, 4) and t["groups_per_cu"] >= 1 and
+               t["waves"] in (4, 8) and t["chunk_strips"] in (8, 16, 32, 64) for t in times.values())
     b.submit(sub)
     tuned = [b.features(s, 0, d["n"]) for s, d in enumerate(STREAMS[:6])]
     b.close()
@@ -208,6 +209,28 @@ def test_batch_tune_and_no_graph_path(vca, frames, monkeypatch):
             b3.set_arrangement(2)
         finally:
             b3.close()
+
+
+@pytest.mark.parametrize("waves,chunk", [(8, 8), (4, 64), (8, 16)])
+def test_batch_class_shapes(vca, frames, waves, chunk):
+    """Every class pinned to 4 or 8 wavefronts per workgroup and 8 to 64
+    strips per chunk gives the plain path's features (two rounds, so h
+    crosses a round); bad shapes fail before any launch."""
+    print_case(test="batch_class_shapes", waves=waves, chunk=chunk)
+    b = vca.Batch(STREAMS)
+    classes = {f"b{d.get('bit_depth', 8)}_w{d['block_size']}_k{d.get('lowpass_k', 0) or d['block_size']}"
+               for d in STREAMS}
+    for i, cls in enumerate(sorted(classes)):
+        b.set_class_shape(cls, (1, 2, 4)[i % 3], i % 3, waves, chunk)
+    b.submit(list(frames))
+    b.submit(list(frames))
+    got = [b.features(s, 0, 2 * d["n"]) for s, d in enumerate(STREAMS)]
+    for bad in ((3, 0, 4, 32), (2, -1, 4, 32), (2, 0, 6, 32), (2, 0, 4, 24)):
+        with pytest.raises(vca.VcaError):
+            b.set_class_shape("b8_w32_k32", *bad)
+    b.close()
+    for s, d in enumerate(STREAMS):
+        assert got[s].tobytes() == plain_features(vca, d, frames[s], 2).tobytes(), f"stream {s} ({d})"
 
 
 def test_plain_tune(vca, frames):
