@@ -275,11 +275,15 @@ vca_status vca_analyze_noalloc(const vca_config* cfg, const vca_frames* frames, 
  * launches: per class of streams (bit depth, w, K) ONE persistent kernel
  * launch over all their tiles (its wavefronts draw work from a device counter
  * of the class; one small kernel zeroes the counters first), each followed by
- * the class's reduction launch, the classes on parallel branches; the round
- * is captured into a hipGraph on the first call with a given frame-count
- * signature and replayed afterwards (only the per-stream descriptor tables
- * are uploaded per call).  Per stream the results are identical to a
- * vca_ctx opened with the same configuration and fed the same frames. */
+ * the class's reduction launch, the classes one after another or side by
+ * side on parallel branches (the tuned arrangement); the round is captured
+ * into a hipGraph on the first call with a given signature (frames per
+ * stream, class shapes, arrangement) and replayed afterwards (only the
+ * per-stream descriptor tables are uploaded per call).  A batch keeps up to
+ * 16 such graphs until it is closed; a round with a further signature runs
+ * its launches in line on the batch's stream.  Per stream the results are
+ * identical to a vca_ctx opened with the same configuration and fed the
+ * same frames. */
 typedef struct vca_batch vca_batch; /* opaque; owned by the library */
 
 /* Opens a batch of n_streams streams (cfgs[s] configures stream s; all on

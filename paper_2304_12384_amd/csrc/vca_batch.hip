@@ -227,16 +227,14 @@ struct vca_batch {
   ReduceParams* h_red = nullptr;
   hipEvent_t uploaded = nullptr;   // staging buffers reusable once this completes
   bool upload_pending = false;
-  // executable graphs of the recent launch signatures (frames per stream and
-  // per-class launch shapes), least recently used first out
+  // executable graphs of the launch signatures met so far (frames per stream,
+  // per-class launch shapes, arrangement), up to kMaxGraphs
   struct CachedGraph {
     std::vector<int32_t> sig;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t used = 0;
   };
   std::vector<CachedGraph> graphs;
-  uint64_t graph_clock = 0;
   bool use_graph = true;
   KindRange kinds[kKinds] = {};    // flat-list ranges of the current round
   int32_t kind_frames[kKinds] = {};   // frames of each class in the current round
@@ -279,11 +277,15 @@ vca_status balloc(vca_batch* b, T** p, size_t count) {
   return VCA_OK;
 }
 
-constexpr size_t kMaxGraphs = 8;
+// Executable graphs a batch keeps.  None is destroyed before the batch is
+// closed: destroying a cached graph and then capturing another crashed the
+// host inside the HIP runtime (both with the graph's launch possibly still
+// pending and after draining the stream), so a round whose signature finds
+// the cache full runs its launches eagerly, in line on the batch's stream.
+constexpr size_t kMaxGraphs = 16;
 
-// Destroys every cached graph.  The caller has drained the batch's stream:
-// an executable graph whose launch may still be pending is never destroyed
-// (its independent branches run on streams the executable owns).
+// Destroys every cached graph (at close, once the batch's stream has
+// drained).
 void drop_graphs(vca_batch* b) {
   for (auto& c : b->graphs) {
     if (c.exec) (void)hipGraphExecDestroy(c.exec);
@@ -483,6 +485,22 @@ vca_status enqueue_classes(vca_batch* b, hipStream_t st, bool serial, bool with_
 // One round on st in the batch's arrangement of classes.
 vca_status enqueue_round(vca_batch* b, hipStream_t st) {
   return enqueue_classes(b, st, b->serial != 0, true);
+}
+
+// One round on st alone, with no branch: every class's forward launch and
+// then its reduction, class after class (rounds whose signature finds the
+// graph cache full).
+vca_status enqueue_round_in_line(vca_batch* b, hipStream_t st) {
+  int list[kKinds];
+  const int n = present_classes(b, list);
+  hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(64), 0, st, b->queue);
+  BHIP_TRY(b, hipGetLastError());
+  vca_status s = VCA_OK;
+  for (int j = 0; j < n; j++) {
+    if ((s = launch_forward(b, st, list[j], class_choice(b, list[j]))) != VCA_OK) return s;
+    if ((s = launch_reduce(b, st, list[j])) != VCA_OK) return s;
+  }
+  return VCA_OK;
 }
 
 // Copies the staging descriptors to the device on the batch's stream.
@@ -765,16 +783,8 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
       vca_batch::CachedGraph* hit = nullptr;
       for (auto& c : b->graphs)
         if (c.sig == sig) hit = &c;
-      if (!hit) {
-        if (b->graphs.size() >= kMaxGraphs) {
-          // evict the least recently used once the stream has drained
-          BHIP_TRY(b, hipStreamSynchronize(b->stream));
-          auto lru = std::min_element(b->graphs.begin(), b->graphs.end(),
-                                      [](const auto& x, const auto& y) { return x.used < y.used; });
-          (void)hipGraphExecDestroy(lru->exec);
-          (void)hipGraphDestroy(lru->graph);
-          b->graphs.erase(lru);
-        }
+      const bool eager = !hit && b->graphs.size() >= kMaxGraphs;   // cache full
+      if (!hit && !eager) {
         BHIP_TRY(b, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
         st = enqueue_round(b, b->capture);
         hipGraph_t g = nullptr;
@@ -790,11 +800,14 @@ vca_status vca_analyze_batch(vca_batch* b, const vca_frames* frames, const int32
           (void)hipGraphDestroy(g);
           return bfail(b, VCA_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
         }
-        b->graphs.push_back(vca_batch::CachedGraph{sig, g, x, 0});
+        b->graphs.push_back(vca_batch::CachedGraph{sig, g, x});
         hit = &b->graphs.back();
       }
-      hit->used = ++b->graph_clock;
-      BHIP_TRY(b, hipGraphLaunch(hit->exec, b->stream));
+      if (eager) {
+        if ((st = enqueue_round_in_line(b, b->stream)) != VCA_OK) return st;
+      } else {
+        BHIP_TRY(b, hipGraphLaunch(hit->exec, b->stream));
+      }
     } else {
       if ((st = enqueue_round(b, b->stream)) != VCA_OK) return st;
     }
