@@ -273,6 +273,42 @@ def test_batch_class_shapes(vca, frames, waves, chunk):
         assert got[s].tobytes() == plain_features(vca, d, frames[s], 2).tobytes(), f"stream {s} ({d})"
 
 
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_batch_random_mixes(vca, seed):
+    """Seeded random mixes of 5-9 streams (width and height, w, K, bit depth
+    and frame count drawn per stream; some streams share a class, some
+    classes hold one stream), two calls each: every stream's features equal
+    the plain path's bytes."""
+    rng = np.random.default_rng(seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    descs, planes = [], []
+    for _ in range(int(rng.integers(5, 10))):
+        w = int(rng.choice([8, 16, 32]))
+        k = int(rng.choice([0, w // 2, w // 4]))
+        bits = int(rng.choice([8, 10]))
+        width = 32 * int(rng.integers(max(2, w // 16 + 1), 40))
+        height = 2 * int(rng.integers(w, 200))
+        n = int(rng.integers(1, 7))
+        top = (1 << bits) - 1
+        dt = torch.uint8 if bits == 8 else torch.int16
+        pl = tuple(torch.randint(0, top + 1, (n, hh, ww), device="cuda", generator=g).to(dt)
+                   for hh, ww in ((height, width), (height // 2, width // 2), (height // 2, width // 2)))
+        descs.append(dict(width=width, height=height, block_size=w, lowpass_k=k, bit_depth=bits, n=n))
+        planes.append(pl)
+    print_case(test="batch_random_mix", seed=seed,
+               streams=[(d["width"], d["height"], d["block_size"], d["lowpass_k"], d["bit_depth"], d["n"])
+                        for d in descs])
+    b = vca.Batch(descs)
+    b.submit(planes)
+    b.submit(planes)
+    got = [b.features(s, 0, 2 * d["n"]) for s, d in enumerate(descs)]
+    b.close()
+    for s, d in enumerate(descs):
+        ref = plain_features(vca, d, planes[s], 2)
+        assert got[s].tobytes() == ref.tobytes(), f"stream {s} ({d})"
+
+
 def test_plain_tune(vca, frames):
     print_case(test="plain_tune")
     d = STREAMS[5]
