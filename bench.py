@@ -439,6 +439,17 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
             fwd_ms += ev[0].elapsed_time(ev[1]) / reps
             bwd_ms += ev[1].elapsed_time(ev[2]) / reps
     assert torch.equal(gxb, gx), "C-ABI backward differs from the autograd path"
+    # the forward call alone, back to back: its reads then find no dirty
+    # gradient lines of a preceding backward call waiting to be written back
+    fwd_alone_ms = 0.0
+    for i in range(reps + 1):
+        ev[0].record(stream)
+        _lib.check(L.vca_energy_forward(ctypes.byref(cfg), xd.data_ptr(), E.data_ptr(), h.data_ptr(),
+                                        ws.data_ptr(), stream.cuda_stream), "vca_energy_forward")
+        ev[1].record(stream)
+        ev[1].synchronize()
+        if i > 0:
+            fwd_alone_ms += ev[0].elapsed_time(ev[1]) / reps
 
     an = vca.Analyzer(W, H, block_size=w, max_batch=n)
     for _ in range(warmup):
@@ -461,6 +472,8 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
     f16_bwd = tiles * 10 * 2 * 32 * 32 * 16
     bw_gbs = bytes_bwd / (bwd_ms * 1e-3) / 1e9
     fw_gbs = bytes_fwd / (fwd_ms * 1e-3) / 1e9
+    fa_gbs = bytes_fwd / (fwd_alone_ms * 1e-3) / 1e9
+    pair_gbs = (bytes_fwd + bytes_bwd) / ((fwd_ms + bwd_ms) * 1e-3) / 1e9
     return {
         "value": steps * n / dt, "unit": "frames/s",
         "workload": f"{n_seq} pairs of {W}x{H} float32 luma (8-bit values), w={w}, "
@@ -473,6 +486,12 @@ def run_backward(vca, steps: int, warmup: int) -> dict:
                               "unit": "TFLOP/s"},
         "forward_hbm": {"achieved": fw_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": fw_gbs / HBM_PEAK_GBS},
+        "forward_alone": {"ms": fwd_alone_ms, "achieved": fa_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": fa_gbs / HBM_PEAK_GBS,
+                          "what": "forward calls back to back, no backward call between them"},
+        "pair_hbm": {"achieved": pair_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": pair_gbs / HBM_PEAK_GBS, "bytes": bytes_fwd + bytes_bwd,
+                     "what": "forward + backward call: both calls' algorithmic bytes over both kernels' time"},
         "forward_mfma_f16": {"achieved": f16_fwd / (fwd_ms * 1e-3) / 1e12, "peak": FP16_PEAK_TFLOPS,
                              "unit": "TFLOP/s"},
         "plain_same_frames": {"value": steps * n / dt_plain, "unit": "frames/s",
@@ -656,7 +675,9 @@ def main() -> int:
         log("timing the backward form")
         backward = run_backward(vca, max(50, 5 * args.steps), 20)
         log(f"backward: {backward['value']:.0f} frames/s forward+backward, kernels "
-            f"{backward['forward_kernel_ms']:.3f} + {backward['backward_kernel_ms']:.3f} ms")
+            f"{backward['forward_kernel_ms']:.3f} + {backward['backward_kernel_ms']:.3f} ms "
+            f"(pair {backward['pair_hbm']['frac']:.2f} of HBM; forward alone "
+            f"{backward['forward_alone']['ms']:.3f} ms, {backward['forward_alone']['frac']:.2f})")
 
     cpu = None
     if args.cpu_frames > 0:
