@@ -423,6 +423,12 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
   H8 ct[2];
 #pragma unroll
   for (int h = 0; h < 2; h++) ct[h] = ld8(p.tab->ct[h], lane);
+  // one 32 x 32 gradient tile per wavefront, rows padded to 36 floats: the
+  // eight lanes of one 16-byte piece of eight rows (the writes) and the eight
+  // lanes of one row (the reads) fall in different banks
+  constexpr int kStageRow = 36;
+  __shared__ __attribute__((aligned(16))) float stage_all[kGWaves][32 * kStageRow];
+  float* const stage = stage_all[wave];
   const int total = p.n_frames * p.tiles_per_frame;
   const int stride = gridDim.x * kGWaves;
   // a tile's inputs: its sign masks; per block column of the lane's block
@@ -510,19 +516,28 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
       if (has_next) c -= ghn * sgn(cur.hn[b] - cur.hc[b]);
       cb[b] = c * p.grad_scale;
     }
-    // pixel (r, m_j): registers 4q..4q+3 are columns 8q + 4g + 0..3
-    float* out = p.gx + t.origin + (int64_t)r * p.pitch;
-    const int rows = t.vr * kW, cols = t.vc * kW;
-    if (r < rows) {
+    // pixel (r, m_j): registers 4q..4q+3 are columns 8q + 4g + 0..3.  The
+    // scaled tile goes through the wavefront's LDS area and comes back as
+    // whole rows: store q of lane 8 rho + pi writes piece pi (16 bytes) of row
+    // 8 q + rho, so each store instruction covers eight full 128-byte rows.
+    // Whole-row streaming stores go on to HBM during this kernel; 16-byte
+    // pieces of 32 rows per instruction leave the gradients as dirty lines
+    // in the memory-side cache, written back while the next forward call
+    // reads its samples.
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const int col = 8 * q + 4 * g;
-        if (col < cols) {
-          const float c = cb[col / kW];
-          const v4f v = {gt[4 * q] * c, gt[4 * q + 1] * c, gt[4 * q + 2] * c, gt[4 * q + 3] * c};
-          *reinterpret_cast<v4f*>(out + col) = v;
-        }
-      }
+    for (int q = 0; q < 4; q++) {
+      const int col = 8 * q + 4 * g;
+      const float c = cb[col / kW];
+      const v4f v = {gt[4 * q] * c, gt[4 * q + 1] * c, gt[4 * q + 2] * c, gt[4 * q + 3] * c};
+      *reinterpret_cast<v4f*>(&stage[r * kStageRow + col]) = v;
+    }
+    const int rows = t.vr * kW, cols = t.vc * kW;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int row = 8 * q + (lane >> 3), col = 4 * (lane & 7);
+      const v4f v = *reinterpret_cast<const v4f*>(&stage[row * kStageRow + col]);
+      if (row < rows && col < cols)
+        __builtin_nontemporal_store(v, reinterpret_cast<v4f*>(p.gx + t.origin + (int64_t)row * p.pitch + col));
     }
   };
   // Two input sets in turn, as in the forward kernel: the next tile's loads
