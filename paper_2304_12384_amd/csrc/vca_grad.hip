@@ -63,16 +63,19 @@ struct H8 {
 };
 
 // Per-lane operand tables and weights.  Slot s of MFMA h of lane (c + 32 g):
-//   b1: Cd[c][16 g + 8 h + s]        (stage 1 B; the lane's samples 16 g..)
+//   b1: 2^-12 Cd[c][16 g + 8 h + s]  (stage 1 B; the lane's samples 16 g..)
 //   a2: Cd[c][m_{8h+s}(g)]           (stage 2 A; T rows held in registers)
-//   a2x2: 2 a2                        (stage 2 A of the 2 t_h digit products)
+//   a2x2: 2^-11 a2                    (stage 2 A of the 2 t_h digit products)
 //   ct: Cd[m_{8h+s}(g)][c]           (backward: B of S^T Cd and A of Cd^T U)
+// The 2^-12 of b1 makes the horizontal pass T / 4096 (its split needs no
+// scaling); a2x2 and wd carry the matching powers of two, so every value is
+// the unscaled one times a power of two and rounds alike.
 struct alignas(16) GradTables {
   H8 b1[2][64];
   H8 a2[2][64];
   H8 a2x2[2][64];
   H8 ct[2][64];
-  double wd[16][64];   // weight * 2^-(s1+s2) of coefficient register j (energy)
+  double wd[16][64];   // weight * 2^-(s1+s2) * 4096 of coefficient register j (energy)
   float w0[16][64];    // weight = w0 + w1, both fp16 values (backward)
   float w1[16][64];
 };
@@ -190,7 +193,7 @@ __device__ inline bool digit(const float (&x)[16], int which, H8 (&d)[2]) {
         const float ia = rintf(xv);
         float r = xv - ia;                                   // exact, |r| <= 1/2
         if (which == 0) {
-          frac |= r != 0.f;
+          frac |= xv != ia;
           v[e] = ia;
         } else {
           const float ib = rintf(r * 2048.f);
@@ -208,7 +211,8 @@ __device__ inline bool digit(const float (&x)[16], int which, H8 (&d)[2]) {
   return frac;
 }
 
-// Horizontal pass of one digit: T = X Cd^T (|T| <= 2048 * 2048 = 2^22).
+// Horizontal pass of one digit, T / 4096 = X (2^-12 Cd)^T (|T| <= 2048 * 2048 =
+// 2^22, an integer, so T / 4096 is exact in FP32).
 __device__ inline v16f stage1(const H8 (&b1)[2], const H8 (&xd)[2]) {
   v16f t = {};
   t = mma(xd[0], b1[0], t);
@@ -216,15 +220,16 @@ __device__ inline v16f stage1(const H8 (&b1)[2], const H8 (&xd)[2]) {
   return t;
 }
 
-// Vertical-pass operands of T's registers 8h..8h+7: T = 4096 th + tl with
-// th = rint(T / 4096) (|th| <= 1024) and |tl| <= 2048.
+// Vertical-pass operands of registers 8h..8h+7 of t = T / 4096: T = 4096 th +
+// tl with th = rint(t) (|th| <= 1024, an integer) and tl / 4096 = t - th
+// (|tl| <= 2048 an integer, so tl / 4096 is exact in fp16).
 __device__ inline void split_t(const v16f& t, int h, H8& th, H8& tl) {
 #pragma unroll
   for (int q = 0; q < 4; q++) {
     const int j = 8 * h + 2 * q;
-    const float ha = rintf(t[j] * (1.f / 4096.f)), hb = rintf(t[j + 1] * (1.f / 4096.f));
+    const float ha = rintf(t[j]), hb = rintf(t[j + 1]);
     th.w[q] = pk(ha, hb);
-    tl.w[q] = pk(fmaf(-4096.f, ha, t[j]), fmaf(-4096.f, hb, t[j + 1]));
+    tl.w[q] = pk(t[j] - ha, t[j + 1] - hb);
   }
 }
 
@@ -235,6 +240,8 @@ __device__ inline void split_t(const v16f& t, int h, H8& th, H8& tl) {
 //   A3 = Cd t_l(b) + 2Cd t_h(c),  A4 = Cd t_l(c),
 // where t(d) is the horizontal pass of digit d.  |t_h(b)|, |t_h(c)| <= 512,
 // so A2 and A3 stay below 2^23 and every accumulator is an exact integer.
+// The accumulators hold A1 and A2 / 4096, A3 / 4096, A4 / 4096 (the t_l
+// operands and a2x2 carry the 2^-12), so Y / 4096 is formed.
 // kFrac = false: integer samples (b = c = 0), A1 and A2 only.
 struct YAcc {
   v16f a1, a2, a3, a4;
@@ -280,11 +287,11 @@ __device__ inline YAcc tile_acc(const H8 (&b1)[2], const H8 (&a2)[2], const H8 (
   return y;
 }
 
-// Coefficient j of the tile from its accumulators, exactly (up to one FP64
-// rounding in the last term).
+// Coefficient j of the tile / 4096 from its accumulators, exactly (up to one
+// FP64 rounding in the last term).
 template <bool kFrac>
 __device__ inline double coeff(const YAcc& y, int j) {
-  double v = fma(4096.0, (double)y.a1[j], (double)y.a2[j]);
+  double v = (double)y.a1[j] + (double)y.a2[j];
   if constexpr (kFrac) {
     v = fma(0x1p-11, (double)y.a3[j], v);
     v = fma(0x1p-22, (double)y.a4[j], v);
@@ -603,9 +610,9 @@ void build_grad_tables(int w, int K, int bit_depth, GradTables& t) {
       float vb1[8], va2[8], va2x2[8], vct[8];
       for (int s = 0; s < 8; s++) {
         const int m = reg_row(8 * h + s, g);
-        vb1[s] = (float)matd(w, c, 16 * g + 8 * h + s);
+        vb1[s] = std::ldexp((float)matd(w, c, 16 * g + 8 * h + s), -12);
         va2[s] = (float)matd(w, c, m);
-        va2x2[s] = 2.f * va2[s];
+        va2x2[s] = std::ldexp(va2[s], -11);
         vct[s] = (float)matd(w, m, c);
       }
       put8(t.b1[h][lane], vb1);
@@ -615,7 +622,7 @@ void build_grad_tables(int w, int K, int bit_depth, GradTables& t) {
     }
     for (int j = 0; j < 16; j++) {
       const double wv = wt[j * 64 + lane];
-      t.wd[j][lane] = wv * sc;
+      t.wd[j][lane] = std::ldexp(wv * sc, 12);
       const float hi = (float)(_Float16)(float)wv;      // nearest fp16
       const float lo = (float)(_Float16)(float)(wv - (double)hi);
       t.w0[j][lane] = hi;
