@@ -26,7 +26,10 @@
 //            c = (dL/dE_t + dL/dh_t sgn(H_t - H_{t-1})
 //                 - dL/dh_{t+1} sgn(H_{t+1} - H_t)) 2^-(s1+s2) / (C_Y w^2).
 //            The backward reads 256 bytes of masks per tile instead of the
-//            4 KiB tile of samples, and does not repeat the forward passes.
+//            4 KiB tile of samples, and does not repeat the forward passes;
+//            it writes each gradient tile as whole 128-byte rows (through
+//            LDS) with streaming stores, so no dirty gradient lines are left
+//            in the memory-side cache for the next forward call's reads.
 
 #include <hip/hip_runtime.h>
 
