@@ -326,10 +326,13 @@ vca_status vca_batch_features_many(vca_batch* b, int32_t n_requests, const int32
  * ring depth (1, 2, 4), wavefronts per workgroup (4, 8) and count of
  * workgroups per compute unit that fits, then every chunk size (8, 16, 32,
  * 64 strips) at the fastest of those, and keeps the fastest per class; then
- * times the tuned classes one after another and side by side and keeps the
- * faster arrangement (vca_batch_arrangement).  Cached under the batch's
- * stream list for the process (and in the file named by VCA_TUNE_CACHE).
- * Features and h state are unchanged. */
+ * times whole rounds of the tuned classes (reductions included) one after
+ * another and side by side, max(reps, 4) of each in turn, and keeps the
+ * faster arrangement
+ * (vca_batch_arrangement).  Cached under the batch's stream list for the
+ * process (and in the file named by VCA_TUNE_CACHE).  Allocates a scratch
+ * area of 32 bytes per feature-ring slot of the largest ring while it runs
+ * (VCA_ERR_OOM if that fails).  Features and h state are unchanged. */
 vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t* n_frames,
                           int32_t reps);
 
@@ -353,8 +356,8 @@ vca_status vca_batch_class_times(const vca_batch* b, double* ms, int32_t* depth,
  * the next class), 0 when they run side by side on parallel branches.
  * Serial unless vca_tune_batch (here or earlier in the process, or through
  * VCA_TUNE_CACHE) measured side by side faster; *serial_ms and *parallel_ms
- * are those tuned forward-round times (0 when not measured).  Each output
- * may be NULL.  Host only. */
+ * are those tuned round times, reductions included (0 when not measured).
+ * Each output may be NULL.  Host only. */
 vca_status vca_batch_arrangement(const vca_batch* b, int32_t* serial, double* serial_ms,
                                  double* parallel_ms);
 

@@ -480,7 +480,8 @@ class Batch:
 
     def arrangement(self) -> dict:
         """How a round runs its classes: {"serial": bool, "serial_ms", "parallel_ms"}
-        (the tuned forward-round times of either arrangement, 0 if not measured)."""
+        (the tuned round times of either arrangement, reductions included, 0 if
+        not measured)."""
         sr, sm, pm = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
         check(_lib.lib().vca_batch_arrangement(self._b, ctypes.byref(sr), ctypes.byref(sm),
                                                ctypes.byref(pm)), "vca_batch_arrangement",

@@ -244,7 +244,7 @@ struct vca_batch {
   hipEvent_t join_ev[kKinds] = {};
   hipEvent_t fwd_ev[kKinds] = {};     // serial arrangement: class j's forward launch done
   int serial = 1;                     // classes one after another (1) or side by side (0)
-  double serial_ms = 0.0, parallel_ms = 0.0;   // tuned forward rounds of either arrangement
+  double serial_ms = 0.0, parallel_ms = 0.0;   // tuned whole rounds of either arrangement
   LaunchChoice kind_tuned[kKinds];    // per class: ring depth, workgroups per CU, ms
   LaunchChoice tuned;                 // summary: the most expensive class's shape, total ms
   // timing
@@ -553,10 +553,11 @@ void load_tuned(vca_batch* b) {
     }
   }
   if (worst >= 0.0) b->tuned.ms = total;
-  // the arrangement of the classes: serial unless side by side measured faster
+  // the arrangement of the classes: serial unless side by side measured
+  // faster over whole rounds
   LaunchChoice par, ser;
-  if (TuneCache::get().find(batch_tune_key(b) + "/parallel", &par) &&
-      TuneCache::get().find(batch_tune_key(b) + "/serial", &ser)) {
+  if (TuneCache::get().find(batch_tune_key(b) + "/parallel_round", &par) &&
+      TuneCache::get().find(batch_tune_key(b) + "/serial_round", &ser)) {
     b->parallel_ms = par.ms;
     b->serial_ms = ser.ms;
     b->serial = ser.ms <= par.ms ? 1 : 0;
@@ -907,27 +908,56 @@ vca_status vca_tune_batch(vca_batch* b, const vca_frames* frames, const int32_t*
       st = refill();
     }
   }
-  // then the arrangement of the tuned classes: forward launches only, one
-  // after another or side by side
+  // then the arrangement of the tuned classes, one after another or side by
+  // side: whole rounds, reductions included (in the serial arrangement they
+  // run beside the next class's forward launch, which decides between the
+  // two).  The reductions' features and marks go to a scratch area and
+  // their h state to the buffer the next round overwrites, so no stream's
+  // features or state change.
   double arr_ms[2] = {0.0, 0.0};
+  void* scratch = nullptr;
   if (st == VCA_OK && n > 1) st = ensure_branches(b, n);
-  for (int serial = 0; serial < 2 && st == VCA_OK && n > 1; serial++) {
-    st = enqueue_classes(b, b->stream, serial != 0, false);   // warm-up
-    if (st != VCA_OK) break;
+  if (st == VCA_OK && n > 1) {
+    int64_t cap = 1;
+    for (int s = 0; s < b->n; s++) cap = std::max<int64_t>(cap, b->cfgs[s].feature_capacity);
+    if (hipMalloc(&scratch, (size_t)cap * 8 * sizeof(float)) != hipSuccess) {
+      scratch = nullptr;
+      st = bfail(b, VCA_ERR_OOM, "hipMalloc (tuning scratch)");
+    } else if ((st = wait_staging(b)) == VCA_OK) {
+      for (int i = 0; i < b->n; i++) {
+        b->h_red[i].ring = static_cast<float*>(scratch);
+        b->h_red[i].err_ring = reinterpret_cast<int32_t*>(static_cast<float*>(scratch) + cap * 7);
+      }
+      st = upload_descriptors(b);
+    }
+  }
+  // one warm-up round of each, then at least four rounds of each in turn,
+  // so that a drift of the clock over the tuning falls on both alike
+  const int arr_reps = std::max(reps, 4);
+  for (int serial = 0; serial < 2 && st == VCA_OK && n > 1; serial++)
+    st = enqueue_classes(b, b->stream, serial != 0, true);
+  for (int r = 0; r < 2 * arr_reps && st == VCA_OK && n > 1; r++) {
+    const int serial = r & 1;
     if (hipEventRecord(e0, b->stream) != hipSuccess) { st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord"); break; }
-    for (int r = 0; r < reps && st == VCA_OK; r++) st = enqueue_classes(b, b->stream, serial != 0, false);
-    if (st != VCA_OK) break;
+    if ((st = enqueue_classes(b, b->stream, serial != 0, true)) != VCA_OK) break;
     if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
       st = bfail(b, VCA_ERR_DEVICE, "hipEventRecord/Synchronize");
       break;
     }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
-    arr_ms[serial] = ms / reps;
+    arr_ms[serial] += ms / arr_reps;
+  }
+  if (scratch) {
+    // every launch that writes the scratch area has finished before it goes
+    if (hipStreamSynchronize(b->stream) != hipSuccess && st == VCA_OK)
+      st = bfail(b, VCA_ERR_DEVICE, "hipStreamSynchronize");
+    (void)hipFree(scratch);
+    if (st == VCA_OK) st = refill();   // the real feature rings back in the descriptors
   }
   if (st == VCA_OK && n > 1) {
-    TuneCache::get().put(batch_tune_key(b) + "/parallel", LaunchChoice{1, 0, arr_ms[0]});
-    TuneCache::get().put(batch_tune_key(b) + "/serial", LaunchChoice{1, 0, arr_ms[1]});
+    TuneCache::get().put(batch_tune_key(b) + "/parallel_round", LaunchChoice{1, 0, arr_ms[0]});
+    TuneCache::get().put(batch_tune_key(b) + "/serial_round", LaunchChoice{1, 0, arr_ms[1]});
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
