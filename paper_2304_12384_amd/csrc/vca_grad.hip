@@ -19,7 +19,7 @@
 //            exact for such samples (|x| < 2^11).  Tiles of integer samples
 //            have b = c = 0 and skip their products.  Block energies in
 //            FP64; per tile the signs of the coefficients go to the
-//            workspace as two 16-bit masks per lane.
+//            workspace as sixteen 2-bit fields per lane.
 //   backward S = W o sign(Y) from the masks (W = w0 + w1, two fp16 parts),
 //            U = S^T Cd, G^T = Cd^T U (U in three fp16 parts), both chained
 //            in registers, then each block of G times its upstream factor
@@ -87,7 +87,7 @@ struct GradParams {
   const float* x;
   float* gx;
   double* blk_h;        // [frames][C_Y]
-  uint32_t* masks;      // [tiles][64]: bit j positive, bit 16 + j negative
+  uint32_t* masks;      // [tiles][64]: bits 2j, 2j + 1 sign(Y_j) as a 2-bit signed field
   const float* gE;      // [frames]
   const float* gh;      // [frames]
   const GradTables* tab;
@@ -322,16 +322,27 @@ __global__ __launch_bounds__(kGThreads) void energy_fwd_kernel(GradParams p) {
   const int stride = gridDim.x * kGWaves;
   int id = blockIdx.x * kGWaves + wave;
   if (id >= total) return;
-  // Energies and coefficient signs of tile `id` (samples x).
-  // energies and sign masks from the exact coefficients
+  // Energies and coefficient signs of tile `id` (samples x), from the exact
+  // coefficients.  sign(Y_j) goes into bits 2j, 2j + 1 of the lane's mask as
+  // a 2-bit signed field (1, 0 or -1), shifted in from the top one field per
+  // register.  Adding +0.0 turns a -0 into +0; a nonzero coefficient is far
+  // above the subnormal range, so the high word of its FP64 value is a
+  // positive or negative integer other than 0x80000000, and its clamp to
+  // [-1, 1] is the sign.
   auto energy = [&](const YAcc& y, double (&h)[kBpt], uint32_t& mask, auto frac) {
     constexpr bool kFrac = decltype(frac)::value;
 #pragma unroll
     for (int j = 0; j < 16; j++) {
-      if (!reg_used(j, kW, kK)) continue;
-      const double v = coeff<kFrac>(y, j);
+      if (!reg_used(j, kW, kK)) {
+        mask >>= 2;
+        continue;
+      }
+      const double v = coeff<kFrac>(y, j) + 0.0;
       h[(8 * (j / 4)) / kW] = fma(wd[j], fabs(v), h[(8 * (j / 4)) / kW]);
-      mask |= (v > 0.0 ? 1u << j : 0u) | (v < 0.0 ? 1u << (16 + j) : 0u);
+      const int hi = (int)(__builtin_bit_cast(uint64_t, v) >> 32);
+      int sg;   // the clamp as one instruction (written as min/max it compiles to two selects)
+      asm("v_med3_i32 %0, %1, -1, 1" : "=v"(sg) : "v"(hi));
+      mask = __builtin_amdgcn_alignbit((uint32_t)sg, mask, 2);
     }
   };
   auto tile = [&](const FTile<kW>& t, const float (&x)[16], int id) {
@@ -487,7 +498,8 @@ __global__ __launch_bounds__(kGThreads) void energy_bwd_kernel(GradParams p) {
 #pragma unroll
         for (int e = 0; e < 2; e++) {
           const int j = 8 * h + 2 * q + e;
-          const float sg = (mask >> j) & 1u ? 1.f : ((mask >> (16 + j)) & 1u ? -1.f : 0.f);
+          // the builtin's result type is unsigned: the field, sign-extended, as int
+          const float sg = (float)(int)__builtin_amdgcn_sbfe(mask, 2 * j, 2);
           a[0][e] = sg * w0[j];
           a[1][e] = sg * w1[j];
         }
