@@ -251,6 +251,30 @@ def test_batch_tune_and_no_graph_path(vca, frames, monkeypatch):
             b3.close()
 
 
+def test_batch_tune_between_rounds_keeps_features_and_state(vca, frames):
+    """Tuning after a round (its arrangement timing runs whole rounds with
+    their reductions) leaves the features already computed and the h state
+    alone, even with feature rings of one round, whose slots the tuning
+    rounds would reuse: both rounds still match the plain path."""
+    print_case(test="batch_tune_between_rounds")
+    streams = [dict(d, max_batch=d["n"], feature_capacity=d["n"]) for d in STREAMS[:4]]
+    sub = list(frames[:4])
+    b = vca.Batch(streams)
+    b.submit(sub)
+    first = [b.features(s, 0, d["n"]) for s, d in enumerate(streams)]
+    b.tune(sub, reps=1)
+    assert b.arrangement()["serial_ms"] > 0
+    again = [b.features(s, 0, d["n"]) for s, d in enumerate(streams)]
+    b.submit(sub)
+    second = [b.features(s, d["n"], d["n"]) for s, d in enumerate(streams)]
+    b.close()
+    for s, d in enumerate(streams):
+        ref = plain_features(vca, d, frames[s], 2)
+        assert again[s].tobytes() == first[s].tobytes(), s
+        assert first[s].tobytes() == ref[:d["n"]].tobytes(), s
+        assert second[s].tobytes() == ref[d["n"]:].tobytes(), s
+
+
 @pytest.mark.parametrize("waves,chunk", [(8, 8), (4, 64), (8, 16)])
 def test_batch_class_shapes(vca, frames, waves, chunk):
     """Every class pinned to 4 or 8 wavefronts per workgroup and 8 to 64
